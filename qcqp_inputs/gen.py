@@ -1,0 +1,181 @@
+"""Seeded instance generators (numpy PCG64 on the host, torch Philox on a device).
+
+Recipes (the workloads the method is measured on):
+
+* random convex QCQP: A_i iid N(0,1) n x n, Q_i = sym(A_i A_i^T / n) + shift*I for i=0..m,
+  q_i ~ N(0, I), c_0 = 0, c_i ~ U(-1, -0.1) so that x = 0 is strictly feasible (a Slater
+  point), X = [-10, 10]^n.  With shift = 0.01 every Q_i is positive definite.
+* kernel-learning QCQP (§5.2 stand-in): two Gaussian clusters in R^20, RBF Gram matrices,
+  variables (alpha, t); see kml_qcqp.
+* rounded instances: Q rounded once (round-to-nearest-even) to a 16/32-bit storage type; the
+  rounded values, upcast exactly, ARE the instance that both the oracle and the GPU solve.
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+
+BASE_SEED = 20260529
+
+
+def config_seed(config: int, instance: int = 0) -> int:
+    """Fixed seed per (workload number, instance index)."""
+    return BASE_SEED + 1000 * config + instance
+
+
+@dataclasses.dataclass
+class Instance:
+    n: int
+    m: int
+    p: int
+    Q: object            # (m+1 or m, n, n) array (numpy or torch), dtype float64/float32/bf16/fp16
+    q: np.ndarray        # (m+1, n) float64
+    c: np.ndarray        # (m+1,) float64
+    lb: np.ndarray       # (n,)
+    ub: np.ndarray       # (n,)
+    A: np.ndarray | None = None   # (p, n)
+    b: np.ndarray | None = None   # (p,)
+    has_q0: bool = True
+    name: str = ""
+
+    def q_as_float64_numpy(self) -> np.ndarray:
+        Q = self.Q
+        if hasattr(Q, "detach"):
+            Q = Q.detach().to("cpu")
+            import torch
+            return Q.to(torch.float64).numpy()
+        return np.asarray(Q, dtype=np.float64)
+
+
+def _box(n, lo=-10.0, hi=10.0):
+    return np.full(n, lo), np.full(n, hi)
+
+
+def random_qcqp(n: int, m: int, seed: int, shift: float = 0.0, box: float = 10.0,
+                p: int = 0) -> Instance:
+    """Random convex QCQP on the host with numpy PCG64 (float64)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Q = np.empty((m + 1, n, n))
+    for i in range(m + 1):
+        Ai = rng.standard_normal((n, n))
+        Qi = Ai @ Ai.T / n
+        Qi = 0.5 * (Qi + Qi.T)
+        if shift:
+            Qi[np.diag_indices(n)] += shift
+        Q[i] = Qi
+    q = rng.standard_normal((m + 1, n))
+    c = np.concatenate([[0.0], rng.uniform(-1.0, -0.1, m)])
+    lb, ub = _box(n, -box, box)
+    A = b = None
+    if p > 0:
+        A = rng.standard_normal((p, n)) / np.sqrt(n)
+        b = np.zeros(p)          # x = 0 stays feasible (Slater point)
+    return Instance(n, m, p, Q, q, c, lb, ub, A, b, True, f"rand_n{n}_m{m}_s{seed}")
+
+
+def random_qcqp_torch(n: int, m: int, seed: int, shift: float = 0.0, box: float = 10.0,
+                      device="cuda", store_dtype=None) -> Instance:
+    """Same recipe drawn with torch's Philox generator on `device`.
+
+    Q is produced matrix by matrix in float64 and stored in `store_dtype` (float64 if None),
+    rounded once with round-to-nearest-even, so a 16-bit stack never exists in float64 at once.
+    q and c are drawn on the device and returned as float64 numpy arrays.
+    """
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    sd = store_dtype or torch.float64
+    Q = torch.empty((m + 1, n, n), dtype=sd, device=device)
+    eye = torch.eye(n, dtype=torch.float64, device=device)
+    for i in range(m + 1):
+        Ai = torch.randn((n, n), generator=g, dtype=torch.float64, device=device)
+        Qi = Ai @ Ai.T / n
+        Qi = 0.5 * (Qi + Qi.T)
+        if shift:
+            Qi = Qi + shift * eye
+        Q[i].copy_(Qi.to(sd))
+        del Ai, Qi
+    q = torch.randn((m + 1, n), generator=g, dtype=torch.float64, device=device).cpu().numpy()
+    u = torch.rand((m,), generator=g, dtype=torch.float64, device=device).cpu().numpy()
+    c = np.concatenate([[0.0], -1.0 + 0.9 * u])
+    lb, ub = _box(n, -box, box)
+    return Instance(n, m, 0, Q, q, c, lb, ub, None, None, True, f"randT_n{n}_m{m}_s{seed}")
+
+
+def round_instance(inst: Instance, dtype: str) -> Instance:
+    """Round Q once (RNE) to 'float32' | 'bfloat16' | 'float16' (torch tensors on Q's device)."""
+    import torch
+    tdt = {"float32": torch.float32, "bfloat16": torch.bfloat16, "float16": torch.float16,
+           "float64": torch.float64}[dtype]
+    Q = inst.Q if hasattr(inst.Q, "to") else torch.from_numpy(np.ascontiguousarray(inst.Q))
+    return dataclasses.replace(inst, Q=Q.to(tdt), name=inst.name + "_" + dtype)
+
+
+def kml_qcqp(npts: int = 8000, dim: int = 20, bandwidths=(0.5, 1.0, 2.0, 4.0, 8.0), seed: int = 0,
+             C: float = 1.0, device=None, store_dtype=None) -> Instance:
+    """Kernel-learning QCQP in variables z = (alpha, t), n = npts + 1.
+
+    Two Gaussian clusters (means +-mu*1/sqrt(dim), identity covariance), labels +-1, features
+    standardised per column.  K_j = exp(-||a-a'||^2 / (2 h_j^2)) (diag = 1, tr K_j = npts).
+        min  -2 * 1'alpha + c * t
+        s.t. g_j(z) = 1/2 z' Q_j z - t <= 0,  Q_j = blkdiag(2 diag(y) K_j diag(y) / tr K_j, 0)
+             y'alpha = 0 (p = 1),  0 <= alpha <= C,  0 <= t <= npts * C^2
+    with c = sum_j tr K_j.  Q_0 = 0 is not stored (has_q0 = False).
+    """
+    import torch
+    rng = np.random.Generator(np.random.PCG64(seed))
+    half = npts // 2
+    mu = np.ones(dim) / np.sqrt(dim)
+    X = np.concatenate([rng.standard_normal((half, dim)) + mu,
+                        rng.standard_normal((npts - half, dim)) - mu])
+    y = np.concatenate([np.ones(half), -np.ones(npts - half)])
+    perm = rng.permutation(npts)
+    X, y = X[perm], y[perm]
+    X = (X - X.mean(0)) / X.std(0)
+    n = npts + 1
+    m = len(bandwidths)
+    dev = device or "cpu"
+    sd = store_dtype or torch.float64
+    Xt = torch.from_numpy(X).to(dev)
+    yt = torch.from_numpy(y).to(dev)
+    sq = (Xt * Xt).sum(1)
+    D2 = (sq[:, None] + sq[None, :] - 2.0 * (Xt @ Xt.T)).clamp_min_(0.0)
+    Q = torch.zeros((m, n, n), dtype=sd, device=dev)
+    traces = []
+    for j, h in enumerate(bandwidths):
+        K = torch.exp(-D2 / (2.0 * h * h))
+        tr = float(torch.diagonal(K).sum())
+        traces.append(tr)
+        H = (yt[:, None] * K * yt[None, :]) * (2.0 / tr)
+        H = 0.5 * (H + H.T)
+        Q[j, :npts, :npts] = H.to(sd)
+        del K, H
+    csum = float(sum(traces))
+    q = np.zeros((m + 1, n))
+    q[0, :npts] = -2.0
+    q[0, npts] = csum
+    q[1:, npts] = -1.0
+    c = np.zeros(m + 1)
+    lb = np.zeros(n)
+    ub = np.concatenate([np.full(npts, C), [npts * C * C]])
+    A = np.concatenate([y, [0.0]])[None, :]
+    b = np.zeros(1)
+    Qout = Q if (device is not None) else Q.numpy()
+    return Instance(n, m, 1, Qout, q, c, lb, ub, A, b, False, f"kml_n{npts}_s{seed}")
+
+
+def serving_trace(num: int, seed: int, n_range=(200, 3000), m_range=(5, 200), rate=None):
+    """Request sizes (n_k, m_k), per-request seeds and Poisson arrival times (seconds).
+
+    rate=None means closed loop (all arrivals at t = 0).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ns = rng.integers(n_range[0], n_range[1] + 1, size=num)
+    ms = rng.integers(m_range[0], m_range[1] + 1, size=num)
+    seeds = seed * 7919 + np.arange(num)
+    if rate is None:
+        arr = np.zeros(num)
+    else:
+        arr = np.cumsum(rng.exponential(1.0 / rate, size=num))
+    return [dict(n=int(ns[k]), m=int(ms[k]), seed=int(seeds[k]), arrival=float(arr[k]))
+            for k in range(num)]
