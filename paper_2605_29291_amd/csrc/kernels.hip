@@ -1,0 +1,1355 @@
+// HIP kernels (gfx950) of the rAPDB hot path for convex QCQPs.
+//
+// Paper: "Restarted Accelerated Primal-Dual Algorithms with Adaptive Stepsizes for Nonlinear
+// Conic Constrained Convex Optimization" (arXiv 2605.29291).  Section / equation references:
+//   eq. (qcqp-coupling), §2.1 .... Phi, grad_x Phi = Q_0x+q_0+sum lambda_i (Q_ix+q_i)+A'v,
+//                                   grad_y Phi = (Ax-b, g(x))
+//   eq. (apdb-yx-y), §3.2 ......... APDB-yx updates and its test function E_k
+//   Algorithm 1, §3 ............... backtracking loop, tau/gamma rule, ergodic averages
+//   Remark (non-monotone), §3.1 ... c_nm = 1 step rule
+//   Algorithm 2, §4.1 ............. fixed-frequency restarts
+//   Theorem (metric subregularity), §4.3 ... residual r(x,v,lambda) behind the KKT stop test
+//
+// All reductions are fixed-order (wave butterflies, then waves in index order), never atomics,
+// so every slot's arithmetic is bitwise independent of what else shares a launch.
+#include "qcqp_device.h"
+
+namespace qcqp {
+
+// ---------------------------------------------------------------------------------------
+// small helpers
+
+__device__ __forceinline__ double clipd(double v, double lo, double hi)
+{
+    // same comparison form as a plain projection: NaN passes through (and is caught later)
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// Deterministic block sum of NV doubles; the result is valid in thread 0 only.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV])
+{
+    __shared__ double sh[NV][STEP_BS / 64];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sh[k][wave] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < STEP_BS / 64; ++w) s += sh[k][w];
+            v[k] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------------------
+// storage types: one 16-byte vector load per lane per chunk
+
+template <int DT> struct Store;
+
+template <> struct Store<DT_F64> {
+    static constexpr int V = 2;
+    using acc_t = double;
+    using vec_t = double2;
+    __device__ static __forceinline__ vec_t ld(const void *Q, size_t idx)
+    {
+        return *reinterpret_cast<const double2 *>(reinterpret_cast<const double *>(Q) + idx);
+    }
+    __device__ static __forceinline__ double get(const vec_t &v, int e) { return e == 0 ? v.x : v.y; }
+};
+
+template <> struct Store<DT_F32> {
+    static constexpr int V = 4;
+    using acc_t = float;
+    using vec_t = float4;
+    __device__ static __forceinline__ vec_t ld(const void *Q, size_t idx)
+    {
+        return *reinterpret_cast<const float4 *>(reinterpret_cast<const float *>(Q) + idx);
+    }
+    __device__ static __forceinline__ float get(const vec_t &v, int e)
+    {
+        return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
+    }
+};
+
+template <> struct Store<DT_BF16> {
+    static constexpr int V = 8;
+    using acc_t = float;
+    using vec_t = uint4;
+    __device__ static __forceinline__ vec_t ld(const void *Q, size_t idx)
+    {
+        return *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint16_t *>(Q) + idx);
+    }
+    __device__ static __forceinline__ float get(const vec_t &v, int e)
+    {
+        const uint32_t w = (e >> 1) == 0 ? v.x : ((e >> 1) == 1 ? v.y : ((e >> 1) == 2 ? v.z : v.w));
+        const uint32_t bits = (e & 1) ? (w & 0xffff0000u) : (w << 16);
+        return __uint_as_float(bits);   // bf16 -> fp32 is exact
+    }
+};
+
+template <> struct Store<DT_F16> {
+    static constexpr int V = 8;
+    using acc_t = float;
+    using vec_t = uint4;
+    __device__ static __forceinline__ vec_t ld(const void *Q, size_t idx)
+    {
+        return *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint16_t *>(Q) + idx);
+    }
+    __device__ static __forceinline__ float get(const vec_t &v, int e)
+    {
+        const uint32_t w = (e >> 1) == 0 ? v.x : ((e >> 1) == 1 ? v.y : ((e >> 1) == 2 ? v.z : v.w));
+        const uint16_t h = (e & 1) ? (uint16_t)(w >> 16) : (uint16_t)(w & 0xffffu);
+        return (float)__builtin_bit_cast(_Float16, h);   // fp16 -> fp32 is exact
+    }
+};
+
+// ---------------------------------------------------------------------------------------
+// Q-stack pass: out_b[uoff + r] = sum_j Q[r, j] * w_b[j] for the stored rows r of a tile.
+// LPR lanes share one row: each lane streams 16-byte vectors of the row (coalesced across
+// the group), four loads in flight, multiply-adds against w held in LDS, then a butterfly
+// reduction over the LPR lanes in FP64.  With FP32 accumulation each lane sums at most
+// n / (LPR V) * V <= n / LPR products in FP32 before the FP64 combine.
+
+template <int DT, typename AT, int B, int LPR>
+__device__ __forceinline__ void pass_rows(const void *__restrict__ Q, int n, size_t ld, int row0,
+                                          int nrows, const AT *__restrict__ w, int nw,
+                                          double *const (&outs)[B], int uoff)
+{
+    using T = Store<DT>;
+    constexpr int V = T::V;
+    constexpr int NG = PASS_BS / LPR;
+    constexpr int STRIDE = LPR * V;
+    const int lane = threadIdx.x & (LPR - 1);
+    const int grp = threadIdx.x / LPR;
+    for (int r = row0 + grp; r < row0 + nrows; r += NG) {
+        const size_t base = (size_t)r * ld;
+        AT acc[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) acc[b] = AT(0);
+        int col = lane * V;
+        for (; col + 3 * STRIDE < n; col += 4 * STRIDE) {
+            const typename T::vec_t v0 = T::ld(Q, base + col);
+            const typename T::vec_t v1 = T::ld(Q, base + col + STRIDE);
+            const typename T::vec_t v2 = T::ld(Q, base + col + 2 * STRIDE);
+            const typename T::vec_t v3 = T::ld(Q, base + col + 3 * STRIDE);
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const AT q0 = (AT)T::get(v0, e), q1 = (AT)T::get(v1, e);
+                const AT q2 = (AT)T::get(v2, e), q3 = (AT)T::get(v3, e);
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const AT *wb = w + b * nw + col + e;
+                    acc[b] = fma(q0, wb[0], acc[b]);
+                    acc[b] = fma(q1, wb[STRIDE], acc[b]);
+                    acc[b] = fma(q2, wb[2 * STRIDE], acc[b]);
+                    acc[b] = fma(q3, wb[3 * STRIDE], acc[b]);
+                }
+            }
+        }
+        for (; col < n; col += STRIDE) {
+            const typename T::vec_t v0 = T::ld(Q, base + col);
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const AT q0 = (AT)T::get(v0, e);
+#pragma unroll
+                for (int b = 0; b < B; ++b) acc[b] = fma(q0, w[b * nw + col + e], acc[b]);
+            }
+        }
+        double s[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            s[b] = (double)acc[b];
+#pragma unroll
+            for (int off = LPR / 2; off > 0; off >>= 1) s[b] += __shfl_xor(s[b], off, LPR);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int b = 0; b < B; ++b) outs[b][uoff + r] = s[b];
+        }
+    }
+}
+
+template <int DT, typename AT, int B>
+__device__ __forceinline__ void pass_rows_lpr(int lpr, const void *Q, int n, size_t ld, int row0,
+                                              int nrows, const AT *w, int nw,
+                                              double *const (&outs)[B], int uoff)
+{
+    if (lpr == 64) pass_rows<DT, AT, B, 64>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
+    else if (lpr == 32) pass_rows<DT, AT, B, 32>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
+    else pass_rows<DT, AT, B, 16>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
+}
+
+template <int DT, int B>
+__global__ void __launch_bounds__(PASS_BS) k_pass(Slot *__restrict__ slots,
+                                                  const Tile *__restrict__ tiles)
+{
+    const Tile t = tiles[blockIdx.x];
+    Slot *S = slots + t.slot;
+    if (S->status != ST_RUNNING) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = S->n, nw = S->nw;
+    const int uoff = S->has_q0 ? 0 : n;
+    const size_t ld = (size_t)S->ld;
+    using AT = typename Store<DT>::acc_t;
+    if (S->mode == MODE_ANCHOR) {
+        // direct pass at the iterate, accumulated in FP64 whatever the storage type
+        double *w = reinterpret_cast<double *>(smem);
+        const double *x = S->x;
+        for (int j = threadIdx.x; j < nw; j += PASS_BS) w[j] = j < n ? x[j] : 0.0;
+        __syncthreads();
+        double *const outs[1] = {S->Uc[0]};
+        pass_rows_lpr<DT, double, 1>(t.lpr, S->Q, n, ld, t.row0, t.nrows, w, nw, outs, uoff);
+    } else {
+        AT *w = reinterpret_cast<AT *>(smem);
+        const bool inc = S->incremental != 0;
+        const double *x = S->x;
+        double *outs[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const double *xc = S->xc[b];
+            for (int j = threadIdx.x; j < nw; j += PASS_BS) {
+                double v = 0.0;
+                if (j < n) v = inc ? xc[j] - x[j] : xc[j];
+                w[b * nw + j] = (AT)v;
+            }
+            outs[b] = inc ? S->W[b] : S->Uc[b];
+        }
+        __syncthreads();
+        double *const (&co)[B] = outs;
+        pass_rows_lpr<DT, AT, B>(t.lpr, S->Q, n, ld, t.row0, t.nrows, w, nw, co, uoff);
+    }
+}
+
+// plain single-matrix product z = Q_i v (power iteration for the default step size)
+template <int DT>
+__global__ void __launch_bounds__(PASS_BS) k_matvec1(const void *__restrict__ Q, int n, int ld,
+                                                     int row_base, int lpr, int rows_per_block,
+                                                     const double *__restrict__ v, int nw,
+                                                     double *__restrict__ z)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *w = reinterpret_cast<double *>(smem);
+    for (int j = threadIdx.x; j < nw; j += PASS_BS) w[j] = j < n ? v[j] : 0.0;
+    __syncthreads();
+    const int r0 = blockIdx.x * rows_per_block;
+    const int nr = min(rows_per_block, n - r0);
+    if (nr <= 0) return;
+    double *const outs[1] = {z - row_base};
+    pass_rows_lpr<DT, double, 1>(lpr, Q, n, (size_t)ld, row_base + r0, nr, w, nw, outs, 0);
+}
+
+// ---------------------------------------------------------------------------------------
+// step kernel: dual step then primal step for B candidate step sizes (eq. (apdb-yx-y)):
+//   sigma = gamma tau, theta = sigma_{k-1}/sigma, s = (1+theta) G^k - theta G^{k-1},
+//   y+ = Pi_Y(y + sigma s)   (lambda >= 0, v free),
+//   x+ = Pi_X(x - tau grad_x Phi(x^k, y+)),  grad from the cached U^k = [Q_i x^k].
+// Also the KKT partials of the iterate (x^k, y^k).
+
+template <int B>
+__global__ void __launch_bounds__(STEP_BS) k_step(Slot *__restrict__ slots)
+{
+    Slot *S = slots + blockIdx.y;
+    if (S->status != ST_RUNNING || S->mode != MODE_TRIAL) return;
+    if ((int)blockIdx.x >= S->nblk_step) return;
+    const int n = S->n, m = S->m, p = S->p, ny = S->ny;
+    extern __shared__ double sm[];
+    double *ycur = sm;
+    double *ynew = sm + ny;
+    double tau_b[B], sig_b[B], th_b[B];
+    {
+        double t = S->tau;
+        const double gam = S->gam, sp = S->sig_prev, eta = S->eta;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            tau_b[b] = t;
+            sig_b[b] = gam * t;
+            th_b[b] = sp / sig_b[b];
+            t *= eta;
+        }
+    }
+    const double *G = S->G, *Gp = S->Gp, *y = S->y;
+    for (int l = threadIdx.x; l < ny; l += STEP_BS) {
+        const double yl = y[l], gl = G[l], gpl = Gp[l];
+        ycur[l] = yl;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const double s = (1.0 + th_b[b]) * gl - th_b[b] * gpl;
+            double v = yl + sig_b[b] * s;
+            if (l >= p) v = v < 0.0 ? 0.0 : v;
+            ynew[b * ny + l] = v;
+            if (blockIdx.x == 0) S->yc[b][l] = v;
+        }
+    }
+    __syncthreads();
+    double part[NPART];
+#pragma unroll
+    for (int f = 0; f < NPART; ++f) part[f] = 0.0;
+    const int j = blockIdx.x * STEP_BS + threadIdx.x;
+    if (j < n) {
+        const double *U = S->U, *q = S->q;
+        const double u0 = U[j] + q[j];
+        double acc[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) acc[b] = u0;
+        double kk = 0.0;
+        for (int i = 1; i <= m; ++i) {
+            const double t = U[(size_t)i * n + j] + q[(size_t)i * n + j];
+#pragma unroll
+            for (int b = 0; b < B; ++b) acc[b] = fma(ynew[b * ny + p + i - 1], t, acc[b]);
+            kk = fma(ycur[p + i - 1], t, kk);
+        }
+        double av = 0.0;
+        for (int l = 0; l < p; ++l) {
+            const double a = S->A[(size_t)l * n + j];
+#pragma unroll
+            for (int b = 0; b < B; ++b) acc[b] = fma(ynew[b * ny + l], a, acc[b]);
+            av = fma(ycur[l], a, av);
+        }
+        const double xj = S->x[j], lo = S->lb[j], hi = S->ub[j];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const double xn = clipd(xj - tau_b[b] * acc[b], lo, hi);
+            S->xc[b][j] = xn;
+            const double d = xn - xj;
+            part[4 + b] = d * d;
+        }
+        const double gk = u0 + kk + av;
+        const double r = xj - clipd(xj - gk, lo, hi);
+        part[0] = r * r;
+        part[1] = u0 * u0;
+        part[2] = kk * kk;
+        part[3] = av * av;
+    }
+    block_sum<NPART>(part);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int f = 0; f < NPART; ++f) S->part[(size_t)blockIdx.x * NPART + f] = part[f];
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// epilogue: one block per (matrix i or equality row l, slot).
+//   anchor:      G_i = 1/2 x'U_i + q_i'x + c_i            (g_i, and f for i = 0)
+//   direct:      e_i = d'(U+_i - U_i),  G+_i = 1/2 x+'U+_i + q_i'x+ + c_i
+//   incremental: e_i = d'W_i,  G+_i - G_i = d'U_i + 1/2 e_i + q_i'd  (Q_i symmetric), and
+//                U+_i = U_i + W_i
+// G arrays are laid out (Ax-b [p], g [m], f [1]).
+
+template <int B>
+__global__ void __launch_bounds__(STEP_BS) k_epi(Slot *__restrict__ slots)
+{
+    Slot *S = slots + blockIdx.y;
+    if (S->status != ST_RUNNING) return;
+    const int n = S->n, m = S->m, p = S->p, ny = S->ny;
+    const int row = blockIdx.x;
+    if (row > m + p) return;
+    const bool anchor = S->mode == MODE_ANCHOR;
+    const bool inc = S->incremental != 0;
+    const double *x = S->x;
+    const int tid = threadIdx.x;
+    if (row <= m) {
+        const int gi = row == 0 ? ny : p + row - 1;
+        const double *q = S->q + (size_t)row * n;
+        const double ci = S->c[row];
+        const size_t off = (size_t)row * n;
+        if (anchor) {
+            const double *u = S->Uc[0] + off;
+            double v[2] = {0.0, 0.0};
+            for (int j = tid; j < n; j += STEP_BS) {
+                const double xj = x[j];
+                v[0] = fma(xj, u[j], v[0]);
+                v[1] = fma(q[j], xj, v[1]);
+            }
+            block_sum<2>(v);
+            if (tid == 0) S->Gc[0][gi] = 0.5 * v[0] + v[1] + ci;
+        } else if (inc) {
+            const double *u = S->U + off;
+            double v[3 * B];
+#pragma unroll
+            for (int k = 0; k < 3 * B; ++k) v[k] = 0.0;
+            for (int j = tid; j < n; j += STEP_BS) {
+                const double xj = x[j], uj = u[j], qj = q[j];
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const double d = S->xc[b][j] - xj;
+                    const double wv = S->W[b][off + j];
+                    v[3 * b + 0] = fma(d, wv, v[3 * b + 0]);
+                    v[3 * b + 1] = fma(d, uj, v[3 * b + 1]);
+                    v[3 * b + 2] = fma(qj, d, v[3 * b + 2]);
+                    S->Uc[b][off + j] = uj + wv;
+                }
+            }
+            block_sum<3 * B>(v);
+            if (tid == 0) {
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const double e = v[3 * b];
+                    const double dg = v[3 * b + 1] + 0.5 * e + v[3 * b + 2];
+                    S->e[b * (m + 1) + row] = e;
+                    S->dG[b][gi] = dg;
+                    S->Gc[b][gi] = S->G[gi] + dg;
+                }
+            }
+        } else {
+            const double *u = S->U + off;
+            double v[3 * B];
+#pragma unroll
+            for (int k = 0; k < 3 * B; ++k) v[k] = 0.0;
+            for (int j = tid; j < n; j += STEP_BS) {
+                const double xj = x[j], uj = u[j], qj = q[j];
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const double xn = S->xc[b][j];
+                    const double un = S->Uc[b][off + j];
+                    v[3 * b + 0] = fma(xn - xj, un - uj, v[3 * b + 0]);
+                    v[3 * b + 1] = fma(xn, un, v[3 * b + 1]);
+                    v[3 * b + 2] = fma(qj, xn, v[3 * b + 2]);
+                }
+            }
+            block_sum<3 * B>(v);
+            if (tid == 0) {
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const double gn = 0.5 * v[3 * b + 1] + v[3 * b + 2] + ci;
+                    S->e[b * (m + 1) + row] = v[3 * b];
+                    S->Gc[b][gi] = gn;
+                    S->dG[b][gi] = gn - S->G[gi];
+                }
+            }
+        }
+    } else {
+        const int l = row - (m + 1);
+        const double *a = S->A + (size_t)l * n;
+        const double bl = S->b[l];
+        if (anchor) {
+            double v[1] = {0.0};
+            for (int j = tid; j < n; j += STEP_BS) v[0] = fma(a[j], x[j], v[0]);
+            block_sum<1>(v);
+            if (tid == 0) S->Gc[0][l] = v[0] - bl;
+        } else {
+            double v[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) v[b] = 0.0;
+            for (int j = tid; j < n; j += STEP_BS) {
+                const double aj = a[j];
+#pragma unroll
+                for (int b = 0; b < B; ++b) v[b] = fma(aj, inc ? S->xc[b][j] - x[j] : S->xc[b][j], v[b]);
+            }
+            block_sum<B>(v);
+            if (tid == 0) {
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    if (inc) {
+                        S->dG[b][l] = v[b];
+                        S->Gc[b][l] = S->G[l] + v[b];
+                    } else {
+                        S->Gc[b][l] = v[b] - bl;
+                        S->dG[b][l] = (v[b] - bl) - S->G[l];
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// control kernel (one block per slot, FP64)
+
+__device__ __forceinline__ void swap_ptr(double *&a, double *&b)
+{
+    double *t = a;
+    a = b;
+    b = t;
+}
+
+// New epoch of Algorithm 2: rs = 1 restarts at the last iterate, rs = 2 at the ergodic
+// average; the routine's first line resets tau, gamma, the momentum (x^{-1} = x^0) and the
+// averages.  A re-anchor (exact direct pass at the restart point) follows when the point moved
+// or when trial products are formed incrementally.  Called by all threads of one block.
+__device__ void restart_epoch(Slot *S, int rs)
+{
+    const int n = S->n, ny = S->ny, tid = threadIdx.x;
+    if (rs == 2) {
+        const double invT = 1.0 / S->T;
+        double *x = S->x, *y = S->y;
+        const double *cx = S->cx, *cy = S->cy;
+        for (int j = tid; j < n; j += STEP_BS) x[j] = cx[j] * invT;
+        for (int l = tid; l < ny; l += STEP_BS) y[l] = cy[l] * invT;
+    }
+    __syncthreads();
+    double *cx = S->cx, *cy = S->cy;
+    for (int j = tid; j < n; j += STEP_BS) cx[j] = 0.0;
+    for (int l = tid; l < ny; l += STEP_BS) cy[l] = 0.0;
+    const bool anchor = (rs == 2) || S->incremental;
+    if (!anchor) {
+        const double *G = S->G;
+        double *Gp = S->Gp;
+        for (int l = tid; l <= ny; l += STEP_BS) Gp[l] = G[l];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        S->tau = S->tau_bar;
+        S->tau_prev = S->tau_bar;
+        S->sig_prev = S->gamma0 * S->tau_bar;
+        S->gam = S->gamma0;
+        S->alpha_k = S->c_alpha / S->sig_prev;
+        S->T = 0.0;
+        S->ke = 0;
+        S->restarts += 1;
+        if (anchor) S->mode = MODE_ANCHOR;
+    }
+}
+
+template <int B>
+__global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots)
+{
+    Slot *S = slots + blockIdx.x;
+    const int status = S->status;
+    const int mode = S->mode;
+    __syncthreads();
+    if (status != ST_RUNNING) return;
+    const int n = S->n, m = S->m, p = S->p, ny = S->ny;
+    const int tid = threadIdx.x;
+    __shared__ int s_dec;       // accepted candidate, -1 none, -2 stop
+    __shared__ int s_restart;   // 0 none, 1 restart at last iterate, 2 from the average
+    __shared__ double s_t;
+
+    if (mode == MODE_ANCHOR) {
+        // install [Q_i x] and G(x) of the anchor point; x^{-1} = x^0 (epoch start)
+        if (tid == 0) {
+            swap_ptr(S->U, S->Uc[0]);
+            swap_ptr(S->G, S->Gc[0]);
+        }
+        __syncthreads();
+        const double *G = S->G;
+        double *Gp = S->Gp;
+        for (int l = tid; l <= ny; l += STEP_BS) Gp[l] = G[l];
+        if (tid == 0) {
+            S->f = G[ny];
+            S->mode = MODE_TRIAL;
+            S->passes += 1;
+        }
+        return;
+    }
+
+    // ---- 1. relative KKT residual of the iterate (x^k, y^k) ----
+    double tot[NPART];
+#pragma unroll
+    for (int f = 0; f < NPART; ++f) tot[f] = 0.0;
+    for (int blk = tid; blk < S->nblk_step; blk += STEP_BS) {
+#pragma unroll
+        for (int f = 0; f < NPART; ++f) tot[f] += S->part[(size_t)blk * NPART + f];
+    }
+    block_sum<NPART>(tot);
+    double kv[3] = {0.0, 0.0, 0.0};   // ||min(lambda,-g)||^2, ||([g]+, Ax-b)||^2, max violation
+    {
+        const double *G = S->G, *y = S->y;
+        double mx = 0.0;
+        for (int l = tid; l < ny; l += STEP_BS) {
+            const double gl = G[l];
+            if (l < p) {
+                kv[1] += gl * gl;
+                mx = fmax(mx, fabs(gl));
+            } else {
+                const double lam = y[l];
+                const double mn = lam < -gl ? lam : -gl;
+                kv[0] += mn * mn;
+                if (gl > 0.0) {
+                    kv[1] += gl * gl;
+                    mx = fmax(mx, gl);
+                }
+            }
+        }
+        kv[2] = mx;
+        // max is order independent; reuse the sum tree on the square-free value via a max pass
+        __shared__ double s_mx[STEP_BS];
+        s_mx[tid] = mx;
+        __syncthreads();
+        if (tid == 0) {
+            double mm = 0.0;
+            for (int t = 0; t < STEP_BS; ++t) mm = fmax(mm, s_mx[t]);
+            kv[2] = mm;
+        }
+        __syncthreads();
+        double kk2[2] = {kv[0], kv[1]};
+        block_sum<2>(kk2);
+        kv[0] = kk2[0];
+        kv[1] = kk2[1];
+    }
+
+    // ---- 2. test quantities per candidate ----
+    double tq[3 * B];   // quad, ||dG||^2, ||dy||^2
+#pragma unroll
+    for (int k = 0; k < 3 * B; ++k) tq[k] = 0.0;
+    {
+        const double *y = S->y;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const double *e = S->e + b * (m + 1);
+            const double *yc = S->yc[b];
+            for (int i = tid; i <= m; i += STEP_BS) {
+                const double wgt = (i == 0) ? 1.0 : yc[p + i - 1];
+                tq[3 * b] = fma(wgt, e[i], tq[3 * b]);
+            }
+            const double *dg = S->dG[b];
+            for (int l = tid; l < ny; l += STEP_BS) {
+                tq[3 * b + 1] = fma(dg[l], dg[l], tq[3 * b + 1]);
+                const double dy = yc[l] - y[l];
+                tq[3 * b + 2] = fma(dy, dy, tq[3 * b + 2]);
+            }
+        }
+    }
+    block_sum<3 * B>(tq);
+
+    if (tid == 0) {
+        const double rel_dual = sqrt(tot[0]) / (1.0 + sqrt(tot[1]) + sqrt(tot[2]) + sqrt(tot[3]));
+        const double rel_comp = sqrt(kv[0]) / (1.0 + S->cnorm);
+        const double rel_pri = sqrt(kv[1]) / (1.0 + S->cnorm + S->bnorm);
+        double rk = fmax(rel_dual, fmax(rel_pri, rel_comp));
+        if (isnan(rel_dual) || isnan(rel_pri) || isnan(rel_comp)) rk = NAN;
+        S->kkt[0] = rk;
+        S->kkt[1] = rel_dual;
+        S->kkt[2] = rel_pri;
+        S->kkt[3] = rel_comp;
+        S->maxviol = kv[2];
+        int dec = -1;
+        if (isnan(rk)) {
+            S->status = ST_NUMERICAL;
+            dec = -2;
+        } else if (rk <= S->tol) {
+            S->status = ST_CONVERGED;
+            dec = -2;
+        } else if (S->k >= S->max_iter) {
+            S->status = ST_MAX_ITER;
+            dec = -2;
+        }
+        if (dec == -1) {
+            S->passes += 1;
+            double t = S->tau;
+            const double gam = S->gam, sp = S->sig_prev, eta = S->eta;
+            for (int b = 0; b < B; ++b) {
+                const double sig = gam * t;
+                const double th = sp / sig;
+                const double alpha_next = S->c_alpha / sig;          // alpha_{k+1} = c_a / sigma_k
+                const double dd = tot[4 + b], dg2 = tq[3 * b + 1], dy2 = tq[3 * b + 2];
+                const double Dp = 0.5 * dd, Dd = 0.5 * dy2;
+                const double quad = 0.5 * tq[3 * b];                  // 1/2 d'Q(lambda+)d
+                const double E = quad - Dp / t + dg2 / (2.0 * alpha_next) -
+                                 (1.0 / sig - th * S->alpha_k) * Dd;
+                const double rhs = -(S->delta / t) * Dp - (S->delta / sig) * Dd;
+                if (E <= rhs) {
+                    dec = b;
+                    break;
+                }
+                if (isnan(E) || isnan(rhs)) {
+                    dec = -3;
+                    break;
+                }
+                t *= eta;
+            }
+            if (dec == -3) {
+                S->status = ST_NUMERICAL;
+                dec = -2;
+            } else if (dec == -1) {
+                // all candidates rejected: tau <- eta^B tau, next group retries
+                S->tau = t;
+                S->trials += B;
+                S->iter_trials += B;
+                if (S->iter_trials > 400 || !(t > 1e-300)) {
+                    S->status = ST_NUMERICAL;
+                    dec = -2;
+                }
+            }
+        }
+        s_dec = dec;
+        if (dec >= 0) {
+            double t = S->tau;
+            for (int b = 0; b < dec; ++b) t *= S->eta;
+            const double sig = S->gam * t;
+            if (S->ke == 0) S->sig0 = sig;
+            s_t = sig / S->sig0;                                     // t_k = sigma_k / sigma_0
+        }
+    }
+    __syncthreads();
+    const int dec = s_dec;
+    if (dec < 0) return;
+
+    // ---- 3. accepted candidate `dec`: ergodic sums (Algorithm 1) ----
+    {
+        const double tk = s_t;
+        const double *xn = S->xc[dec], *yn = S->yc[dec];
+        double *cx = S->cx, *cy = S->cy;
+        for (int j = tid; j < n; j += STEP_BS) cx[j] = fma(tk, xn[j], cx[j]);
+        for (int l = tid; l < ny; l += STEP_BS) cy[l] = fma(tk, yn[l], cy[l]);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double t = S->tau;
+        for (int b = 0; b < dec; ++b) t *= S->eta;
+        const double sig = S->gam * t;
+        S->T += s_t;
+        S->trials += dec + 1;
+        S->iter_trials = 0;
+        // step-size rule, Algorithm 1 (non-monotone form with c_nm = 1)
+        const double gam_next = S->gam * (1.0 + S->mu * t);
+        const double tau_next = t * sqrt(S->gam / gam_next * (1.0 + S->c_nm * t / S->tau_prev));
+        // shift the state: (x, U, y) <- candidate, G^{k-1} <- G^k, G^k <- candidate
+        swap_ptr(S->x, S->xc[dec]);
+        swap_ptr(S->U, S->Uc[dec]);
+        swap_ptr(S->y, S->yc[dec]);
+        double *gold = S->Gp;
+        S->Gp = S->G;
+        S->G = S->Gc[dec];
+        S->Gc[dec] = gold;
+        S->f = S->G[ny];
+        S->alpha_k = S->c_alpha / sig;
+        S->sig_prev = sig;
+        S->tau_prev = t;
+        S->tau = tau_next;
+        S->gam = gam_next;
+        S->k += 1;
+        S->ke += 1;
+        int rs = 0;
+        if (S->restart == 1 && S->ke >= S->restart_every) rs = 1;
+        if (S->restart == 2 &&
+            (S->k == S->ada_first || (S->k > S->ada_first && (S->k % S->ada_every) == 0)))
+            S->status = ST_GAP_PENDING;
+        if (rs && S->restart_from_avg && S->T > 0.0) rs = 2;
+        s_restart = rs;
+    }
+    __syncthreads();
+    const int rs = s_restart;
+    if (rs == 0) return;
+
+    // ---- 4. restart (Algorithm 2) ----
+    restart_epoch(S, rs);
+}
+
+// ---------------------------------------------------------------------------------------
+// start: clip x^0 into X, project lambda^0 onto R^m_+, clear the averages; the first group
+// is an anchor pass.
+
+__global__ void __launch_bounds__(STEP_BS) k_start(Slot *__restrict__ S)
+{
+    const int n = S->n, ny = S->ny, p = S->p;
+    for (int j = threadIdx.x; j < n; j += STEP_BS) {
+        S->x[j] = clipd(S->x[j], S->lb[j], S->ub[j]);
+        S->cx[j] = 0.0;
+    }
+    for (int l = threadIdx.x; l < ny; l += STEP_BS) {
+        if (l >= p && S->y[l] < 0.0) S->y[l] = 0.0;
+        S->cy[l] = 0.0;
+    }
+}
+
+// adaptive restart decision after the host evaluated G_xi at the iterate (eq. (ada_restart)):
+// first = 1 records the reference value G_ref only; otherwise restart when
+// G_xi(candidate) <= q G_ref and take the candidate's value as the new reference.
+__global__ void __launch_bounds__(STEP_BS) k_restart_decision(Slot *__restrict__ S, double gap,
+                                                              int first)
+{
+    __shared__ int s_rs;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        S->gap_evals += 1;
+        S->last_gap = gap;
+        int rs = 0;
+        if (first) {
+            S->Gref = gap;
+        } else if (gap <= S->q_restart * S->Gref) {
+            S->Gref = gap;
+            rs = (S->restart_from_avg && S->T > 0.0) ? 2 : 1;
+        }
+        S->status = ST_RUNNING;
+        s_rs = rs;
+    }
+    __syncthreads();
+    if (s_rs) restart_epoch(S, s_rs);
+}
+
+// ---------------------------------------------------------------------------------------
+// standalone evaluations: gradient and KKT residual at an arbitrary (x, y), given U = [Q_i x]
+
+__global__ void __launch_bounds__(STEP_BS) k_grad(const Slot *__restrict__ S,
+                                                  const double *__restrict__ U,
+                                                  const double *__restrict__ y,
+                                                  double *__restrict__ out)
+{
+    const int n = S->n, m = S->m, p = S->p;
+    const int j = blockIdx.x * STEP_BS + threadIdx.x;
+    if (j >= n) return;
+    double g = U[j] + S->q[j];
+    for (int i = 1; i <= m; ++i)
+        g = fma(y[p + i - 1], U[(size_t)i * n + j] + S->q[(size_t)i * n + j], g);
+    for (int l = 0; l < p; ++l) g = fma(y[l], S->A[(size_t)l * n + j], g);
+    out[j] = g;
+}
+
+__global__ void __launch_bounds__(STEP_BS) k_kkt_part(const Slot *__restrict__ S,
+                                                      const double *__restrict__ x,
+                                                      const double *__restrict__ y,
+                                                      const double *__restrict__ U,
+                                                      double *__restrict__ part)
+{
+    const int n = S->n, m = S->m, p = S->p;
+    const int j = blockIdx.x * STEP_BS + threadIdx.x;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (j < n) {
+        const double u0 = U[j] + S->q[j];
+        double kk = 0.0, av = 0.0;
+        for (int i = 1; i <= m; ++i)
+            kk = fma(y[p + i - 1], U[(size_t)i * n + j] + S->q[(size_t)i * n + j], kk);
+        for (int l = 0; l < p; ++l) av = fma(y[l], S->A[(size_t)l * n + j], av);
+        const double gk = u0 + kk + av;
+        const double r = x[j] - clipd(x[j] - gk, S->lb[j], S->ub[j]);
+        v[0] = r * r;
+        v[1] = u0 * u0;
+        v[2] = kk * kk;
+        v[3] = av * av;
+    }
+    block_sum<4>(v);
+    if (threadIdx.x == 0) {
+        for (int f = 0; f < 4; ++f) part[(size_t)blockIdx.x * 4 + f] = v[f];
+    }
+}
+
+__global__ void __launch_bounds__(STEP_BS) k_kkt_fin(const Slot *__restrict__ S, int nblk,
+                                                     const double *__restrict__ y,
+                                                     const double *__restrict__ G,
+                                                     const double *__restrict__ part,
+                                                     double *__restrict__ out6)
+{
+    const int ny = S->ny, p = S->p;
+    const int tid = threadIdx.x;
+    double tot[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int blk = tid; blk < nblk; blk += STEP_BS)
+        for (int f = 0; f < 4; ++f) tot[f] += part[(size_t)blk * 4 + f];
+    block_sum<4>(tot);
+    double kv[2] = {0.0, 0.0};
+    double mx = 0.0;
+    for (int l = tid; l < ny; l += STEP_BS) {
+        const double gl = G[l];
+        if (l < p) {
+            kv[1] += gl * gl;
+            mx = fmax(mx, fabs(gl));
+        } else {
+            const double lam = y[l];
+            const double mn = lam < -gl ? lam : -gl;
+            kv[0] += mn * mn;
+            if (gl > 0.0) {
+                kv[1] += gl * gl;
+                mx = fmax(mx, gl);
+            }
+        }
+    }
+    __shared__ double s_mx[STEP_BS];
+    s_mx[tid] = mx;
+    block_sum<2>(kv);
+    if (tid == 0) {
+        double mm = 0.0;
+        for (int t = 0; t < STEP_BS; ++t) mm = fmax(mm, s_mx[t]);
+        const double rel_dual = sqrt(tot[0]) / (1.0 + sqrt(tot[1]) + sqrt(tot[2]) + sqrt(tot[3]));
+        const double rel_comp = sqrt(kv[0]) / (1.0 + S->cnorm);
+        const double rel_pri = sqrt(kv[1]) / (1.0 + S->cnorm + S->bnorm);
+        double rk = fmax(rel_dual, fmax(rel_pri, rel_comp));
+        if (isnan(rel_dual) || isnan(rel_pri) || isnan(rel_comp)) rk = NAN;
+        out6[0] = rk;
+        out6[1] = rel_dual;
+        out6[2] = rel_pri;
+        out6[3] = rel_comp;
+        out6[4] = G[ny];
+        out6[5] = mm;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// storage conversion, once at creation: src (dtype, ld_src) -> dst (dtype, ld_dst), the
+// padding columns n..ld_dst-1 set to zero.  FP64 -> 16/32 bit rounds to nearest even in one
+// step: a round-to-odd FP32 intermediate (truncate, then set the sticky bit when inexact)
+// followed by the hardware's nearest-even FP32 -> 16-bit conversion.
+
+__device__ __forceinline__ double load_any(const void *p, int dt, size_t i)
+{
+    switch (dt) {
+    case DT_F64: return reinterpret_cast<const double *>(p)[i];
+    case DT_F32: return (double)reinterpret_cast<const float *>(p)[i];
+    case DT_BF16: return (double)__uint_as_float((uint32_t)reinterpret_cast<const uint16_t *>(p)[i] << 16);
+    default: return (double)(float)__builtin_bit_cast(_Float16, reinterpret_cast<const uint16_t *>(p)[i]);
+    }
+}
+
+__device__ __forceinline__ float round_to_odd_f32(double v)
+{
+    float f = __double2float_rz(v);
+    if ((double)f != v && !isnan(v)) {
+        uint32_t bits = __float_as_uint(f) | 1u;
+        f = __uint_as_float(bits);
+    }
+    return f;
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);   // NaN stays NaN
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+__global__ void k_convert(const void *__restrict__ src, int sdt, int64_t lds,
+                          void *__restrict__ dst, int ddt, int64_t ldd, int64_t rows, int64_t n)
+{
+    const int64_t total = rows * ldd;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = idx / ldd, j = idx - r * ldd;
+        double v = 0.0;
+        if (j < n) v = load_any(src, sdt, (size_t)(r * lds + j));
+        switch (ddt) {
+        case DT_F64: reinterpret_cast<double *>(dst)[idx] = v; break;
+        case DT_F32: reinterpret_cast<float *>(dst)[idx] = (float)v; break;
+        case DT_BF16:
+            if (sdt == DT_BF16)
+                reinterpret_cast<uint16_t *>(dst)[idx] =
+                    j < n ? reinterpret_cast<const uint16_t *>(src)[r * lds + j] : (uint16_t)0;
+            else
+                reinterpret_cast<uint16_t *>(dst)[idx] = f32_to_bf16_rne(round_to_odd_f32(v));
+            break;
+        default: {
+            _Float16 h;
+            if (sdt == DT_F16) {
+                h = j < n ? __builtin_bit_cast(_Float16, reinterpret_cast<const uint16_t *>(src)[r * lds + j])
+                          : (_Float16)0.0f;
+            } else {
+                h = (_Float16)round_to_odd_f32(v);
+            }
+            reinterpret_cast<uint16_t *>(dst)[idx] = __builtin_bit_cast(uint16_t, h);
+        }
+        }
+    }
+}
+
+
+// ---------------------------------------------------------------------------------------
+// smoothed duality gap G_xi(z) (Definition in §4; Euclidean evaluation of the Remark in §4.2)
+//   y-part: Py = <G, y'-y> - xi ||y'-y||^2,  y' = Pi_Y(y + G/(2 xi))          (closed form)
+//   x-part: Px = -min_{x+D in X} grad'D + 1/2 D'(Q(lambda) + 2 xi I)D         (box QP)
+// The box QP runs accelerated projected gradient with gradient restart, step 1/L, L the
+// Gershgorin bound of H = Q(lambda) + 2 xi I, until L ||D+ - Z|| <= tol (1 + ||grad||).
+// ctl layout: [0] t, [1] beta, [2] restart, [3] done, [4] iters, [5] L, [6] gnorm, [7] tol,
+//             [8] skip, [9] Py, [10] Px
+
+__global__ void __launch_bounds__(STEP_BS) k_gap_py(const Slot *__restrict__ S,
+                                                    const double *__restrict__ y,
+                                                    const double *__restrict__ G, double xi,
+                                                    double *__restrict__ ctl)
+{
+    const int ny = S->ny, p = S->p;
+    double v[1] = {0.0};
+    for (int l = threadIdx.x; l < ny; l += STEP_BS) {
+        double yp = y[l] + G[l] / (2.0 * xi);
+        if (l >= p && yp < 0.0) yp = 0.0;
+        const double d = yp - y[l];
+        v[0] += G[l] * d - xi * d * d;
+    }
+    block_sum<1>(v);
+    if (threadIdx.x == 0) ctl[9] = v[0];
+}
+
+// H = Q(lambda) + 2 xi I (row r per block), rowabs[r] = sum_j |H_rj|; matrices with a zero
+// multiplier are skipped (they contribute nothing)
+__global__ void __launch_bounds__(STEP_BS) k_form_h(const Slot *__restrict__ S,
+                                                    const double *__restrict__ y, double xi,
+                                                    double *__restrict__ H, int ldh,
+                                                    double *__restrict__ rowabs)
+{
+    const int n = S->n, m = S->m, p = S->p, r = blockIdx.x;
+    const size_t ld = (size_t)S->ld;
+    const int dt = S->dtype;
+    const int has_q0 = S->has_q0;
+    double v[1] = {0.0};
+    for (int j = n + threadIdx.x; j < ldh; j += STEP_BS) H[(size_t)r * ldh + j] = 0.0;   // padding
+    for (int j = threadIdx.x; j < n; j += STEP_BS) {
+        double h = 0.0;
+        if (has_q0) h = load_any(S->Q, dt, (size_t)r * ld + j);
+        for (int i = 1; i <= m; ++i) {
+            const double w = y[p + i - 1];
+            if (w == 0.0) continue;
+            const size_t mat = (size_t)(i - 1 + has_q0);
+            h += w * load_any(S->Q, dt, (mat * n + r) * ld + j);
+        }
+        if (j == r) h += 2.0 * xi;
+        H[(size_t)r * ldh + j] = h;
+        v[0] += fabs(h);
+    }
+    block_sum<1>(v);
+    if (threadIdx.x == 0) rowabs[r] = v[0];
+}
+
+__global__ void __launch_bounds__(STEP_BS) k_gap_init(int n, const double *__restrict__ grad,
+                                                      const double *__restrict__ rowabs,
+                                                      double tol, double *__restrict__ ctl)
+{
+    double v[1] = {0.0};
+    double mx = 0.0;
+    for (int j = threadIdx.x; j < n; j += STEP_BS) {
+        v[0] += grad[j] * grad[j];
+        mx = fmax(mx, rowabs[j]);
+    }
+    __shared__ double s_mx[STEP_BS];
+    s_mx[threadIdx.x] = mx;
+    block_sum<1>(v);
+    if (threadIdx.x == 0) {
+        double mm = 0.0;
+        for (int t = 0; t < STEP_BS; ++t) mm = fmax(mm, s_mx[t]);
+        ctl[0] = 1.0;
+        ctl[1] = 0.0;
+        ctl[2] = 0.0;
+        ctl[3] = 0.0;
+        ctl[4] = 0.0;
+        ctl[5] = mm;
+        ctl[6] = sqrt(v[0]);
+        ctl[7] = tol;
+        ctl[8] = 0.0;
+    }
+}
+
+// z = H v (FP64); skipped once the inner loop is done unless force != 0
+__global__ void __launch_bounds__(PASS_BS) k_hmv(const double *__restrict__ H, int n, int ldh,
+                                                 int lpr, int rows_per_block,
+                                                 const double *__restrict__ v, int nw,
+                                                 double *__restrict__ z,
+                                                 const double *__restrict__ ctl, int force)
+{
+    if (!force && ctl[3] != 0.0) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *w = reinterpret_cast<double *>(smem);
+    for (int j = threadIdx.x; j < nw; j += PASS_BS) w[j] = j < n ? v[j] : 0.0;
+    __syncthreads();
+    const int r0 = blockIdx.x * rows_per_block;
+    const int nr = min(rows_per_block, n - r0);
+    if (nr <= 0) return;
+    double *const outs[1] = {z};
+    pass_rows_lpr<DT_F64, double, 1>(lpr, H, n, (size_t)ldh, r0, nr, w, nw, outs, 0);
+}
+
+__global__ void __launch_bounds__(STEP_BS) k_fista_u1(const Slot *__restrict__ S,
+                                                      const double *__restrict__ x,
+                                                      const double *__restrict__ grad,
+                                                      const double *__restrict__ Hz,
+                                                      const double *__restrict__ Z,
+                                                      const double *__restrict__ D,
+                                                      double *__restrict__ Dn,
+                                                      const double *__restrict__ ctl,
+                                                      double *__restrict__ part)
+{
+    if (ctl[3] != 0.0) return;
+    const int n = S->n;
+    const int j = blockIdx.x * STEP_BS + threadIdx.x;
+    const double L = ctl[5];
+    double v[2] = {0.0, 0.0};
+    if (j < n) {
+        const double gz = grad[j] + Hz[j];
+        const double xj = x[j];
+        const double dn = clipd(Z[j] - gz / L, S->lb[j] - xj, S->ub[j] - xj);
+        Dn[j] = dn;
+        const double a = dn - Z[j];
+        v[0] = a * a;
+        v[1] = (Z[j] - dn) * (dn - D[j]);
+    }
+    block_sum<2>(v);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = v[0];
+        part[2 * blockIdx.x + 1] = v[1];
+    }
+}
+
+__global__ void __launch_bounds__(STEP_BS) k_fista_sc(int nblk, const double *__restrict__ part,
+                                                      double *__restrict__ ctl, int64_t max_inner)
+{
+    if (ctl[3] != 0.0) {
+        if (threadIdx.x == 0) ctl[8] = 1.0;
+        return;
+    }
+    double v[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += STEP_BS) {
+        v[0] += part[2 * b];
+        v[1] += part[2 * b + 1];
+    }
+    block_sum<2>(v);
+    if (threadIdx.x == 0) {
+        const double t = ctl[0];
+        double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+        if (v[1] > 0.0) {          // gradient restart
+            tn = 1.0;
+            ctl[2] = 1.0;
+        } else {
+            ctl[2] = 0.0;
+            ctl[1] = (t - 1.0) / tn;
+        }
+        ctl[0] = tn;
+        ctl[4] += 1.0;
+        ctl[8] = 0.0;
+        if (ctl[5] * sqrt(v[0]) <= ctl[7] * (1.0 + ctl[6]) || ctl[4] >= (double)max_inner) ctl[3] = 1.0;
+    }
+}
+
+__global__ void __launch_bounds__(STEP_BS) k_fista_u2(int n, const double *__restrict__ Dn,
+                                                      double *__restrict__ D,
+                                                      double *__restrict__ Z,
+                                                      const double *__restrict__ ctl)
+{
+    if (ctl[8] != 0.0) return;
+    const int j = blockIdx.x * STEP_BS + threadIdx.x;
+    if (j >= n) return;
+    const double dn = Dn[j];
+    Z[j] = ctl[2] != 0.0 ? dn : dn + ctl[1] * (dn - D[j]);
+    D[j] = dn;
+}
+
+// Px = -(grad'D + 1/2 D'(H D))
+__global__ void __launch_bounds__(STEP_BS) k_gap_px(int n, const double *__restrict__ grad,
+                                                    const double *__restrict__ D,
+                                                    const double *__restrict__ HD,
+                                                    double *__restrict__ ctl)
+{
+    double v[1] = {0.0};
+    for (int j = threadIdx.x; j < n; j += STEP_BS) v[0] += grad[j] * D[j] + 0.5 * D[j] * HD[j];
+    block_sum<1>(v);
+    if (threadIdx.x == 0) ctl[10] = -v[0];
+}
+
+hipError_t launch_gap_setup(hipStream_t s, const Slot *slot, int n, const double *y,
+                            const double *G, const double *grad, double xi, double *H, int ldh,
+                            double *rowabs, double tol, double *ctl)
+{
+    k_gap_py<<<1, STEP_BS, 0, s>>>(slot, y, G, xi, ctl);
+    k_form_h<<<n, STEP_BS, 0, s>>>(slot, y, xi, H, ldh, rowabs);
+    k_gap_init<<<1, STEP_BS, 0, s>>>(n, grad, rowabs, tol, ctl);
+    return hipGetLastError();
+}
+
+static void hmv_shape(int n, int *lpr, int *rpb)
+{
+    const int vpr = (n + 1) / 2;
+    int l = 16;
+    if (vpr >= 4 * 64) l = 64;
+    else if (vpr >= 4 * 32) l = 32;
+    *lpr = l;
+    *rpb = 32;
+}
+
+hipError_t launch_gap_iters(hipStream_t s, const Slot *slot, int n, const double *x,
+                            const double *grad, const double *H, int ldh, int nw, double *Z,
+                            double *D, double *Dn, double *Hz, double *part, double *ctl,
+                            int iters, int64_t max_inner)
+{
+    int lpr, rpb;
+    hmv_shape(n, &lpr, &rpb);
+    const int nblk_r = (n + rpb - 1) / rpb;
+    const int nblk = (n + STEP_BS - 1) / STEP_BS;
+    const size_t lds = (size_t)nw * sizeof(double);
+    for (int it = 0; it < iters; ++it) {
+        k_hmv<<<nblk_r, PASS_BS, lds, s>>>(H, n, ldh, lpr, rpb, Z, nw, Hz, ctl, 0);
+        k_fista_u1<<<nblk, STEP_BS, 0, s>>>(slot, x, grad, Hz, Z, D, Dn, ctl, part);
+        k_fista_sc<<<1, STEP_BS, 0, s>>>(nblk, part, ctl, max_inner);
+        k_fista_u2<<<nblk, STEP_BS, 0, s>>>(n, Dn, D, Z, ctl);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gap_finish(hipStream_t s, int n, const double *grad, const double *H, int ldh,
+                             int nw, const double *D, double *HD, double *ctl)
+{
+    int lpr, rpb;
+    hmv_shape(n, &lpr, &rpb);
+    const int nblk_r = (n + rpb - 1) / rpb;
+    k_hmv<<<nblk_r, PASS_BS, (size_t)nw * sizeof(double), s>>>(H, n, ldh, lpr, rpb, D, nw, HD, ctl, 1);
+    k_gap_px<<<1, STEP_BS, 0, s>>>(n, grad, D, HD, ctl);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// launch wrappers
+
+template <int B>
+static hipError_t group_b(hipStream_t s, Slot *slots, int nslots, const Tile *tiles, int ntiles,
+                          int dtype, int max_nblk_step, int max_ny, int max_nw, int max_epi,
+                          hipEvent_t ev0, hipEvent_t ev1)
+{
+    const size_t step_lds = (size_t)(B + 1) * (size_t)(max_ny > 0 ? max_ny : 1) * sizeof(double);
+    k_step<B><<<dim3(max_nblk_step, nslots), STEP_BS, step_lds, s>>>(slots);
+    const size_t accsz = dtype == DT_F64 ? sizeof(double) : sizeof(float);
+    size_t pass_lds = (size_t)max_nw * sizeof(double);
+    const size_t trial_lds = (size_t)B * max_nw * accsz;
+    if (trial_lds > pass_lds) pass_lds = trial_lds;
+    if (ev0) hipEventRecord(ev0, s);
+    switch (dtype) {
+    case DT_F64: k_pass<DT_F64, B><<<ntiles, PASS_BS, pass_lds, s>>>(slots, tiles); break;
+    case DT_F32: k_pass<DT_F32, B><<<ntiles, PASS_BS, pass_lds, s>>>(slots, tiles); break;
+    case DT_BF16: k_pass<DT_BF16, B><<<ntiles, PASS_BS, pass_lds, s>>>(slots, tiles); break;
+    default: k_pass<DT_F16, B><<<ntiles, PASS_BS, pass_lds, s>>>(slots, tiles); break;
+    }
+    if (ev1) hipEventRecord(ev1, s);
+    k_epi<B><<<dim3(max_epi, nslots), STEP_BS, 0, s>>>(slots);
+    k_ctrl<B><<<nslots, STEP_BS, 0, s>>>(slots);
+    return hipGetLastError();
+}
+
+hipError_t launch_group(hipStream_t s, Slot *slots, int nslots, const Tile *tiles, int ntiles,
+                        int B, int dtype, int max_nblk_step, int max_ny, int max_nw,
+                        int max_epi, hipEvent_t ev0, hipEvent_t ev1)
+{
+    switch (B) {
+    case 1: return group_b<1>(s, slots, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, ev0, ev1);
+    case 2: return group_b<2>(s, slots, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, ev0, ev1);
+    case 3: return group_b<3>(s, slots, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, ev0, ev1);
+    default: return group_b<4>(s, slots, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, ev0, ev1);
+    }
+}
+
+template <int B>
+static hipError_t pass_only_b(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles, int dtype,
+                              int max_nw)
+{
+    const size_t accsz = dtype == DT_F64 ? sizeof(double) : sizeof(float);
+    size_t pass_lds = (size_t)max_nw * sizeof(double);
+    const size_t trial_lds = (size_t)B * max_nw * accsz;
+    if (trial_lds > pass_lds) pass_lds = trial_lds;
+    switch (dtype) {
+    case DT_F64: k_pass<DT_F64, B><<<ntiles, PASS_BS, pass_lds, s>>>(slots, tiles); break;
+    case DT_F32: k_pass<DT_F32, B><<<ntiles, PASS_BS, pass_lds, s>>>(slots, tiles); break;
+    case DT_BF16: k_pass<DT_BF16, B><<<ntiles, PASS_BS, pass_lds, s>>>(slots, tiles); break;
+    default: k_pass<DT_F16, B><<<ntiles, PASS_BS, pass_lds, s>>>(slots, tiles); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pass_only(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles, int B,
+                            int dtype, int max_nw)
+{
+    switch (B) {
+    case 1: return pass_only_b<1>(s, slots, tiles, ntiles, dtype, max_nw);
+    case 2: return pass_only_b<2>(s, slots, tiles, ntiles, dtype, max_nw);
+    case 3: return pass_only_b<3>(s, slots, tiles, ntiles, dtype, max_nw);
+    default: return pass_only_b<4>(s, slots, tiles, ntiles, dtype, max_nw);
+    }
+}
+
+hipError_t launch_epi_anchor(hipStream_t s, Slot *slots, int nslots, int max_epi)
+{
+    // k_epi<1> handles the anchor mode for any B (it only touches candidate 0)
+    k_epi<1><<<dim3(max_epi, nslots), STEP_BS, 0, s>>>(slots);
+    return hipGetLastError();
+}
+
+hipError_t launch_matvec1(hipStream_t s, const void *Q, int dtype, int n, int ld, int row_base,
+                          const double *v, int nw, double *z)
+{
+    const int vec = dtype == DT_F64 ? 2 : (dtype == DT_F32 ? 4 : 8);
+    const int vpr = (n + vec - 1) / vec;
+    int lpr = 16;
+    if (vpr >= 4 * 64) lpr = 64;
+    else if (vpr >= 4 * 32) lpr = 32;
+    const int rows_per_block = 32;
+    const int nblk = (n + rows_per_block - 1) / rows_per_block;
+    const size_t lds = (size_t)nw * sizeof(double);
+    switch (dtype) {
+    case DT_F64: k_matvec1<DT_F64><<<nblk, PASS_BS, lds, s>>>(Q, n, ld, row_base, lpr, rows_per_block, v, nw, z); break;
+    case DT_F32: k_matvec1<DT_F32><<<nblk, PASS_BS, lds, s>>>(Q, n, ld, row_base, lpr, rows_per_block, v, nw, z); break;
+    case DT_BF16: k_matvec1<DT_BF16><<<nblk, PASS_BS, lds, s>>>(Q, n, ld, row_base, lpr, rows_per_block, v, nw, z); break;
+    default: k_matvec1<DT_F16><<<nblk, PASS_BS, lds, s>>>(Q, n, ld, row_base, lpr, rows_per_block, v, nw, z); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_grad(hipStream_t s, const Slot *slot, int n, const double *U, const double *y,
+                       double *out)
+{
+    k_grad<<<(n + STEP_BS - 1) / STEP_BS, STEP_BS, 0, s>>>(slot, U, y, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_kkt(hipStream_t s, const Slot *slot, int n, const double *x, const double *y,
+                      const double *U, const double *G, double *part, double *out6)
+{
+    const int nblk = (n + STEP_BS - 1) / STEP_BS;
+    k_kkt_part<<<nblk, STEP_BS, 0, s>>>(slot, x, y, U, part);
+    k_kkt_fin<<<1, STEP_BS, 0, s>>>(slot, nblk, y, G, part, out6);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(hipStream_t s, const void *src, int src_dtype, int64_t ld_src,
+                          void *dst, int dst_dtype, int64_t ld_dst, int64_t rows, int64_t n)
+{
+    const int64_t total = rows * ld_dst;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    k_convert<<<(unsigned)blocks, 256, 0, s>>>(src, src_dtype, ld_src, dst, dst_dtype, ld_dst, rows, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_start(hipStream_t s, Slot *slot)
+{
+    k_start<<<1, STEP_BS, 0, s>>>(slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_restart_decision(hipStream_t s, Slot *slot, double gap, int first)
+{
+    k_restart_decision<<<1, STEP_BS, 0, s>>>(slot, gap, first);
+    return hipGetLastError();
+}
+
+template <int DT, int B>
+static hipError_t set_attr_one(int max_lds)
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass<DT, B>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+}
+
+hipError_t prepare_kernels(int max_lds)
+{
+    hipError_t e = hipSuccess;
+#define QCQP_ATTR(DT)                                    \
+    if (e == hipSuccess) e = set_attr_one<DT, 1>(max_lds);      \
+    if (e == hipSuccess) e = set_attr_one<DT, 2>(max_lds);      \
+    if (e == hipSuccess) e = set_attr_one<DT, 3>(max_lds);      \
+    if (e == hipSuccess) e = set_attr_one<DT, 4>(max_lds);
+    QCQP_ATTR(DT_F64)
+    QCQP_ATTR(DT_F32)
+    QCQP_ATTR(DT_BF16)
+    QCQP_ATTR(DT_F16)
+#undef QCQP_ATTR
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_hmv),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_matvec1<DT_F64>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_matvec1<DT_F32>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_matvec1<DT_BF16>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_matvec1<DT_F16>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    return e;
+}
+
+}  // namespace qcqp

@@ -1,0 +1,107 @@
+// Device-side data layout shared by the HIP kernels and the host runtime of the rAPDB library.
+//
+// One "slot" is one resident QCQP solve.  A trial group (one backtracking test of APDB-yx,
+// §3.2, for every running slot) is four launches on one stream:
+//   k_step  : dual step + cone projection (eq. (apdb-yx-y)), primal step + box projection,
+//             for spec_trials candidate step sizes tau * eta^b; KKT partials of the iterate;
+//   k_pass  : the Q-stack pass -- one streamed GEMV over the stacked ((m+1) n) x n matrix per
+//             slot, all candidates at once, x (or the step d) staged in LDS;
+//   k_epi   : per-matrix dot products (g_i, f, d'(Q_i d)) with fixed-order block reductions;
+//   k_ctrl  : FP64 test E_k <= rhs per candidate in order, acceptance, step-size/momentum/
+//             averaging bookkeeping (Algorithm 1), fixed restarts (Algorithm 2), KKT stop.
+// The host never reads per-trial data: it enqueues groups and polls a status word.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qcqp {
+
+constexpr int MAXB = 4;            // max speculative candidates per pass
+constexpr int NPART = 4 + MAXB;    // step-kernel partials per block: rx2, s0, s1, s2, dd[b]
+constexpr int STEP_BS = 256;       // threads per block of the vector kernels
+constexpr int PASS_BS = 256;       // threads per block of the pass kernel
+
+enum SlotStatus : int32_t {
+    ST_RUNNING = 0,
+    ST_CONVERGED = 1,
+    ST_MAX_ITER = 2,
+    ST_NUMERICAL = 3,
+    ST_GAP_PENDING = 4,   // adaptive restart: host evaluates G_xi, then resumes the slot
+    ST_IDLE = 5
+};
+
+enum SlotMode : int32_t {
+    MODE_TRIAL = 0,       // candidates -> pass -> test
+    MODE_ANCHOR = 1       // direct FP64-accumulated pass at x (start / restart)
+};
+
+enum StoreType : int32_t { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2, DT_F16 = 3 };
+
+struct Slot {
+    // ---- constants (set at admission) ----
+    int32_t n, m, p, ny;          // ny = p + m
+    int32_t nq, has_q0;           // stored matrices nq = m + has_q0
+    int32_t ld, dtype;            // row stride (elements) and storage type of Q
+    int32_t c_nm, restart, restart_from_avg, incremental;
+    int32_t B, nblk_step, nw, pad0;   // nw = n rounded up to the pass vector width
+    int64_t restart_every, ada_first, ada_every, max_iter;
+    double eta, tau_bar, gamma0, mu, c_alpha, delta, tol, q_restart;
+    double cnorm, bnorm;          // ||c_{1..m}||, ||b||  (KKT scales)
+    const void *Q;
+    const double *q, *c, *A, *b, *lb, *ub;
+    // ---- buffers (pointers swapped by k_ctrl on acceptance) ----
+    double *x, *xc[MAXB];         // iterate x^k and candidates x^{k+1}(tau_b)
+    double *U, *Uc[MAXB];         // [Q_i x] of the iterate / of the candidates, (m+1) x n
+    double *W[MAXB];              // incremental pass outputs [Q_i d_b]
+    double *y, *yc[MAXB];         // y^k = (v, lambda) and candidates, ny
+    double *G, *Gc[MAXB], *Gp;    // (Ax-b, g(x), f(x)), ny + 1; Gp = value at x^{k-1}
+    double *dG[MAXB];             // incremental: exact difference Gc - G, ny + 1
+    double *e;                    // MAXB x (m+1): d_b'(Q_i d_b)
+    double *cx, *cy;              // weighted sums for the ergodic average
+    double *part;                 // nblk_step x NPART step partials
+    // ---- mutable scalars ----
+    double tau, tau_prev, sig_prev, gam, sig0, alpha_k, T;
+    double kkt[4];                // rel_kkt, rel_dual, rel_pri, rel_comp of the iterate
+    double f, maxviol;
+    double Gref, last_gap;
+    int64_t k, ke, trials, passes, restarts, gap_evals, iter_trials;
+    int32_t status, mode;
+};
+
+struct Tile {
+    int32_t slot;
+    int32_t row0;    // first stored row (0 .. nq*n)
+    int32_t nrows;
+    int32_t lpr;     // lanes per row: 16, 32 or 64
+};
+
+// ---- launch wrappers (kernels.hip) ----
+hipError_t launch_group(hipStream_t s, Slot *slots, int nslots, const Tile *tiles, int ntiles,
+                        int B, int dtype, int max_nblk_step, int max_ny, int max_nw,
+                        int max_epi, hipEvent_t ev0, hipEvent_t ev1);
+hipError_t launch_pass_only(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles, int B,
+                            int dtype, int max_nw);
+hipError_t launch_epi_anchor(hipStream_t s, Slot *slots, int nslots, int max_epi);
+hipError_t launch_matvec1(hipStream_t s, const void *Q, int dtype, int n, int ld, int row_base,
+                          const double *v, int nw, double *z);
+hipError_t launch_grad(hipStream_t s, const Slot *slot, int n, const double *U, const double *y,
+                       double *out);
+hipError_t launch_kkt(hipStream_t s, const Slot *slot, int n, const double *x, const double *y,
+                      const double *U, const double *G, double *part, double *out6);
+hipError_t launch_convert(hipStream_t s, const void *src, int src_dtype, int64_t ld_src,
+                          void *dst, int dst_dtype, int64_t ld_dst, int64_t rows, int64_t n);
+hipError_t launch_start(hipStream_t s, Slot *slot);
+hipError_t launch_restart_decision(hipStream_t s, Slot *slot, double gap, int first);
+hipError_t launch_gap_setup(hipStream_t s, const Slot *slot, int n, const double *y,
+                            const double *G, const double *grad, double xi, double *H, int ldh,
+                            double *rowabs, double tol, double *ctl);
+hipError_t launch_gap_iters(hipStream_t s, const Slot *slot, int n, const double *x,
+                            const double *grad, const double *H, int ldh, int nw, double *Z,
+                            double *D, double *Dn, double *Hz, double *part, double *ctl,
+                            int iters, int64_t max_inner);
+hipError_t launch_gap_finish(hipStream_t s, int n, const double *grad, const double *H, int ldh,
+                             int nw, const double *D, double *HD, double *ctl);
+hipError_t prepare_kernels(int max_lds_bytes);
+
+}  // namespace qcqp

@@ -1,0 +1,1040 @@
+// Host runtime of the rAPDB library: handles, device memory, the device-resident solve loop,
+// evaluations, and continuous batching.  Implements include/qcqp.h.
+//
+// Paper: "Restarted Accelerated Primal-Dual Algorithms with Adaptive Stepsizes for Nonlinear
+// Conic Constrained Convex Optimization" (arXiv 2605.29291); the method is Algorithm 2
+// (rAPDB) around the APDB-yx routine of §3.2; see kernels.hip for the per-kernel mapping.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/qcqp.h"
+#include "qcqp_device.h"
+
+using namespace qcqp;
+
+namespace {
+
+thread_local std::string g_err;
+
+qcqp_status fail(qcqp_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(e_ == hipErrorOutOfMemory ? QCQP_E_NOMEM : QCQP_E_DEVICE, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                   \
+    } while (0)
+
+int elem_size(int dt) { return dt == DT_F64 ? 8 : (dt == DT_F32 ? 4 : 2); }
+int vec_width(int dt) { return 16 / elem_size(dt); }
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+bool prepared = false;
+int prepared_dev = -1;
+int max_lds = 64 * 1024;   // dynamic LDS a workgroup may request on this device
+
+qcqp_status ensure_prepared()
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (!prepared || prepared_dev != dev) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess || v <= 0)
+            HIPCHK(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        max_lds = v;
+        HIPCHK(prepare_kernels(v));
+        prepared = true;
+        prepared_dev = dev;
+    }
+    return QCQP_OK;
+}
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// lanes per row and rows per tile for a stack of `rows` rows of n elements of type dt
+void tile_shape(int64_t n, int dt, int64_t rows, int *lpr, int *rows_per_tile)
+{
+    const int64_t vpr = (n + vec_width(dt) - 1) / vec_width(dt);   // 16-byte vectors per row
+    int l = 16;
+    if (vpr >= 4 * 64) l = 64;
+    else if (vpr >= 4 * 32) l = 32;
+    const int ng = PASS_BS / l;
+    // aim for >= ~1024 tiles when the stack is large, never more than 128 rows per tile
+    int64_t r = (rows + 1023) / 1024;
+    r = round_up(std::max<int64_t>(r, ng), ng);
+    r = std::min<int64_t>(r, 128);
+    *lpr = l;
+    *rows_per_tile = (int)r;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+
+struct qcqp_handle {
+    int dev = 0;
+    hipStream_t stream = nullptr;
+    qcqp_options opt{};
+    int64_t n = 0, m = 0, p = 0, ny = 0, nq = 0, ld = 0, nw = 0;
+    int has_q0 = 1, on_device = 0, dtype = DT_F64, incremental = 0, B = 1;
+    void *dQ = nullptr;
+    char *arena = nullptr;
+    size_t arena_bytes = 0, q_bytes = 0;
+    Slot hslot{};             // canonical buffer assignment; uploaded at the start of a run
+    Slot *dslot = nullptr;    // device copy used by single solves
+    Slot *dslot_eval = nullptr;   // device slot of point evaluations (never the running one)
+    Tile *dtiles = nullptr;
+    std::vector<Tile> tiles;  // slot field 0
+    int nblk_step = 1;
+    double *d_ueval = nullptr, *d_geval = nullptr, *d_grad = nullptr, *d_kpart = nullptr,
+           *d_out6 = nullptr, *d_xe = nullptr, *d_ye = nullptr;
+    Slot *h_poll = nullptr;   // pinned
+    double *h_out = nullptr;  // pinned scratch (16 doubles)
+    qcqp_batch *owner = nullptr;
+    double *gap_mem = nullptr;  // G_xi scratch: H (n x ldh), 6 vectors, partials, control
+    size_t gap_bytes = 0;
+};
+
+struct qcqp_batch {
+    qcqp_options opt{};
+    size_t budget = 0;
+    int64_t max_slots = 0;
+    int dev = 0;
+    hipStream_t stream = nullptr;
+    std::vector<qcqp_handle *> handles;   // per slot, nullptr = free
+    std::vector<int> finished;            // per slot: status already reported finished
+    Slot *dslots = nullptr;
+    Slot *h_poll = nullptr;               // pinned copy of all slots
+    Tile *dtiles = nullptr;
+    size_t tiles_cap = 0;
+    int ntiles = 0, max_nblk = 1, max_ny = 1, max_nw = 2, max_epi = 1;
+    bool dirty = true;
+};
+
+// ---------------------------------------------------------------------------------------
+
+extern "C" {
+
+const char *qcqp_last_error(void) { return g_err.c_str(); }
+
+void qcqp_options_default(qcqp_options *o)
+{
+    std::memset(o, 0, sizeof(*o));
+    o->variant = QCQP_YX;
+    o->c_nm = 1;
+    o->eta = 0.7;
+    o->tau_bar = 0.0;
+    o->gamma0 = 0.1;
+    o->mu = 0.0;
+    o->c_alpha = 0.4;
+    o->c_beta = 0.0;
+    o->delta = 0.5;
+    o->restart = QCQP_RESTART_FIXED;
+    o->restart_every = 400;
+    o->restart_from_average = 0;
+    o->xi = 0.04;
+    o->q_restart = 0.5;
+    o->ada_first = 50;
+    o->ada_every = 500;
+    o->max_iter = 50000;
+    o->tol = 1e-6;
+    o->storage = QCQP_F64;
+    o->pass_mode = QCQP_PASS_AUTO;
+    o->spec_trials = 2;
+    o->poll_every = 0;
+    o->timing = 0;
+    o->inner_tol = 1e-12;
+    o->max_inner = 100000;
+    o->stream = nullptr;
+}
+
+static qcqp_status validate_options(const qcqp_options *o)
+{
+    if (o->variant != QCQP_YX)
+        return fail(QCQP_E_INVALID, "only the APDB-yx routine runs on the GPU (variant=%d)", (int)o->variant);
+    if (!(o->eta > 0.0 && o->eta < 1.0)) return fail(QCQP_E_INVALID, "eta must lie in (0,1)");
+    if (!(o->gamma0 > 0.0) || !std::isfinite(o->gamma0)) return fail(QCQP_E_INVALID, "gamma0 must be > 0");
+    if (!(o->tau_bar >= 0.0) || !std::isfinite(o->tau_bar)) return fail(QCQP_E_INVALID, "tau_bar must be >= 0");
+    if (!(o->mu >= 0.0)) return fail(QCQP_E_INVALID, "mu must be >= 0");
+    if (!(o->c_alpha > 0.0 && o->delta >= 0.0 && o->delta < 1.0 && o->c_alpha + o->delta <= 1.0))
+        return fail(QCQP_E_INVALID, "APDB-yx needs c_alpha > 0, delta in [0,1), c_alpha + delta <= 1");
+    if (o->c_nm != 0 && o->c_nm != 1) return fail(QCQP_E_INVALID, "c_nm must be 0 or 1");
+    if (o->restart < QCQP_RESTART_NONE || o->restart > QCQP_RESTART_ADAPTIVE)
+        return fail(QCQP_E_INVALID, "unknown restart mode");
+    if (o->restart == QCQP_RESTART_FIXED && o->restart_every < 1)
+        return fail(QCQP_E_INVALID, "restart_every must be >= 1");
+    if (o->restart == QCQP_RESTART_ADAPTIVE &&
+        (o->ada_every < 1 || o->ada_first < 0 || !(o->xi > 0.0) || !(o->q_restart > 0.0 && o->q_restart < 1.0)))
+        return fail(QCQP_E_INVALID, "adaptive restart needs ada_every >= 1, xi > 0, q in (0,1)");
+    if (o->max_iter < 0) return fail(QCQP_E_INVALID, "max_iter must be >= 0");
+    if (!(o->tol >= 0.0)) return fail(QCQP_E_INVALID, "tol must be >= 0");
+    if (o->storage < QCQP_F64 || o->storage > QCQP_F16) return fail(QCQP_E_INVALID, "unknown storage type");
+    if (o->spec_trials < 1 || o->spec_trials > MAXB)
+        return fail(QCQP_E_INVALID, "spec_trials must be in 1..%d", MAXB);
+    if (o->pass_mode < QCQP_PASS_AUTO || o->pass_mode > QCQP_PASS_INCREMENTAL)
+        return fail(QCQP_E_INVALID, "unknown pass mode");
+    return QCQP_OK;
+}
+
+static void free_handle_memory(qcqp_handle *h)
+{
+    if (h->dQ) (void)hipFree(h->dQ);
+    if (h->arena) (void)hipFree(h->arena);
+    if (h->h_poll) (void)hipHostFree(h->h_poll);
+    if (h->h_out) (void)hipHostFree(h->h_out);
+    if (h->gap_mem) (void)hipFree(h->gap_mem);
+    h->gap_mem = nullptr;
+    h->dQ = nullptr;
+    h->arena = nullptr;
+    h->h_poll = nullptr;
+    h->h_out = nullptr;
+}
+
+// largest eigenvalue estimate of stored matrix `mat` by power iteration from 1/sqrt(n)
+static qcqp_status power_norm(qcqp_handle *h, int mat, double *out)
+{
+    const int64_t n = h->n;
+    double *v = h->d_xe, *z = h->d_grad;
+    std::vector<double> hv(n, 1.0 / std::sqrt((double)n)), hz(n);
+    HIPCHK(hipMemcpyAsync(v, hv.data(), n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    double lam = 0.0;
+    for (int it = 0; it < 30; ++it) {
+        HIPCHK(launch_matvec1(h->stream, h->dQ, h->dtype, (int)n, (int)h->ld, (int)(mat * n), v,
+                              (int)h->nw, z));
+        HIPCHK(hipMemcpyAsync(hz.data(), z, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        double s = 0.0;
+        for (int64_t j = 0; j < n; ++j) s += hz[j] * hz[j];
+        lam = std::sqrt(s);
+        if (!(lam > 0.0)) break;
+        for (int64_t j = 0; j < n; ++j) hv[j] = hz[j] / lam;
+        HIPCHK(hipMemcpyAsync(v, hv.data(), n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    }
+    *out = lam;
+    return QCQP_OK;
+}
+
+qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_handle **out)
+{
+    g_err.clear();
+    if (!P || !out) return fail(QCQP_E_INVALID, "null argument");
+    qcqp_options o;
+    if (opt) o = *opt;
+    else qcqp_options_default(&o);
+    qcqp_status st = validate_options(&o);
+    if (st) return st;
+    const int64_t n = P->n, m = P->m, p = P->p;
+    if (n <= 0 || m < 0 || p < 0 || p >= n) return fail(QCQP_E_INVALID, "need n > 0, m >= 0, 0 <= p < n");
+    if (n > 16384 || m > 1024 || p > 64)
+        return fail(QCQP_E_INVALID, "sizes beyond the supported limits (n<=16384, m<=1024, p<=64)");
+    const int64_t ldq = P->ldq ? P->ldq : n;
+    if (ldq < n) return fail(QCQP_E_INVALID, "ldq < n");
+    if (!P->q || !P->c || !P->lb || !P->ub) return fail(QCQP_E_INVALID, "q, c, lb, ub are required");
+    if (p > 0 && (!P->A || !P->b)) return fail(QCQP_E_INVALID, "A and b are required when p > 0");
+    if ((P->has_q0 || m > 0) && !P->Q) return fail(QCQP_E_INVALID, "Q is required");
+    if (P->Q_dtype < QCQP_F64 || P->Q_dtype > QCQP_F16) return fail(QCQP_E_INVALID, "unknown Q_dtype");
+    const int has_q0 = P->has_q0 ? 1 : 0;
+    const int64_t nq = m + has_q0;
+
+    qcqp_handle *h = new (std::nothrow) qcqp_handle();
+    if (!h) return fail(QCQP_E_NOMEM, "host allocation");
+    h->opt = o;
+    h->n = n; h->m = m; h->p = p; h->ny = p + m; h->nq = nq; h->has_q0 = has_q0;
+    h->on_device = P->on_device ? 1 : 0;
+    h->dtype = (int)o.storage;
+    h->stream = (hipStream_t)o.stream;
+    h->B = o.spec_trials;
+    h->incremental = o.pass_mode == QCQP_PASS_INCREMENTAL ||
+                     (o.pass_mode == QCQP_PASS_AUTO && o.storage != QCQP_F64);
+    if (hipGetDevice(&h->dev) != hipSuccess) { delete h; return fail(QCQP_E_DEVICE, "no HIP device"); }
+    if ((st = ensure_prepared())) { delete h; return st; }
+
+    // ---- host-side validation of the small vectors (copied to host when on device) ----
+    std::vector<double> hq((m + 1) * n), hc(m + 1), hlb(n), hub(n), hA(p * n), hb(p);
+    auto fetch = [&](std::vector<double> &dst, const double *src, size_t cnt) -> qcqp_status {
+        if (cnt == 0) return QCQP_OK;
+        if (h->on_device) HIPCHK(hipMemcpy(dst.data(), src, cnt * sizeof(double), hipMemcpyDeviceToHost));
+        else std::memcpy(dst.data(), src, cnt * sizeof(double));
+        return QCQP_OK;
+    };
+    if ((st = fetch(hq, P->q, hq.size())) || (st = fetch(hc, P->c, hc.size())) ||
+        (st = fetch(hlb, P->lb, n)) || (st = fetch(hub, P->ub, n)) ||
+        (st = fetch(hA, P->A, hA.size())) || (st = fetch(hb, P->b, hb.size()))) {
+        delete h;
+        return st;
+    }
+    for (int64_t j = 0; j < n; ++j)
+        if (!std::isfinite(hlb[j]) || !std::isfinite(hub[j]) || !(hlb[j] <= hub[j])) {
+            delete h;
+            return fail(QCQP_E_INVALID, "box bounds must be finite with lb <= ub (index %lld)", (long long)j);
+        }
+    for (double v : hq) if (!std::isfinite(v)) { delete h; return fail(QCQP_E_INVALID, "non-finite q"); }
+    for (double v : hc) if (!std::isfinite(v)) { delete h; return fail(QCQP_E_INVALID, "non-finite c"); }
+    for (double v : hA) if (!std::isfinite(v)) { delete h; return fail(QCQP_E_INVALID, "non-finite A"); }
+    for (double v : hb) if (!std::isfinite(v)) { delete h; return fail(QCQP_E_INVALID, "non-finite b"); }
+
+    // ---- Q stack in the storage type, rows padded to 128 bytes ----
+    const int es = elem_size(h->dtype);
+    h->ld = round_up(n, 128 / es);
+    h->nw = round_up(n, vec_width(h->dtype));
+    {
+        const size_t acc = h->dtype == DT_F64 ? 8 : 4;
+        const size_t lds = std::max<size_t>((size_t)h->nw * 8, (size_t)h->B * h->nw * acc);
+        if (lds > (size_t)max_lds) {
+            delete h;
+            return fail(QCQP_E_INVALID, "n = %lld with spec_trials = %d needs %zu bytes of LDS (device allows %d)",
+                        (long long)n, o.spec_trials, lds, max_lds);
+        }
+    }
+    h->q_bytes = (size_t)nq * n * h->ld * es;
+    if (nq > 0) {
+        if (hipMalloc(&h->dQ, h->q_bytes) != hipSuccess) {
+            delete h;
+            return fail(QCQP_E_NOMEM, "Q stack (%zu bytes)", h->q_bytes);
+        }
+        const int sdt = (int)P->Q_dtype;
+        const size_t smat = (size_t)n * ldq * elem_size(sdt);
+        void *stage = nullptr;
+        if (!h->on_device) {
+            if (hipMalloc(&stage, smat) != hipSuccess) {
+                free_handle_memory(h);
+                delete h;
+                return fail(QCQP_E_NOMEM, "staging buffer");
+            }
+        }
+        for (int64_t i = 0; i < nq; ++i) {
+            const char *src = (const char *)P->Q + i * smat;
+            const void *dsrc = src;
+            hipError_t e = hipSuccess;
+            if (!h->on_device) {
+                e = hipMemcpy(stage, src, smat, hipMemcpyHostToDevice);
+                dsrc = stage;
+            }
+            if (e == hipSuccess)
+                e = launch_convert(h->stream, dsrc, sdt, ldq, (char *)h->dQ + (size_t)i * n * h->ld * es,
+                                   h->dtype, h->ld, n, n);
+            if (e == hipSuccess && !h->on_device) e = hipStreamSynchronize(h->stream);
+            if (e != hipSuccess) {
+                if (stage) (void)hipFree(stage);
+                free_handle_memory(h);
+                delete h;
+                return fail(QCQP_E_DEVICE, "Q upload/convert: %s", hipGetErrorString(e));
+            }
+        }
+        if (stage) (void)hipFree(stage);
+    }
+
+    // ---- arena for vectors and state ----
+    const int B = h->B;
+    h->nblk_step = (int)((n + STEP_BS - 1) / STEP_BS);
+    const int64_t ny = h->ny, U1 = (m + 1) * n;
+    std::vector<std::pair<double **, int64_t>> plan;
+    Slot &S = h->hslot;
+    std::memset(&S, 0, sizeof(S));
+    double *dq, *dc, *dA = nullptr, *db = nullptr, *dlb, *dub;
+    plan.push_back({&dq, U1});
+    plan.push_back({&dc, m + 1});
+    if (p) { plan.push_back({&dA, p * n}); plan.push_back({&db, p}); }
+    plan.push_back({&dlb, n});
+    plan.push_back({&dub, n});
+    plan.push_back({&S.x, n});
+    for (int b = 0; b < B; ++b) plan.push_back({&S.xc[b], n});
+    plan.push_back({&S.U, U1});
+    for (int b = 0; b < B; ++b) plan.push_back({&S.Uc[b], U1});
+    if (h->incremental)
+        for (int b = 0; b < B; ++b) plan.push_back({&S.W[b], U1});
+    plan.push_back({&S.y, ny + 1});
+    for (int b = 0; b < B; ++b) plan.push_back({&S.yc[b], ny + 1});
+    plan.push_back({&S.G, ny + 1});
+    for (int b = 0; b < B; ++b) plan.push_back({&S.Gc[b], ny + 1});
+    plan.push_back({&S.Gp, ny + 1});
+    for (int b = 0; b < B; ++b) plan.push_back({&S.dG[b], ny + 1});
+    plan.push_back({&S.e, MAXB * (m + 1)});
+    plan.push_back({&S.cx, n});
+    plan.push_back({&S.cy, ny + 1});
+    plan.push_back({&S.part, (int64_t)h->nblk_step * NPART});
+    plan.push_back({&h->d_ueval, U1});
+    plan.push_back({&h->d_geval, ny + 1});
+    plan.push_back({&h->d_grad, n});
+    plan.push_back({&h->d_kpart, (int64_t)h->nblk_step * 4});
+    plan.push_back({&h->d_out6, 8});
+    plan.push_back({&h->d_xe, n});
+    plan.push_back({&h->d_ye, ny + 1});
+    size_t total = 0;
+    for (auto &pr : plan) total += (size_t)round_up(pr.second * 8, 256);
+    const size_t slot_off = total;
+    total += 2 * round_up(sizeof(Slot), 256);
+    // tiles
+    int lpr = 16, rpt = 16;
+    tile_shape(n, h->dtype, nq * n, &lpr, &rpt);
+    const int64_t rows = nq * n;
+    for (int64_t r0 = 0; r0 < rows; r0 += rpt)
+        h->tiles.push_back(Tile{0, (int32_t)r0, (int32_t)std::min<int64_t>(rpt, rows - r0), lpr});
+    const size_t tile_off = total;
+    total += round_up((int64_t)std::max<size_t>(h->tiles.size(), 1) * sizeof(Tile), 256);
+    if (hipMalloc(&h->arena, total) != hipSuccess) {
+        free_handle_memory(h);
+        delete h;
+        return fail(QCQP_E_NOMEM, "state arena (%zu bytes)", total);
+    }
+    h->arena_bytes = total;
+    {
+        size_t off = 0;
+        for (auto &pr : plan) {
+            *pr.first = reinterpret_cast<double *>(h->arena + off);
+            off += (size_t)round_up(pr.second * 8, 256);
+        }
+    }
+    h->dslot = reinterpret_cast<Slot *>(h->arena + slot_off);
+    h->dslot_eval = reinterpret_cast<Slot *>(h->arena + slot_off + round_up(sizeof(Slot), 256));
+    h->dtiles = reinterpret_cast<Tile *>(h->arena + tile_off);
+    hipError_t e = hipMemsetAsync(h->arena, 0, total, h->stream);
+    if (e == hipSuccess && !h->tiles.empty())
+        e = hipMemcpyAsync(h->dtiles, h->tiles.data(), h->tiles.size() * sizeof(Tile),
+                           hipMemcpyHostToDevice, h->stream);
+    const hipMemcpyKind k = hipMemcpyHostToDevice;
+    if (e == hipSuccess) e = hipMemcpyAsync(dq, hq.data(), U1 * 8, k, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dc, hc.data(), (m + 1) * 8, k, h->stream);
+    if (e == hipSuccess && p) e = hipMemcpyAsync(dA, hA.data(), p * n * 8, k, h->stream);
+    if (e == hipSuccess && p) e = hipMemcpyAsync(db, hb.data(), p * 8, k, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dlb, hlb.data(), n * 8, k, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dub, hub.data(), n * 8, k, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_poll, sizeof(Slot));
+    if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_out, 16 * sizeof(double));
+    if (e != hipSuccess) {
+        free_handle_memory(h);
+        delete h;
+        return fail(QCQP_E_DEVICE, "initial upload: %s", hipGetErrorString(e));
+    }
+
+    // ---- constant slot fields ----
+    S.n = (int32_t)n; S.m = (int32_t)m; S.p = (int32_t)p; S.ny = (int32_t)ny;
+    S.nq = (int32_t)nq; S.has_q0 = has_q0; S.ld = (int32_t)h->ld; S.dtype = h->dtype;
+    S.c_nm = o.c_nm; S.restart = (int32_t)o.restart; S.restart_from_avg = o.restart_from_average ? 1 : 0;
+    S.incremental = h->incremental; S.B = B; S.nblk_step = h->nblk_step; S.nw = (int32_t)h->nw;
+    S.restart_every = o.restart_every; S.ada_first = o.ada_first; S.ada_every = o.ada_every;
+    S.max_iter = o.max_iter;
+    S.eta = o.eta; S.gamma0 = o.gamma0; S.mu = o.mu; S.c_alpha = o.c_alpha; S.delta = o.delta;
+    S.tol = o.tol; S.q_restart = o.q_restart;
+    double cn = 0.0, bn = 0.0;
+    for (int64_t i = 1; i <= m; ++i) cn += hc[i] * hc[i];
+    for (int64_t l = 0; l < p; ++l) bn += hb[l] * hb[l];
+    S.cnorm = std::sqrt(cn);
+    S.bnorm = std::sqrt(bn);
+    S.Q = h->dQ; S.q = dq; S.c = dc; S.A = dA; S.b = db; S.lb = dlb; S.ub = dub;
+
+    // ---- default initial step: 1 / ||Q_0||_2 (or 1 / max_i ||Q_i||_2 without Q_0) ----
+    double tau_bar = o.tau_bar;
+    if (!(tau_bar > 0.0)) {
+        double L = 0.0;
+        if (nq > 0) {
+            const int first = 0, last = has_q0 ? 0 : (int)nq - 1;
+            for (int mat = first; mat <= last; ++mat) {
+                double lm = 0.0;
+                if ((st = power_norm(h, mat, &lm))) { free_handle_memory(h); delete h; return st; }
+                L = std::max(L, lm);
+            }
+        }
+        tau_bar = L > 0.0 ? 1.0 / L : 1.0;
+    }
+    S.tau_bar = tau_bar;
+    h->opt.tau_bar = tau_bar;
+    *out = h;
+    return QCQP_OK;
+}
+
+size_t qcqp_handle_bytes(const qcqp_handle *h) { return h ? h->q_bytes + h->arena_bytes : 0; }
+
+qcqp_status qcqp_destroy(qcqp_handle *h)
+{
+    if (!h) return QCQP_OK;
+    if (h->owner) return fail(QCQP_E_INVALID, "handle is admitted to a batch; fetch it first");
+    free_handle_memory(h);
+    delete h;
+    return QCQP_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// run-state helpers
+
+static void reset_run_scalars(Slot &S)
+{
+    S.tau = S.tau_bar;
+    S.tau_prev = S.tau_bar;
+    S.sig_prev = S.gamma0 * S.tau_bar;
+    S.gam = S.gamma0;
+    S.sig0 = 0.0;
+    S.alpha_k = S.c_alpha / S.sig_prev;
+    S.T = 0.0;
+    for (double &v : S.kkt) v = NAN;
+    S.f = NAN;
+    S.maxviol = NAN;
+    S.Gref = NAN;
+    S.last_gap = NAN;
+    S.k = S.ke = S.trials = S.passes = S.restarts = S.gap_evals = S.iter_trials = 0;
+    S.status = ST_RUNNING;
+    S.mode = MODE_ANCHOR;
+}
+
+// copy x0 (or zeros) and y0 (or zeros) into the canonical iterate buffers
+static qcqp_status load_start(qcqp_handle *h, const double *x0, const double *y0)
+{
+    const hipMemcpyKind k = h->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (x0) HIPCHK(hipMemcpyAsync(h->hslot.x, x0, h->n * 8, k, h->stream));
+    else HIPCHK(hipMemsetAsync(h->hslot.x, 0, h->n * 8, h->stream));
+    if (h->ny) {
+        if (y0) HIPCHK(hipMemcpyAsync(h->hslot.y, y0, h->ny * 8, k, h->stream));
+        else HIPCHK(hipMemsetAsync(h->hslot.y, 0, h->ny * 8, h->stream));
+    }
+    return QCQP_OK;
+}
+
+static void fill_info(const qcqp_handle *h, const Slot &S, qcqp_info *info, double secs,
+                      double pass_secs, int64_t timed)
+{
+    if (!info) return;
+    std::memset(info, 0, sizeof(*info));
+    info->iters = S.k;
+    info->trials = S.trials;
+    info->q_passes = S.passes;
+    info->restarts = S.restarts;
+    info->gap_evals = S.gap_evals;
+    info->rel_kkt = S.kkt[0];
+    info->rel_dual = S.kkt[1];
+    info->rel_pri = S.kkt[2];
+    info->rel_comp = S.kkt[3];
+    info->f = S.f;
+    info->max_violation = S.maxviol;
+    info->seconds = secs;
+    info->pass_seconds = pass_secs;
+    info->timed_passes = timed;
+    info->last_gap = S.last_gap;
+    info->pass_bytes = (int64_t)h->nq * h->n * h->n * elem_size(h->dtype);
+    switch (S.status) {
+    case ST_CONVERGED: info->status = QCQP_OK; break;
+    case ST_MAX_ITER: info->status = QCQP_E_NOT_CONVERGED; break;
+    case ST_NUMERICAL: info->status = QCQP_E_NUMERICAL; break;
+    default: info->status = QCQP_E_NOT_CONVERGED; break;
+    }
+}
+
+static qcqp_status slot_status_code(int st)
+{
+    switch (st) {
+    case ST_CONVERGED: return QCQP_OK;
+    case ST_MAX_ITER: return QCQP_E_NOT_CONVERGED;
+    case ST_NUMERICAL: return fail(QCQP_E_NUMERICAL, "NaN/Inf met or the backtracking step underflowed");
+    default: return QCQP_E_NOT_CONVERGED;
+    }
+}
+
+static qcqp_status run_gap_for(qcqp_handle *h, Slot *dslot, const Slot &snap, double *gval, double *kk);
+
+qcqp_status qcqp_solve(qcqp_handle *h, const double *x0, const double *y0, double *x_out,
+                       double *y_out, qcqp_info *info)
+{
+    g_err.clear();
+    if (!h || !x_out) return fail(QCQP_E_INVALID, "null argument");
+    if (h->owner) return fail(QCQP_E_INVALID, "handle is admitted to a batch");
+    const double t0 = now_s();
+    qcqp_status st;
+    if ((st = load_start(h, x0, y0))) return st;
+    Slot S0 = h->hslot;
+    reset_run_scalars(S0);
+    HIPCHK(hipMemcpyAsync(h->dslot, &S0, sizeof(Slot), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(launch_start(h->stream, h->dslot));
+    int64_t poll = h->opt.poll_every;
+    if (poll <= 0) {
+        const double bytes = (double)h->q_bytes;
+        poll = bytes > 64e6 ? 4 : (bytes > 4e6 ? 16 : 64);
+    }
+    const bool timing = h->opt.timing != 0;
+    std::vector<hipEvent_t> ev;
+    if (timing) {
+        ev.resize(2 * poll);
+        for (auto &x : ev) HIPCHK(hipEventCreate(&x));
+    }
+    double pass_secs = 0.0;
+    int64_t timed = 0;
+    const int ntiles = (int)h->tiles.size();
+    Slot &snap = *h->h_poll;
+    qcqp_status result = QCQP_OK;
+    int64_t passes_before = 0;
+    for (;;) {
+        for (int64_t g = 0; g < poll; ++g) {
+            hipError_t e = launch_group(h->stream, h->dslot, 1, h->dtiles, ntiles, h->B, h->dtype,
+                                        h->nblk_step, (int)std::max<int64_t>(h->ny, 1), (int)h->nw,
+                                        (int)(h->m + 1 + h->p), timing ? ev[2 * g] : nullptr,
+                                        timing ? ev[2 * g + 1] : nullptr);
+            if (e != hipSuccess) { result = fail(QCQP_E_DEVICE, "launch: %s", hipGetErrorString(e)); break; }
+        }
+        if (result) break;
+        hipError_t e = hipMemcpyAsync(&snap, h->dslot, sizeof(Slot), hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) { result = fail(QCQP_E_DEVICE, "poll: %s", hipGetErrorString(e)); break; }
+        if (timing) {
+            // the groups that streamed a pass are the first (passes now - passes before) of the
+            // chunk: once the slot stops running every later group is a no-op
+            const int64_t worked = std::min<int64_t>(poll, snap.passes - passes_before);
+            for (int64_t g = 0; g < worked; ++g) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, ev[2 * g], ev[2 * g + 1]) == hipSuccess) {
+                    pass_secs += ms * 1e-3;
+                    timed += 1;
+                }
+            }
+        }
+        passes_before = snap.passes;
+        if (snap.status == ST_GAP_PENDING) {
+            double gval = 0.0, kk[6];
+            if ((result = run_gap_for(h, h->dslot, snap, &gval, kk))) break;
+            continue;
+        }
+        if (snap.status != ST_RUNNING) break;
+    }
+    for (auto &x : ev) (void)hipEventDestroy(x);
+    if (result) return result;
+    const hipMemcpyKind k = h->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    HIPCHK(hipMemcpyAsync(x_out, snap.x, h->n * 8, k, h->stream));
+    if (y_out && h->ny) HIPCHK(hipMemcpyAsync(y_out, snap.y, h->ny * 8, k, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    fill_info(h, snap, info, now_s() - t0, pass_secs, timed);
+    return slot_status_code(snap.status);
+}
+
+// ---------------------------------------------------------------------------------------
+// evaluations at an arbitrary point: anchor pass (FP64 accumulation) into the eval buffers
+
+// anchor pass and epilogue at the point already in d_xe / d_ye -> d_ueval, d_geval
+static qcqp_status eval_loaded_point(qcqp_handle *h)
+{
+    Slot S = h->hslot;
+    reset_run_scalars(S);
+    S.x = h->d_xe;
+    S.y = h->d_ye;
+    S.Uc[0] = h->d_ueval;
+    S.Gc[0] = h->d_geval;
+    HIPCHK(hipMemsetAsync(h->d_ueval, 0, (h->m + 1) * h->n * 8, h->stream));
+    HIPCHK(hipMemcpyAsync(h->dslot_eval, &S, sizeof(Slot), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(launch_pass_only(h->stream, h->dslot_eval, h->dtiles, (int)h->tiles.size(), h->B, h->dtype, (int)h->nw));
+    HIPCHK(launch_epi_anchor(h->stream, h->dslot_eval, 1, (int)(h->m + 1 + h->p)));
+    return QCQP_OK;
+}
+
+static qcqp_status load_point(qcqp_handle *h, const double *x, const double *y, bool device_ptrs)
+{
+    const hipMemcpyKind k = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (x != h->d_xe) HIPCHK(hipMemcpyAsync(h->d_xe, x, h->n * 8, k, h->stream));
+    if (h->ny) {
+        if (!y) HIPCHK(hipMemsetAsync(h->d_ye, 0, h->ny * 8, h->stream));
+        else if (y != h->d_ye) HIPCHK(hipMemcpyAsync(h->d_ye, y, h->ny * 8, k, h->stream));
+    }
+    return QCQP_OK;
+}
+
+static qcqp_status eval_point(qcqp_handle *h, const double *x, const double *y)
+{
+    if (h->owner) return fail(QCQP_E_INVALID, "handle is admitted to a batch");
+    qcqp_status st = load_point(h, x, y, h->on_device != 0);
+    if (st) return st;
+    return eval_loaded_point(h);
+}
+
+// G_xi at the device point (x_dev, y_dev); out4 = {G, Py, Px, inner iterations}
+static qcqp_status gap_at_device_point(qcqp_handle *h, const double *x_dev, const double *y_dev,
+                                       double xi, double *out4)
+{
+    qcqp_status st = load_point(h, x_dev, y_dev, true);
+    if (st) return st;
+    if ((st = eval_loaded_point(h))) return st;
+    HIPCHK(launch_grad(h->stream, h->dslot_eval, (int)h->n, h->d_ueval, h->d_ye, h->d_grad));
+    const int64_t n = h->n, ldh = round_up(n, 16);
+    const int nblk = (int)((n + STEP_BS - 1) / STEP_BS);
+    const size_t need = (size_t)(n * ldh + 6 * round_up(n, 32) + 2 * nblk + 64) * sizeof(double);
+    if (h->gap_bytes < need) {
+        if (h->gap_mem) (void)hipFree(h->gap_mem);
+        h->gap_mem = nullptr;
+        h->gap_bytes = 0;
+        if (hipMalloc(&h->gap_mem, need) != hipSuccess) return fail(QCQP_E_NOMEM, "G_xi scratch (%zu bytes)", need);
+        h->gap_bytes = need;
+    }
+    double *H = h->gap_mem;
+    double *v0 = H + n * ldh;
+    const int64_t vs = round_up(n, 32);
+    double *rowabs = v0, *Z = v0 + vs, *D = v0 + 2 * vs, *Dn = v0 + 3 * vs, *Hz = v0 + 4 * vs;
+    double *part = v0 + 6 * vs, *ctl = part + 2 * nblk;
+    HIPCHK(hipMemsetAsync(Z, 0, 2 * vs * 8, h->stream));   // Z and D
+    HIPCHK(launch_gap_setup(h->stream, h->dslot_eval, (int)n, h->d_ye, h->d_geval, h->d_grad, xi, H,
+                            (int)ldh, rowabs, h->opt.inner_tol, ctl));
+    const int chunk = 32;
+    for (int64_t done_it = 0;;) {
+        HIPCHK(launch_gap_iters(h->stream, h->dslot_eval, (int)n, h->d_xe, h->d_grad, H, (int)ldh,
+                                (int)round_up(n, 2), Z, D, Dn, Hz, part, ctl, chunk, h->opt.max_inner));
+        done_it += chunk;
+        HIPCHK(hipMemcpyAsync(h->h_out, ctl, 11 * 8, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        if (h->h_out[3] != 0.0) break;
+        if (done_it > h->opt.max_inner + chunk) break;
+    }
+    HIPCHK(launch_gap_finish(h->stream, (int)n, h->d_grad, H, (int)ldh, (int)round_up(n, 2), D, Hz, ctl));
+    HIPCHK(hipMemcpyAsync(h->h_out, ctl, 11 * 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const double Py = h->h_out[9], Px = h->h_out[10];
+    out4[0] = Py + Px;
+    out4[1] = Py;
+    out4[2] = Px;
+    out4[3] = h->h_out[4];
+    return QCQP_OK;
+}
+
+qcqp_status qcqp_eval_operator(qcqp_handle *h, const double *x, const double *y, double *Qx,
+                               double *g, double *f, double *grad_x)
+{
+    g_err.clear();
+    if (!h || !x) return fail(QCQP_E_INVALID, "null argument");
+    qcqp_status st;
+    if ((st = eval_point(h, x, y))) return st;
+    if (grad_x) HIPCHK(launch_grad(h->stream, h->dslot_eval, (int)h->n, h->d_ueval, h->d_ye, h->d_grad));
+    const hipMemcpyKind k = h->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (Qx) HIPCHK(hipMemcpyAsync(Qx, h->d_ueval, (h->m + 1) * h->n * 8, k, h->stream));
+    if (g && h->m) HIPCHK(hipMemcpyAsync(g, h->d_geval + h->p, h->m * 8, k, h->stream));
+    if (f) HIPCHK(hipMemcpyAsync(f, h->d_geval + h->ny, 8, k, h->stream));
+    if (grad_x) HIPCHK(hipMemcpyAsync(grad_x, h->d_grad, h->n * 8, k, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return QCQP_OK;
+}
+
+qcqp_status qcqp_eval_kkt(qcqp_handle *h, const double *x, const double *y, double *out6)
+{
+    g_err.clear();
+    if (!h || !x || !out6) return fail(QCQP_E_INVALID, "null argument");
+    qcqp_status st;
+    if ((st = eval_point(h, x, y))) return st;
+    HIPCHK(launch_kkt(h->stream, h->dslot_eval, (int)h->n, h->d_xe, h->d_ye, h->d_ueval, h->d_geval,
+                      h->d_kpart, h->d_out6));
+    HIPCHK(hipMemcpyAsync(h->h_out, h->d_out6, 6 * 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    std::memcpy(out6, h->h_out, 6 * 8);
+    return QCQP_OK;
+}
+
+qcqp_status qcqp_eval_gap(qcqp_handle *h, const double *x, const double *y, double xi, double *out4)
+{
+    g_err.clear();
+    if (!h || !x || !out4) return fail(QCQP_E_INVALID, "null argument");
+    if (!(xi > 0.0)) return fail(QCQP_E_INVALID, "xi must be > 0");
+    if (h->owner) return fail(QCQP_E_INVALID, "handle is admitted to a batch");
+    qcqp_status st = load_point(h, x, y, h->on_device != 0);
+    if (st) return st;
+    return gap_at_device_point(h, h->d_xe, h->d_ye, xi, out4);
+}
+
+// adaptive restart: evaluate G_xi at the slot's iterate and let the device decide
+static qcqp_status run_gap_for(qcqp_handle *h, Slot *dslot, const Slot &snap, double *gval, double *kk)
+{
+    (void)kk;
+    double out4[4];
+    qcqp_status st = gap_at_device_point(h, snap.x, snap.y, h->opt.xi, out4);
+    if (st) return st;
+    *gval = out4[0];
+    const int first = snap.k == snap.ada_first ? 1 : 0;
+    HIPCHK(launch_restart_decision(h->stream, dslot, out4[0], first));
+    return QCQP_OK;
+}
+
+qcqp_status qcqp_time_pass(qcqp_handle *h, int64_t reps, double *avg_seconds)
+{
+    g_err.clear();
+    if (!h || !avg_seconds || reps < 1) return fail(QCQP_E_INVALID, "bad argument");
+    if (h->owner) return fail(QCQP_E_INVALID, "handle is admitted to a batch");
+    Slot S = h->hslot;
+    reset_run_scalars(S);
+    S.mode = MODE_TRIAL;
+    HIPCHK(hipMemcpyAsync(h->dslot, &S, sizeof(Slot), hipMemcpyHostToDevice, h->stream));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(launch_pass_only(h->stream, h->dslot, h->dtiles, (int)h->tiles.size(), h->B, h->dtype, (int)h->nw));
+    HIPCHK(hipEventRecord(e0, h->stream));
+    for (int64_t r = 0; r < reps; ++r)
+        HIPCHK(launch_pass_only(h->stream, h->dslot, h->dtiles, (int)h->tiles.size(), h->B, h->dtype, (int)h->nw));
+    HIPCHK(hipEventRecord(e1, h->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_seconds = ms * 1e-3 / (double)reps;
+    return QCQP_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// continuous batching
+
+qcqp_status qcqp_batch_create(const qcqp_options *opt, size_t budget, int64_t max_slots, qcqp_batch **out)
+{
+    g_err.clear();
+    if (!out || max_slots < 1 || max_slots > 65535) return fail(QCQP_E_INVALID, "bad argument");
+    qcqp_options o;
+    if (opt) o = *opt;
+    else qcqp_options_default(&o);
+    qcqp_status st = validate_options(&o);
+    if (st) return st;
+    if ((st = ensure_prepared())) return st;
+    qcqp_batch *bt = new (std::nothrow) qcqp_batch();
+    if (!bt) return fail(QCQP_E_NOMEM, "host allocation");
+    bt->opt = o;
+    bt->budget = budget;
+    bt->max_slots = max_slots;
+    bt->stream = (hipStream_t)o.stream;
+    (void)hipGetDevice(&bt->dev);
+    bt->handles.assign(max_slots, nullptr);
+    bt->finished.assign(max_slots, 0);
+    if (hipMalloc(&bt->dslots, max_slots * sizeof(Slot)) != hipSuccess ||
+        hipHostMalloc((void **)&bt->h_poll, max_slots * sizeof(Slot)) != hipSuccess) {
+        if (bt->dslots) (void)hipFree(bt->dslots);
+        delete bt;
+        return fail(QCQP_E_NOMEM, "slot table");
+    }
+    std::memset(bt->h_poll, 0, max_slots * sizeof(Slot));
+    for (int64_t s = 0; s < max_slots; ++s) bt->h_poll[s].status = ST_IDLE;
+    if (hipMemcpy(bt->dslots, bt->h_poll, max_slots * sizeof(Slot), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(bt->dslots);
+        (void)hipHostFree(bt->h_poll);
+        delete bt;
+        return fail(QCQP_E_DEVICE, "slot table init");
+    }
+    *out = bt;
+    return QCQP_OK;
+}
+
+static size_t batch_resident(const qcqp_batch *bt)
+{
+    size_t s = 0;
+    for (auto *h : bt->handles)
+        if (h) s += h->q_bytes + h->arena_bytes;
+    return s;
+}
+
+qcqp_status qcqp_batch_stats(qcqp_batch *bt, int64_t *running, size_t *resident)
+{
+    if (!bt) return fail(QCQP_E_INVALID, "null batch");
+    int64_t r = 0;
+    for (int64_t s = 0; s < bt->max_slots; ++s)
+        if (bt->handles[s] && !bt->finished[s]) ++r;
+    if (running) *running = r;
+    if (resident) *resident = batch_resident(bt);
+    return QCQP_OK;
+}
+
+qcqp_status qcqp_batch_admit(qcqp_batch *bt, qcqp_handle *h, const double *x0, const double *y0, int64_t *slot)
+{
+    g_err.clear();
+    if (!bt || !h || !slot) return fail(QCQP_E_INVALID, "null argument");
+    if (h->owner) return fail(QCQP_E_INVALID, "handle already admitted");
+    if (h->dtype != (int)bt->opt.storage || h->B != bt->opt.spec_trials || h->dev != bt->dev)
+        return fail(QCQP_E_INVALID, "handle storage/spec_trials/device differ from the batch's");
+    int64_t free_slot = -1;
+    for (int64_t s = 0; s < bt->max_slots; ++s)
+        if (!bt->handles[s]) { free_slot = s; break; }
+    if (free_slot < 0) return fail(QCQP_E_NO_ROOM, "no free slot");
+    if (bt->budget && batch_resident(bt) + h->q_bytes + h->arena_bytes > bt->budget)
+        return fail(QCQP_E_NO_ROOM, "HBM budget exhausted");
+    // the handle's own stream work must be ordered before the batch stream's
+    HIPCHK(hipStreamSynchronize(h->stream));
+    hipStream_t saved = h->stream;
+    h->stream = bt->stream;
+    qcqp_status st = load_start(h, x0, y0);
+    h->stream = saved;
+    if (st) return st;
+    Slot S = h->hslot;
+    reset_run_scalars(S);
+    bt->h_poll[free_slot] = S;
+    HIPCHK(hipMemcpyAsync(bt->dslots + free_slot, &bt->h_poll[free_slot], sizeof(Slot),
+                          hipMemcpyHostToDevice, bt->stream));
+    HIPCHK(launch_start(bt->stream, bt->dslots + free_slot));
+    HIPCHK(hipStreamSynchronize(bt->stream));
+    bt->handles[free_slot] = h;
+    bt->finished[free_slot] = 0;
+    h->owner = bt;
+    bt->dirty = true;
+    *slot = free_slot;
+    return QCQP_OK;
+}
+
+static qcqp_status rebuild_tiles(qcqp_batch *bt)
+{
+    std::vector<Tile> all;
+    bt->max_nblk = 1;
+    bt->max_ny = 1;
+    bt->max_nw = 2;
+    bt->max_epi = 1;
+    for (int64_t s = 0; s < bt->max_slots; ++s) {
+        qcqp_handle *h = bt->handles[s];
+        if (!h || bt->finished[s]) continue;
+        for (Tile t : h->tiles) {
+            t.slot = (int32_t)s;
+            all.push_back(t);
+        }
+        bt->max_nblk = std::max(bt->max_nblk, h->nblk_step);
+        bt->max_ny = std::max<int>(bt->max_ny, (int)h->ny);
+        bt->max_nw = std::max<int>(bt->max_nw, (int)h->nw);
+        bt->max_epi = std::max<int>(bt->max_epi, (int)(h->m + 1 + h->p));
+    }
+    // interleave tiles of different slots so every slot's rows spread over all CUs
+    std::vector<Tile> mixed;
+    mixed.reserve(all.size());
+    {
+        std::vector<std::vector<Tile>> per(bt->max_slots);
+        for (auto &t : all) per[t.slot].push_back(t);
+        size_t idx = 0;
+        bool any = true;
+        while (any) {
+            any = false;
+            for (auto &v : per)
+                if (idx < v.size()) { mixed.push_back(v[idx]); any = true; }
+            ++idx;
+        }
+    }
+    if (mixed.size() > bt->tiles_cap) {
+        if (bt->dtiles) (void)hipFree(bt->dtiles);
+        bt->dtiles = nullptr;
+        size_t cap = std::max<size_t>(mixed.size() * 2, 1024);
+        HIPCHK(hipMalloc(&bt->dtiles, cap * sizeof(Tile)));
+        bt->tiles_cap = cap;
+    }
+    if (!mixed.empty())
+        HIPCHK(hipMemcpyAsync(bt->dtiles, mixed.data(), mixed.size() * sizeof(Tile),
+                              hipMemcpyHostToDevice, bt->stream));
+    bt->ntiles = (int)mixed.size();
+    bt->dirty = false;
+    return QCQP_OK;
+}
+
+qcqp_status qcqp_batch_step(qcqp_batch *bt, int64_t groups)
+{
+    g_err.clear();
+    if (!bt || groups < 0) return fail(QCQP_E_INVALID, "bad argument");
+    qcqp_status st;
+    if (bt->dirty && (st = rebuild_tiles(bt))) return st;
+    if (bt->ntiles > 0) {
+        for (int64_t g = 0; g < groups; ++g) {
+            hipError_t e = launch_group(bt->stream, bt->dslots, (int)bt->max_slots, bt->dtiles, bt->ntiles,
+                                        bt->opt.spec_trials, (int)bt->opt.storage, bt->max_nblk,
+                                        bt->max_ny, bt->max_nw, bt->max_epi, nullptr, nullptr);
+            if (e != hipSuccess) return fail(QCQP_E_DEVICE, "launch: %s", hipGetErrorString(e));
+        }
+    }
+    HIPCHK(hipMemcpyAsync(bt->h_poll, bt->dslots, bt->max_slots * sizeof(Slot), hipMemcpyDeviceToHost, bt->stream));
+    HIPCHK(hipStreamSynchronize(bt->stream));
+    // adaptive restarts pending: evaluate G_xi per slot, then resume
+    for (int64_t s = 0; s < bt->max_slots; ++s) {
+        qcqp_handle *h = bt->handles[s];
+        if (!h || bt->finished[s]) continue;
+        const Slot &S = bt->h_poll[s];
+        if (S.status == ST_GAP_PENDING) {
+            hipStream_t saved = h->stream;
+            h->stream = bt->stream;
+            double gval, kk[6];
+            st = run_gap_for(h, bt->dslots + s, S, &gval, kk);
+            h->stream = saved;
+            if (st) return st;
+        } else if (S.status != ST_RUNNING) {
+            if (!bt->finished[s]) {
+                bt->finished[s] = 1;
+                bt->dirty = true;
+            }
+        }
+    }
+    return QCQP_OK;
+}
+
+qcqp_status qcqp_batch_poll(qcqp_batch *bt, int64_t *done, int64_t cap, int64_t *n_done)
+{
+    if (!bt || !n_done) return fail(QCQP_E_INVALID, "bad argument");
+    int64_t c = 0;
+    for (int64_t s = 0; s < bt->max_slots; ++s)
+        if (bt->handles[s] && bt->finished[s]) {
+            if (done && c < cap) done[c] = s;
+            ++c;
+        }
+    *n_done = std::min(c, cap);
+    return QCQP_OK;
+}
+
+qcqp_status qcqp_batch_fetch(qcqp_batch *bt, int64_t slot, double *x_out, double *y_out,
+                             qcqp_info *info, qcqp_handle **h_out)
+{
+    g_err.clear();
+    if (!bt || slot < 0 || slot >= bt->max_slots || !bt->handles[slot])
+        return fail(QCQP_E_INVALID, "no such slot");
+    if (!bt->finished[slot]) return fail(QCQP_E_INVALID, "slot %lld is still running", (long long)slot);
+    qcqp_handle *h = bt->handles[slot];
+    const Slot &S = bt->h_poll[slot];
+    const hipMemcpyKind k = h->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (x_out) HIPCHK(hipMemcpyAsync(x_out, S.x, h->n * 8, k, bt->stream));
+    if (y_out && h->ny) HIPCHK(hipMemcpyAsync(y_out, S.y, h->ny * 8, k, bt->stream));
+    // mark the device slot idle so later groups skip it
+    Slot idle = S;
+    idle.status = ST_IDLE;
+    bt->h_poll[slot] = idle;
+    HIPCHK(hipMemcpyAsync(bt->dslots + slot, &bt->h_poll[slot], sizeof(Slot), hipMemcpyHostToDevice, bt->stream));
+    HIPCHK(hipStreamSynchronize(bt->stream));
+    fill_info(h, S, info, 0.0, 0.0, 0);
+    if (info) {
+        switch (S.status) {
+        case ST_CONVERGED: info->status = QCQP_OK; break;
+        case ST_MAX_ITER: info->status = QCQP_E_NOT_CONVERGED; break;
+        default: info->status = QCQP_E_NUMERICAL; break;
+        }
+    }
+    bt->handles[slot] = nullptr;
+    bt->finished[slot] = 0;
+    h->owner = nullptr;
+    if (h_out) *h_out = h;
+    bt->dirty = true;
+    return QCQP_OK;
+}
+
+qcqp_status qcqp_batch_destroy(qcqp_batch *bt)
+{
+    if (!bt) return QCQP_OK;
+    (void)hipStreamSynchronize(bt->stream);
+    for (auto *h : bt->handles)
+        if (h) {
+            h->owner = nullptr;
+            free_handle_memory(h);
+            delete h;
+        }
+    if (bt->dslots) (void)hipFree(bt->dslots);
+    if (bt->h_poll) (void)hipHostFree(bt->h_poll);
+    if (bt->dtiles) (void)hipFree(bt->dtiles);
+    delete bt;
+    return QCQP_OK;
+}
+
+}  // extern "C"
+
