@@ -53,44 +53,49 @@ __device__ __forceinline__ void block_sum(double (&v)[NV])
 }
 
 // ---------------------------------------------------------------------------------------
-// storage types: one 16-byte vector load per lane per chunk
+// storage types: one 16-byte vector load per lane per chunk.  Loads go through the global
+// address space (the stack pointer is read from the slot, so the compiler cannot infer it);
+// NT selects non-temporal loads for stacks that cannot stay cache-resident across passes.
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const u32x4 g_u32x4;
+
+template <bool NT>
+__device__ __forceinline__ u32x4 ld16(const void *base, size_t byte_off)
+{
+    const g_u32x4 *p = (const g_u32x4 *)((const char *)base + byte_off);
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
 
 template <int DT> struct Store;
 
 template <> struct Store<DT_F64> {
     static constexpr int V = 2;
+    static constexpr int ES = 8;
     using acc_t = double;
-    using vec_t = double2;
-    __device__ static __forceinline__ vec_t ld(const void *Q, size_t idx)
+    __device__ static __forceinline__ double get(const u32x4 &v, int e)
     {
-        return *reinterpret_cast<const double2 *>(reinterpret_cast<const double *>(Q) + idx);
+        const unsigned lo = e == 0 ? v.x : v.z, hi = e == 0 ? v.y : v.w;
+        return __hiloint2double((int)hi, (int)lo);
     }
-    __device__ static __forceinline__ double get(const vec_t &v, int e) { return e == 0 ? v.x : v.y; }
 };
 
 template <> struct Store<DT_F32> {
     static constexpr int V = 4;
+    static constexpr int ES = 4;
     using acc_t = float;
-    using vec_t = float4;
-    __device__ static __forceinline__ vec_t ld(const void *Q, size_t idx)
+    __device__ static __forceinline__ float get(const u32x4 &v, int e)
     {
-        return *reinterpret_cast<const float4 *>(reinterpret_cast<const float *>(Q) + idx);
-    }
-    __device__ static __forceinline__ float get(const vec_t &v, int e)
-    {
-        return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
+        return __uint_as_float(e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w)));
     }
 };
 
 template <> struct Store<DT_BF16> {
     static constexpr int V = 8;
+    static constexpr int ES = 2;
     using acc_t = float;
-    using vec_t = uint4;
-    __device__ static __forceinline__ vec_t ld(const void *Q, size_t idx)
-    {
-        return *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint16_t *>(Q) + idx);
-    }
-    __device__ static __forceinline__ float get(const vec_t &v, int e)
+    __device__ static __forceinline__ float get(const u32x4 &v, int e)
     {
         const uint32_t w = (e >> 1) == 0 ? v.x : ((e >> 1) == 1 ? v.y : ((e >> 1) == 2 ? v.z : v.w));
         const uint32_t bits = (e & 1) ? (w & 0xffff0000u) : (w << 16);
@@ -100,13 +105,9 @@ template <> struct Store<DT_BF16> {
 
 template <> struct Store<DT_F16> {
     static constexpr int V = 8;
+    static constexpr int ES = 2;
     using acc_t = float;
-    using vec_t = uint4;
-    __device__ static __forceinline__ vec_t ld(const void *Q, size_t idx)
-    {
-        return *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint16_t *>(Q) + idx);
-    }
-    __device__ static __forceinline__ float get(const vec_t &v, int e)
+    __device__ static __forceinline__ float get(const u32x4 &v, int e)
     {
         const uint32_t w = (e >> 1) == 0 ? v.x : ((e >> 1) == 1 ? v.y : ((e >> 1) == 2 ? v.z : v.w));
         const uint16_t h = (e & 1) ? (uint16_t)(w >> 16) : (uint16_t)(w & 0xffffu);
@@ -117,53 +118,47 @@ template <> struct Store<DT_F16> {
 // ---------------------------------------------------------------------------------------
 // Q-stack pass: out_b[uoff + r] = sum_j Q[r, j] * w_b[j] for the stored rows r of a tile.
 // LPR lanes share one row: each lane streams 16-byte vectors of the row (coalesced across
-// the group), four loads in flight, multiply-adds against w held in LDS, then a butterfly
+// the group), UNR loads in flight, multiply-adds against w held in LDS, then a butterfly
 // reduction over the LPR lanes in FP64.  With FP32 accumulation each lane sums at most
-// n / (LPR V) * V <= n / LPR products in FP32 before the FP64 combine.
+// n / LPR products in FP32 before the FP64 combine.
 
-template <int DT, typename AT, int B, int LPR>
+template <int DT, typename AT, int B, int LPR, bool NT>
 __device__ __forceinline__ void pass_rows(const void *__restrict__ Q, int n, size_t ld, int row0,
                                           int nrows, const AT *__restrict__ w, int nw,
                                           double *const (&outs)[B], int uoff)
 {
     using T = Store<DT>;
     constexpr int V = T::V;
+    constexpr int ES = T::ES;
     constexpr int NG = PASS_BS / LPR;
     constexpr int STRIDE = LPR * V;
+    constexpr int UNR = 8;
     const int lane = threadIdx.x & (LPR - 1);
     const int grp = threadIdx.x / LPR;
     for (int r = row0 + grp; r < row0 + nrows; r += NG) {
-        const size_t base = (size_t)r * ld;
+        const size_t base = (size_t)r * ld * ES;
         AT acc[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) acc[b] = AT(0);
-        int col = lane * V;
-        for (; col + 3 * STRIDE < n; col += 4 * STRIDE) {
-            const typename T::vec_t v0 = T::ld(Q, base + col);
-            const typename T::vec_t v1 = T::ld(Q, base + col + STRIDE);
-            const typename T::vec_t v2 = T::ld(Q, base + col + 2 * STRIDE);
-            const typename T::vec_t v3 = T::ld(Q, base + col + 3 * STRIDE);
+        // batches of UNR independent 16-byte loads; the last batch is predicated per lane
+        for (int col = lane * V; col < n; col += UNR * STRIDE) {
+            u32x4 v[UNR];
 #pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const AT q0 = (AT)T::get(v0, e), q1 = (AT)T::get(v1, e);
-                const AT q2 = (AT)T::get(v2, e), q3 = (AT)T::get(v3, e);
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    const AT *wb = w + b * nw + col + e;
-                    acc[b] = fma(q0, wb[0], acc[b]);
-                    acc[b] = fma(q1, wb[STRIDE], acc[b]);
-                    acc[b] = fma(q2, wb[2 * STRIDE], acc[b]);
-                    acc[b] = fma(q3, wb[3 * STRIDE], acc[b]);
-                }
+            for (int u = 0; u < UNR; ++u) {
+                const int c = col + u * STRIDE;
+                v[u] = c < n ? ld16<NT>(Q, base + (size_t)c * ES) : u32x4{0u, 0u, 0u, 0u};
             }
-        }
-        for (; col < n; col += STRIDE) {
-            const typename T::vec_t v0 = T::ld(Q, base + col);
 #pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const AT q0 = (AT)T::get(v0, e);
+            for (int u = 0; u < UNR; ++u) {
+                const int c = col + u * STRIDE;
+                if (c < n) {
 #pragma unroll
-                for (int b = 0; b < B; ++b) acc[b] = fma(q0, w[b * nw + col + e], acc[b]);
+                    for (int e = 0; e < V; ++e) {
+                        const AT qv = (AT)T::get(v[u], e);
+#pragma unroll
+                        for (int b = 0; b < B; ++b) acc[b] = fma(qv, w[b * nw + c + e], acc[b]);
+                    }
+                }
             }
         }
         double s[B];
@@ -180,54 +175,84 @@ __device__ __forceinline__ void pass_rows(const void *__restrict__ Q, int n, siz
     }
 }
 
-template <int DT, typename AT, int B>
+template <int DT, typename AT, int B, bool NT = false>
 __device__ __forceinline__ void pass_rows_lpr(int lpr, const void *Q, int n, size_t ld, int row0,
                                               int nrows, const AT *w, int nw,
                                               double *const (&outs)[B], int uoff)
 {
-    if (lpr == 64) pass_rows<DT, AT, B, 64>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
-    else if (lpr == 32) pass_rows<DT, AT, B, 32>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
-    else pass_rows<DT, AT, B, 16>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
+    if (lpr == 64) pass_rows<DT, AT, B, 64, NT>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
+    else if (lpr == 32) pass_rows<DT, AT, B, 32, NT>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
+    else pass_rows<DT, AT, B, 16, NT>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
 }
 
-template <int DT, int B>
+// The pass kernel runs a persistent grid: block b streams the contiguous tile range
+// [b T / G, (b+1) T / G), so every block gets the same number of equal-byte tiles and the
+// grid finishes together; w is staged into LDS only when the tile's slot changes (tiles are
+// grouped by slot).
+template <int DT, int B, bool NT>
 __global__ void __launch_bounds__(PASS_BS) k_pass(Slot *__restrict__ slots,
-                                                  const Tile *__restrict__ tiles)
+                                                  const Tile *__restrict__ tiles, int ntiles)
 {
-    const Tile t = tiles[blockIdx.x];
-    Slot *S = slots + t.slot;
-    if (S->status != ST_RUNNING) return;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int n = S->n, nw = S->nw;
-    const int uoff = S->has_q0 ? 0 : n;
-    const size_t ld = (size_t)S->ld;
     using AT = typename Store<DT>::acc_t;
-    if (S->mode == MODE_ANCHOR) {
-        // direct pass at the iterate, accumulated in FP64 whatever the storage type
-        double *w = reinterpret_cast<double *>(smem);
-        const double *x = S->x;
-        for (int j = threadIdx.x; j < nw; j += PASS_BS) w[j] = j < n ? x[j] : 0.0;
-        __syncthreads();
-        double *const outs[1] = {S->Uc[0]};
-        pass_rows_lpr<DT, double, 1>(t.lpr, S->Q, n, ld, t.row0, t.nrows, w, nw, outs, uoff);
-    } else {
-        AT *w = reinterpret_cast<AT *>(smem);
-        const bool inc = S->incremental != 0;
-        const double *x = S->x;
-        double *outs[B];
+    const int G = gridDim.x;
+    const int t0 = (int)(((int64_t)blockIdx.x * ntiles) / G);
+    const int t1 = (int)(((int64_t)(blockIdx.x + 1) * ntiles) / G);
+    int cur = -1;
+    bool active = false, anchor = false, inc = false;
+    int n = 0, nw = 0, uoff = 0;
+    size_t ld = 0;
+    const void *Q = nullptr;
+    double *outs[B];
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
-            const double *xc = S->xc[b];
-            for (int j = threadIdx.x; j < nw; j += PASS_BS) {
-                double v = 0.0;
-                if (j < n) v = inc ? xc[j] - x[j] : xc[j];
-                w[b * nw + j] = (AT)v;
+    for (int b = 0; b < B; ++b) outs[b] = nullptr;
+    for (int ti = t0; ti < t1; ++ti) {
+        const Tile t = tiles[ti];
+        if (t.slot != cur) {
+            __syncthreads();   // every wave is done with the previous slot's w
+            cur = t.slot;
+            Slot *S = slots + cur;
+            active = S->status == ST_RUNNING;
+            if (active) {
+                anchor = S->mode == MODE_ANCHOR;
+                inc = S->incremental != 0;
+                n = S->n;
+                nw = S->nw;
+                uoff = S->has_q0 ? 0 : n;
+                ld = (size_t)S->ld;
+                Q = S->Q;
+                const double *x = S->x;
+                if (anchor) {
+                    double *w = reinterpret_cast<double *>(smem);
+                    for (int j = threadIdx.x; j < nw; j += PASS_BS) w[j] = j < n ? x[j] : 0.0;
+                    outs[0] = S->Uc[0];
+                } else {
+                    AT *w = reinterpret_cast<AT *>(smem);
+#pragma unroll
+                    for (int b = 0; b < B; ++b) {
+                        const double *xc = S->xc[b];
+                        for (int j = threadIdx.x; j < nw; j += PASS_BS) {
+                            double v = 0.0;
+                            if (j < n) v = inc ? xc[j] - x[j] : xc[j];
+                            w[b * nw + j] = (AT)v;
+                        }
+                        outs[b] = inc ? S->W[b] : S->Uc[b];
+                    }
+                }
             }
-            outs[b] = inc ? S->W[b] : S->Uc[b];
+            __syncthreads();
         }
-        __syncthreads();
-        double *const (&co)[B] = outs;
-        pass_rows_lpr<DT, AT, B>(t.lpr, S->Q, n, ld, t.row0, t.nrows, w, nw, co, uoff);
+        if (!active) continue;
+        if (anchor) {
+            // direct pass at the iterate, accumulated in FP64 whatever the storage type
+            double *const o1[1] = {outs[0]};
+            pass_rows_lpr<DT, double, 1, NT>(t.lpr, Q, n, ld, t.row0, t.nrows,
+                                             reinterpret_cast<const double *>(smem), nw, o1, uoff);
+        } else {
+            double *const (&co)[B] = outs;
+            pass_rows_lpr<DT, AT, B, NT>(t.lpr, Q, n, ld, t.row0, t.nrows,
+                                         reinterpret_cast<const AT *>(smem), nw, co, uoff);
+        }
     }
 }
 
@@ -1184,25 +1209,80 @@ hipError_t launch_gap_finish(hipStream_t s, int n, const double *grad, const dou
 // ---------------------------------------------------------------------------------------
 // launch wrappers
 
+size_t pass_lds_bytes(int B, int dtype, int max_nw)
+{
+    const size_t accsz = dtype == DT_F64 ? sizeof(double) : sizeof(float);
+    size_t lds = (size_t)max_nw * sizeof(double);
+    const size_t trial = (size_t)B * max_nw * accsz;
+    return trial > lds ? trial : lds;
+}
+
+template <int DT, int B>
+static void launch_pass_dt(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles, size_t lds,
+                           int grid, int nt)
+{
+    if (nt) k_pass<DT, B, true><<<grid, PASS_BS, lds, s>>>(slots, tiles, ntiles);
+    else k_pass<DT, B, false><<<grid, PASS_BS, lds, s>>>(slots, tiles, ntiles);
+}
+
+template <int B>
+static void launch_pass_b(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles, int dtype,
+                          int max_nw, int grid, int nt)
+{
+    const size_t lds = pass_lds_bytes(B, dtype, max_nw);
+    if (grid > ntiles) grid = ntiles;
+    if (grid < 1) grid = 1;
+    switch (dtype) {
+    case DT_F64: launch_pass_dt<DT_F64, B>(s, slots, tiles, ntiles, lds, grid, nt); break;
+    case DT_F32: launch_pass_dt<DT_F32, B>(s, slots, tiles, ntiles, lds, grid, nt); break;
+    case DT_BF16: launch_pass_dt<DT_BF16, B>(s, slots, tiles, ntiles, lds, grid, nt); break;
+    default: launch_pass_dt<DT_F16, B>(s, slots, tiles, ntiles, lds, grid, nt); break;
+    }
+}
+
+template <int DT, int B>
+static int occ_dt(size_t lds)
+{
+    int a = 0, b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_pass<DT, B, false>, PASS_BS, lds) != hipSuccess) a = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_pass<DT, B, true>, PASS_BS, lds) != hipSuccess) b = 1;
+    return a < b ? a : b;
+}
+
+template <int B>
+static int occ_b(int dtype, size_t lds)
+{
+    switch (dtype) {
+    case DT_F64: return occ_dt<DT_F64, B>(lds);
+    case DT_F32: return occ_dt<DT_F32, B>(lds);
+    case DT_BF16: return occ_dt<DT_BF16, B>(lds);
+    default: return occ_dt<DT_F16, B>(lds);
+    }
+}
+
+int pass_blocks_per_cu(int B, int dtype, int max_nw)
+{
+    const size_t lds = pass_lds_bytes(B, dtype, max_nw);
+    int o = 1;
+    switch (B) {
+    case 1: o = occ_b<1>(dtype, lds); break;
+    case 2: o = occ_b<2>(dtype, lds); break;
+    case 3: o = occ_b<3>(dtype, lds); break;
+    default: o = occ_b<4>(dtype, lds); break;
+    }
+    return o < 1 ? 1 : o;
+}
+
 template <int B>
 static hipError_t group_b(hipStream_t s, Slot *slots, int nslots, const Tile *tiles, int ntiles,
                           int dtype, int max_nblk_step, int max_ny, int max_nw, int max_epi,
-                          hipEvent_t ev0, hipEvent_t ev1)
+                          int pass_grid, int nt, hipEvent_t ev0, hipEvent_t ev1)
 {
     const size_t step_lds = (size_t)(B + 1) * (size_t)(max_ny > 0 ? max_ny : 1) * sizeof(double);
     k_step<B><<<dim3(max_nblk_step, nslots), STEP_BS, step_lds, s>>>(slots);
-    const size_t accsz = dtype == DT_F64 ? sizeof(double) : sizeof(float);
-    size_t pass_lds = (size_t)max_nw * sizeof(double);
-    const size_t trial_lds = (size_t)B * max_nw * accsz;
-    if (trial_lds > pass_lds) pass_lds = trial_lds;
-    if (ev0) hipEventRecord(ev0, s);
-    switch (dtype) {
-    case DT_F64: k_pass<DT_F64, B><<<ntiles, PASS_BS, pass_lds, s>>>(slots, tiles); break;
-    case DT_F32: k_pass<DT_F32, B><<<ntiles, PASS_BS, pass_lds, s>>>(slots, tiles); break;
-    case DT_BF16: k_pass<DT_BF16, B><<<ntiles, PASS_BS, pass_lds, s>>>(slots, tiles); break;
-    default: k_pass<DT_F16, B><<<ntiles, PASS_BS, pass_lds, s>>>(slots, tiles); break;
-    }
-    if (ev1) hipEventRecord(ev1, s);
+    if (ev0) (void)hipEventRecord(ev0, s);
+    launch_pass_b<B>(s, slots, tiles, ntiles, dtype, max_nw, pass_grid, nt);
+    if (ev1) (void)hipEventRecord(ev1, s);
     k_epi<B><<<dim3(max_epi, nslots), STEP_BS, 0, s>>>(slots);
     k_ctrl<B><<<nslots, STEP_BS, 0, s>>>(slots);
     return hipGetLastError();
@@ -1210,42 +1290,26 @@ static hipError_t group_b(hipStream_t s, Slot *slots, int nslots, const Tile *ti
 
 hipError_t launch_group(hipStream_t s, Slot *slots, int nslots, const Tile *tiles, int ntiles,
                         int B, int dtype, int max_nblk_step, int max_ny, int max_nw,
-                        int max_epi, hipEvent_t ev0, hipEvent_t ev1)
+                        int max_epi, int pass_grid, int nt, hipEvent_t ev0, hipEvent_t ev1)
 {
     switch (B) {
-    case 1: return group_b<1>(s, slots, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, ev0, ev1);
-    case 2: return group_b<2>(s, slots, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, ev0, ev1);
-    case 3: return group_b<3>(s, slots, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, ev0, ev1);
-    default: return group_b<4>(s, slots, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, ev0, ev1);
+    case 1: return group_b<1>(s, slots, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
+    case 2: return group_b<2>(s, slots, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
+    case 3: return group_b<3>(s, slots, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
+    default: return group_b<4>(s, slots, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
     }
-}
-
-template <int B>
-static hipError_t pass_only_b(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles, int dtype,
-                              int max_nw)
-{
-    const size_t accsz = dtype == DT_F64 ? sizeof(double) : sizeof(float);
-    size_t pass_lds = (size_t)max_nw * sizeof(double);
-    const size_t trial_lds = (size_t)B * max_nw * accsz;
-    if (trial_lds > pass_lds) pass_lds = trial_lds;
-    switch (dtype) {
-    case DT_F64: k_pass<DT_F64, B><<<ntiles, PASS_BS, pass_lds, s>>>(slots, tiles); break;
-    case DT_F32: k_pass<DT_F32, B><<<ntiles, PASS_BS, pass_lds, s>>>(slots, tiles); break;
-    case DT_BF16: k_pass<DT_BF16, B><<<ntiles, PASS_BS, pass_lds, s>>>(slots, tiles); break;
-    default: k_pass<DT_F16, B><<<ntiles, PASS_BS, pass_lds, s>>>(slots, tiles); break;
-    }
-    return hipGetLastError();
 }
 
 hipError_t launch_pass_only(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles, int B,
-                            int dtype, int max_nw)
+                            int dtype, int max_nw, int pass_grid, int nt)
 {
     switch (B) {
-    case 1: return pass_only_b<1>(s, slots, tiles, ntiles, dtype, max_nw);
-    case 2: return pass_only_b<2>(s, slots, tiles, ntiles, dtype, max_nw);
-    case 3: return pass_only_b<3>(s, slots, tiles, ntiles, dtype, max_nw);
-    default: return pass_only_b<4>(s, slots, tiles, ntiles, dtype, max_nw);
+    case 1: launch_pass_b<1>(s, slots, tiles, ntiles, dtype, max_nw, pass_grid, nt); break;
+    case 2: launch_pass_b<2>(s, slots, tiles, ntiles, dtype, max_nw, pass_grid, nt); break;
+    case 3: launch_pass_b<3>(s, slots, tiles, ntiles, dtype, max_nw, pass_grid, nt); break;
+    default: launch_pass_b<4>(s, slots, tiles, ntiles, dtype, max_nw, pass_grid, nt); break;
     }
+    return hipGetLastError();
 }
 
 hipError_t launch_epi_anchor(hipStream_t s, Slot *slots, int nslots, int max_epi)
@@ -1317,8 +1381,12 @@ hipError_t launch_restart_decision(hipStream_t s, Slot *slot, double gap, int fi
 template <int DT, int B>
 static hipError_t set_attr_one(int max_lds)
 {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass<DT, B>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass<DT, B, false>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass<DT, B, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    return e;
 }
 
 hipError_t prepare_kernels(int max_lds)

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -51,6 +52,7 @@ int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 bool prepared = false;
 int prepared_dev = -1;
 int max_lds = 64 * 1024;   // dynamic LDS a workgroup may request on this device
+int num_cus = 0;           // compute units of the device
 
 qcqp_status ensure_prepared()
 {
@@ -61,6 +63,7 @@ qcqp_status ensure_prepared()
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess || v <= 0)
             HIPCHK(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
         max_lds = v;
+        HIPCHK(hipDeviceGetAttribute(&num_cus, hipDeviceAttributeMultiprocessorCount, dev));
         HIPCHK(prepare_kernels(v));
         prepared = true;
         prepared_dev = dev;
@@ -73,20 +76,31 @@ double now_s()
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// lanes per row and rows per tile for a stack of `rows` rows of n elements of type dt
+constexpr double CACHE_RESIDENT_BYTES = 256e6;   // Infinity Cache (MALL) of one MI355X
+
+// Lanes per row and rows per tile for a stack of `rows` rows of n elements of type dt.
+// A lane should issue at least one full batch of 8 loads per row, so short rows share a wave
+// (32 or 16 lanes per row).  Tiles hold ~128 KB of the stack (a multiple of the rows one block
+// covers at once), and there are at least ~1024 of them when the stack allows it, so that the
+// persistent grid splits into equal contiguous ranges.
 void tile_shape(int64_t n, int dt, int64_t rows, int *lpr, int *rows_per_tile)
 {
     const int64_t vpr = (n + vec_width(dt) - 1) / vec_width(dt);   // 16-byte vectors per row
     int l = 16;
-    if (vpr >= 4 * 64) l = 64;
-    else if (vpr >= 4 * 32) l = 32;
+    if (vpr >= 8 * 64) l = 64;
+    else if (vpr >= 8 * 32) l = 32;
     const int ng = PASS_BS / l;
-    // aim for >= ~1024 tiles when the stack is large, never more than 128 rows per tile
-    int64_t r = (rows + 1023) / 1024;
+    const int64_t row_bytes = n * elem_size(dt);
+    int64_t r = std::max<int64_t>(1, (128 * 1024) / std::max<int64_t>(row_bytes, 1));
+    r = std::min<int64_t>(r, std::max<int64_t>(1, rows / 1024));
     r = round_up(std::max<int64_t>(r, ng), ng);
-    r = std::min<int64_t>(r, 128);
     *lpr = l;
     *rows_per_tile = (int)r;
+}
+
+int pass_grid_for(int B, int dtype, int max_nw)
+{
+    return std::max(1, num_cus) * pass_blocks_per_cu(B, dtype, max_nw);
 }
 
 }  // namespace
@@ -108,6 +122,7 @@ struct qcqp_handle {
     Tile *dtiles = nullptr;
     std::vector<Tile> tiles;  // slot field 0
     int nblk_step = 1;
+    int pass_grid = 1, nt = 0;
     double *d_ueval = nullptr, *d_geval = nullptr, *d_grad = nullptr, *d_kpart = nullptr,
            *d_out6 = nullptr, *d_xe = nullptr, *d_ye = nullptr;
     Slot *h_poll = nullptr;   // pinned
@@ -130,6 +145,7 @@ struct qcqp_batch {
     Tile *dtiles = nullptr;
     size_t tiles_cap = 0;
     int ntiles = 0, max_nblk = 1, max_ny = 1, max_nw = 2, max_epi = 1;
+    int pass_grid = 1, nt = 0;
     bool dirty = true;
 };
 
@@ -394,6 +410,9 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
         h->tiles.push_back(Tile{0, (int32_t)r0, (int32_t)std::min<int64_t>(rpt, rows - r0), lpr});
     const size_t tile_off = total;
     total += round_up((int64_t)std::max<size_t>(h->tiles.size(), 1) * sizeof(Tile), 256);
+    h->pass_grid = pass_grid_for(B, h->dtype, (int)h->nw);
+    h->nt = (double)h->q_bytes > CACHE_RESIDENT_BYTES ? 1 : 0;
+    if (const char *ev = std::getenv("QCQP_PASS_NT")) h->nt = std::atoi(ev) ? 1 : 0;   // tuning override
     if (hipMalloc(&h->arena, total) != hipSuccess) {
         free_handle_memory(h);
         delete h;
@@ -587,8 +606,8 @@ qcqp_status qcqp_solve(qcqp_handle *h, const double *x0, const double *y0, doubl
         for (int64_t g = 0; g < poll; ++g) {
             hipError_t e = launch_group(h->stream, h->dslot, 1, h->dtiles, ntiles, h->B, h->dtype,
                                         h->nblk_step, (int)std::max<int64_t>(h->ny, 1), (int)h->nw,
-                                        (int)(h->m + 1 + h->p), timing ? ev[2 * g] : nullptr,
-                                        timing ? ev[2 * g + 1] : nullptr);
+                                        (int)(h->m + 1 + h->p), h->pass_grid, h->nt,
+                                        timing ? ev[2 * g] : nullptr, timing ? ev[2 * g + 1] : nullptr);
             if (e != hipSuccess) { result = fail(QCQP_E_DEVICE, "launch: %s", hipGetErrorString(e)); break; }
         }
         if (result) break;
@@ -639,7 +658,7 @@ static qcqp_status eval_loaded_point(qcqp_handle *h)
     S.Gc[0] = h->d_geval;
     HIPCHK(hipMemsetAsync(h->d_ueval, 0, (h->m + 1) * h->n * 8, h->stream));
     HIPCHK(hipMemcpyAsync(h->dslot_eval, &S, sizeof(Slot), hipMemcpyHostToDevice, h->stream));
-    HIPCHK(launch_pass_only(h->stream, h->dslot_eval, h->dtiles, (int)h->tiles.size(), h->B, h->dtype, (int)h->nw));
+    HIPCHK(launch_pass_only(h->stream, h->dslot_eval, h->dtiles, (int)h->tiles.size(), h->B, h->dtype, (int)h->nw, h->pass_grid, h->nt));
     HIPCHK(launch_epi_anchor(h->stream, h->dslot_eval, 1, (int)(h->m + 1 + h->p)));
     return QCQP_OK;
 }
@@ -777,10 +796,10 @@ qcqp_status qcqp_time_pass(qcqp_handle *h, int64_t reps, double *avg_seconds)
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    HIPCHK(launch_pass_only(h->stream, h->dslot, h->dtiles, (int)h->tiles.size(), h->B, h->dtype, (int)h->nw));
+    HIPCHK(launch_pass_only(h->stream, h->dslot, h->dtiles, (int)h->tiles.size(), h->B, h->dtype, (int)h->nw, h->pass_grid, h->nt));
     HIPCHK(hipEventRecord(e0, h->stream));
     for (int64_t r = 0; r < reps; ++r)
-        HIPCHK(launch_pass_only(h->stream, h->dslot, h->dtiles, (int)h->tiles.size(), h->B, h->dtype, (int)h->nw));
+        HIPCHK(launch_pass_only(h->stream, h->dslot, h->dtiles, (int)h->tiles.size(), h->B, h->dtype, (int)h->nw, h->pass_grid, h->nt));
     HIPCHK(hipEventRecord(e1, h->stream));
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -904,21 +923,14 @@ static qcqp_status rebuild_tiles(qcqp_batch *bt)
         bt->max_nw = std::max<int>(bt->max_nw, (int)h->nw);
         bt->max_epi = std::max<int>(bt->max_epi, (int)(h->m + 1 + h->p));
     }
-    // interleave tiles of different slots so every slot's rows spread over all CUs
-    std::vector<Tile> mixed;
-    mixed.reserve(all.size());
-    {
-        std::vector<std::vector<Tile>> per(bt->max_slots);
-        for (auto &t : all) per[t.slot].push_back(t);
-        size_t idx = 0;
-        bool any = true;
-        while (any) {
-            any = false;
-            for (auto &v : per)
-                if (idx < v.size()) { mixed.push_back(v[idx]); any = true; }
-            ++idx;
-        }
-    }
+    // tiles stay grouped by slot: the persistent pass grid gives each block a contiguous
+    // range, so a block restages the iterate only at slot boundaries
+    std::vector<Tile> &mixed = all;
+    size_t resident = 0;
+    for (int64_t s2 = 0; s2 < bt->max_slots; ++s2)
+        if (bt->handles[s2] && !bt->finished[s2]) resident += bt->handles[s2]->q_bytes;
+    bt->nt = (double)resident > CACHE_RESIDENT_BYTES ? 1 : 0;
+    if (const char *ev = std::getenv("QCQP_PASS_NT")) bt->nt = std::atoi(ev) ? 1 : 0;
     if (mixed.size() > bt->tiles_cap) {
         if (bt->dtiles) (void)hipFree(bt->dtiles);
         bt->dtiles = nullptr;
@@ -930,6 +942,7 @@ static qcqp_status rebuild_tiles(qcqp_batch *bt)
         HIPCHK(hipMemcpyAsync(bt->dtiles, mixed.data(), mixed.size() * sizeof(Tile),
                               hipMemcpyHostToDevice, bt->stream));
     bt->ntiles = (int)mixed.size();
+    bt->pass_grid = pass_grid_for(bt->opt.spec_trials, (int)bt->opt.storage, bt->max_nw);
     bt->dirty = false;
     return QCQP_OK;
 }
@@ -944,7 +957,8 @@ qcqp_status qcqp_batch_step(qcqp_batch *bt, int64_t groups)
         for (int64_t g = 0; g < groups; ++g) {
             hipError_t e = launch_group(bt->stream, bt->dslots, (int)bt->max_slots, bt->dtiles, bt->ntiles,
                                         bt->opt.spec_trials, (int)bt->opt.storage, bt->max_nblk,
-                                        bt->max_ny, bt->max_nw, bt->max_epi, nullptr, nullptr);
+                                        bt->max_ny, bt->max_nw, bt->max_epi, bt->pass_grid, bt->nt,
+                                        nullptr, nullptr);
             if (e != hipSuccess) return fail(QCQP_E_DEVICE, "launch: %s", hipGetErrorString(e));
         }
     }
