@@ -200,6 +200,13 @@ qcqp_status qcqp_batch_fetch(qcqp_batch *bt, int64_t slot, double *x_out, double
 /* Number of running slots and resident bytes. */
 qcqp_status qcqp_batch_stats(qcqp_batch *bt, int64_t *running, size_t *resident_bytes);
 
+/* Pass accounting of the batch since creation: summed pass-kernel seconds (only with
+ * options.timing), algorithmic bytes streamed ((m + has_q0) n^2 sizeof(storage) per slot pass,
+ * counted from the device pass counters) and the number of slot passes.  Any pointer may be
+ * NULL. */
+qcqp_status qcqp_batch_pass_stats(qcqp_batch *bt, double *pass_seconds, double *pass_bytes,
+                                  int64_t *passes);
+
 /* Destroy the batch; handles still admitted are destroyed with it. */
 qcqp_status qcqp_batch_destroy(qcqp_batch *bt);
 

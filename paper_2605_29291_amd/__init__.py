@@ -253,6 +253,11 @@ class Batch:
         abi.check(load().qcqp_batch_stats(self._b, C.byref(r), C.byref(b)))
         return dict(running=r.value, resident_bytes=b.value)
 
+    def pass_stats(self):
+        sec, byt, n = C.c_double(), C.c_double(), C.c_int64()
+        abi.check(load().qcqp_batch_pass_stats(self._b, C.byref(sec), C.byref(byt), C.byref(n)))
+        return dict(pass_seconds=sec.value, pass_bytes=byt.value, passes=n.value)
+
     def close(self):
         if getattr(self, "_b", None) is not None:
             load().qcqp_batch_destroy(self._b)

@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libqcqp_hip.so")
+# QCQP_LIB may name another build of the same library (A/B measurements of kernel variants)
+LIB_PATH = os.environ.get("QCQP_LIB") or os.path.join(_HERE, "libqcqp_hip.so")
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_NOT_CONVERGED, E_NUMERICAL, E_NO_ROOM = range(7)
 STATUS_NAMES = {0: "ok", 1: "invalid", 2: "nomem", 3: "device", 4: "not_converged",
@@ -66,8 +67,8 @@ class Info(C.Structure):
 SYMBOLS = ["qcqp_options_default", "qcqp_last_error", "qcqp_create", "qcqp_solve",
            "qcqp_eval_operator", "qcqp_eval_kkt", "qcqp_eval_gap", "qcqp_destroy",
            "qcqp_batch_create", "qcqp_batch_admit", "qcqp_batch_step", "qcqp_batch_poll",
-           "qcqp_batch_fetch", "qcqp_batch_stats", "qcqp_batch_destroy", "qcqp_handle_bytes",
-           "qcqp_time_pass"]
+           "qcqp_batch_fetch", "qcqp_batch_stats", "qcqp_batch_pass_stats", "qcqp_batch_destroy",
+           "qcqp_handle_bytes", "qcqp_time_pass"]
 
 _LIB = None
 
@@ -102,6 +103,7 @@ def load(path: str = LIB_PATH):
     L.qcqp_batch_poll.argtypes = [vp, vp, i64, P(i64)]
     L.qcqp_batch_fetch.argtypes = [vp, i64, vp, vp, P(Info), P(vp)]
     L.qcqp_batch_stats.argtypes = [vp, P(i64), P(C.c_size_t)]
+    L.qcqp_batch_pass_stats.argtypes = [vp, P(C.c_double), P(C.c_double), P(i64)]
     L.qcqp_batch_destroy.argtypes = [vp]
     L.qcqp_handle_bytes.argtypes = [vp]
     L.qcqp_handle_bytes.restype = C.c_size_t

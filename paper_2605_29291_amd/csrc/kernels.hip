@@ -122,7 +122,28 @@ template <> struct Store<DT_F16> {
 // reduction over the LPR lanes in FP64.  With FP32 accumulation each lane sums at most
 // n / LPR products in FP32 before the FP64 combine.
 
-template <int DT, typename AT, int B, int LPR, bool NT>
+// Rows per group step (R) and 16-byte loads per batch (UNR) for the trial passes: R rows share
+// each w value read from LDS, which cuts LDS traffic by R for the 16/32-bit types (whose w
+// reads are 2-4 LDS bytes per streamed byte).
+#ifndef QCQP_PASS_R16
+#define QCQP_PASS_R16 4
+#endif
+#ifndef QCQP_PASS_UNR16
+#define QCQP_PASS_UNR16 4
+#endif
+#ifndef QCQP_PASS_R64
+#define QCQP_PASS_R64 1
+#endif
+#ifndef QCQP_PASS_UNR64
+#define QCQP_PASS_UNR64 8
+#endif
+
+template <int DT> struct PassShape {
+    static constexpr int R = DT == DT_F64 ? QCQP_PASS_R64 : QCQP_PASS_R16;
+    static constexpr int UNR = DT == DT_F64 ? QCQP_PASS_UNR64 : QCQP_PASS_UNR16;
+};
+
+template <int DT, typename AT, int B, int LPR, bool NT, int R, int UNR>
 __device__ __forceinline__ void pass_rows(const void *__restrict__ Q, int n, size_t ld, int row0,
                                           int nrows, const AT *__restrict__ w, int nw,
                                           double *const (&outs)[B], int uoff)
@@ -132,21 +153,32 @@ __device__ __forceinline__ void pass_rows(const void *__restrict__ Q, int n, siz
     constexpr int ES = T::ES;
     constexpr int NG = PASS_BS / LPR;
     constexpr int STRIDE = LPR * V;
-    constexpr int UNR = 8;
     const int lane = threadIdx.x & (LPR - 1);
     const int grp = threadIdx.x / LPR;
-    for (int r = row0 + grp; r < row0 + nrows; r += NG) {
-        const size_t base = (size_t)r * ld * ES;
-        AT acc[B];
+    const int rend = row0 + nrows;
+    for (int r = row0 + grp * R; r < rend; r += NG * R) {
+        size_t base[R];
+        bool live[R];
 #pragma unroll
-        for (int b = 0; b < B; ++b) acc[b] = AT(0);
-        // batches of UNR independent 16-byte loads; the last batch is predicated per lane
+        for (int i = 0; i < R; ++i) {
+            live[i] = r + i < rend;
+            base[i] = (size_t)(live[i] ? r + i : r) * ld * ES;
+        }
+        AT acc[R][B];
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+            for (int b = 0; b < B; ++b) acc[i][b] = AT(0);
+        // batches of R x UNR independent 16-byte loads; the last batch is predicated per lane
         for (int col = lane * V; col < n; col += UNR * STRIDE) {
-            u32x4 v[UNR];
+            u32x4 v[R][UNR];
 #pragma unroll
             for (int u = 0; u < UNR; ++u) {
                 const int c = col + u * STRIDE;
-                v[u] = c < n ? ld16<NT>(Q, base + (size_t)c * ES) : u32x4{0u, 0u, 0u, 0u};
+#pragma unroll
+                for (int i = 0; i < R; ++i)
+                    v[i][u] = (c < n && live[i]) ? ld16<NT>(Q, base[i] + (size_t)c * ES)
+                                                 : u32x4{0u, 0u, 0u, 0u};
             }
 #pragma unroll
             for (int u = 0; u < UNR; ++u) {
@@ -154,35 +186,44 @@ __device__ __forceinline__ void pass_rows(const void *__restrict__ Q, int n, siz
                 if (c < n) {
 #pragma unroll
                     for (int e = 0; e < V; ++e) {
-                        const AT qv = (AT)T::get(v[u], e);
+                        AT wv[B];
 #pragma unroll
-                        for (int b = 0; b < B; ++b) acc[b] = fma(qv, w[b * nw + c + e], acc[b]);
+                        for (int b = 0; b < B; ++b) wv[b] = w[b * nw + c + e];
+#pragma unroll
+                        for (int i = 0; i < R; ++i) {
+                            const AT qv = (AT)T::get(v[i][u], e);
+#pragma unroll
+                            for (int b = 0; b < B; ++b) acc[i][b] = fma(qv, wv[b], acc[i][b]);
+                        }
                     }
                 }
             }
         }
-        double s[B];
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
-            s[b] = (double)acc[b];
+        for (int i = 0; i < R; ++i) {
+            double sv[B];
 #pragma unroll
-            for (int off = LPR / 2; off > 0; off >>= 1) s[b] += __shfl_xor(s[b], off, LPR);
-        }
-        if (lane == 0) {
+            for (int b = 0; b < B; ++b) {
+                sv[b] = (double)acc[i][b];
 #pragma unroll
-            for (int b = 0; b < B; ++b) outs[b][uoff + r] = s[b];
+                for (int off = LPR / 2; off > 0; off >>= 1) sv[b] += __shfl_xor(sv[b], off, LPR);
+            }
+            if (lane == 0 && live[i]) {
+#pragma unroll
+                for (int b = 0; b < B; ++b) outs[b][uoff + r + i] = sv[b];
+            }
         }
     }
 }
 
-template <int DT, typename AT, int B, bool NT = false>
+template <int DT, typename AT, int B, bool NT = false, int R = 1, int UNR = 8>
 __device__ __forceinline__ void pass_rows_lpr(int lpr, const void *Q, int n, size_t ld, int row0,
                                               int nrows, const AT *w, int nw,
                                               double *const (&outs)[B], int uoff)
 {
-    if (lpr == 64) pass_rows<DT, AT, B, 64, NT>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
-    else if (lpr == 32) pass_rows<DT, AT, B, 32, NT>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
-    else pass_rows<DT, AT, B, 16, NT>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
+    if (lpr == 64) pass_rows<DT, AT, B, 64, NT, R, UNR>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
+    else if (lpr == 32) pass_rows<DT, AT, B, 32, NT, R, UNR>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
+    else pass_rows<DT, AT, B, 16, NT, R, UNR>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
 }
 
 // The pass kernel runs a persistent grid: block b streams the contiguous tile range
@@ -250,8 +291,8 @@ __global__ void __launch_bounds__(PASS_BS) k_pass(Slot *__restrict__ slots,
                                              reinterpret_cast<const double *>(smem), nw, o1, uoff);
         } else {
             double *const (&co)[B] = outs;
-            pass_rows_lpr<DT, AT, B, NT>(t.lpr, Q, n, ld, t.row0, t.nrows,
-                                         reinterpret_cast<const AT *>(smem), nw, co, uoff);
+            pass_rows_lpr<DT, AT, B, NT, PassShape<DT>::R, PassShape<DT>::UNR>(
+                t.lpr, Q, n, ld, t.row0, t.nrows, reinterpret_cast<const AT *>(smem), nw, co, uoff);
         }
     }
 }
@@ -282,9 +323,10 @@ __global__ void __launch_bounds__(PASS_BS) k_matvec1(const void *__restrict__ Q,
 // Also the KKT partials of the iterate (x^k, y^k).
 
 template <int B>
-__global__ void __launch_bounds__(STEP_BS) k_step(Slot *__restrict__ slots)
+__global__ void __launch_bounds__(STEP_BS) k_step(Slot *__restrict__ slots,
+                                                  const int *__restrict__ live)
 {
-    Slot *S = slots + blockIdx.y;
+    Slot *S = slots + live[blockIdx.y];
     if (S->status != ST_RUNNING || S->mode != MODE_TRIAL) return;
     if ((int)blockIdx.x >= S->nblk_step) return;
     const int n = S->n, m = S->m, p = S->p, ny = S->ny;
@@ -372,9 +414,10 @@ __global__ void __launch_bounds__(STEP_BS) k_step(Slot *__restrict__ slots)
 // G arrays are laid out (Ax-b [p], g [m], f [1]).
 
 template <int B>
-__global__ void __launch_bounds__(STEP_BS) k_epi(Slot *__restrict__ slots)
+__global__ void __launch_bounds__(STEP_BS) k_epi(Slot *__restrict__ slots,
+                                                 const int *__restrict__ live)
 {
-    Slot *S = slots + blockIdx.y;
+    Slot *S = slots + live[blockIdx.y];
     if (S->status != ST_RUNNING) return;
     const int n = S->n, m = S->m, p = S->p, ny = S->ny;
     const int row = blockIdx.x;
@@ -532,14 +575,18 @@ __device__ void restart_epoch(Slot *S, int rs)
         S->T = 0.0;
         S->ke = 0;
         S->restarts += 1;
-        if (anchor) S->mode = MODE_ANCHOR;
+        if (anchor) {
+            S->mode = MODE_ANCHOR;
+            S->anchor_keep_gp = 0;
+        }
     }
 }
 
 template <int B>
-__global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots)
+__global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
+                                                  const int *__restrict__ live)
 {
-    Slot *S = slots + blockIdx.x;
+    Slot *S = slots + live[blockIdx.x];
     const int status = S->status;
     const int mode = S->mode;
     __syncthreads();
@@ -559,11 +606,15 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots)
         __syncthreads();
         const double *G = S->G;
         double *Gp = S->Gp;
-        for (int l = tid; l <= ny; l += STEP_BS) Gp[l] = G[l];
+        if (!S->anchor_keep_gp)
+            for (int l = tid; l <= ny; l += STEP_BS) Gp[l] = G[l];
+        __syncthreads();
         if (tid == 0) {
             S->f = G[ny];
             S->mode = MODE_TRIAL;
             S->passes += 1;
+            S->fresh = 1;
+            S->anchor_keep_gp = 0;
         }
         return;
     }
@@ -649,18 +700,25 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots)
         S->kkt[3] = rel_comp;
         S->maxviol = kv[2];
         int dec = -1;
+        S->passes += 1;                 // this group's pass was streamed, whatever follows
         if (isnan(rk)) {
             S->status = ST_NUMERICAL;
             dec = -2;
         } else if (rk <= S->tol) {
-            S->status = ST_CONVERGED;
+            if (S->fresh) {
+                S->status = ST_CONVERGED;
+            } else {
+                // the cached U carries FP32 / incremental rounding: confirm the stop test on
+                // exact FP64 values first (refresh anchor, the epoch continues)
+                S->mode = MODE_ANCHOR;
+                S->anchor_keep_gp = 1;
+            }
             dec = -2;
         } else if (S->k >= S->max_iter) {
             S->status = ST_MAX_ITER;
             dec = -2;
         }
         if (dec == -1) {
-            S->passes += 1;
             double t = S->tau;
             const double gam = S->gam, sp = S->sig_prev, eta = S->eta;
             for (int b = 0; b < B; ++b) {
@@ -738,6 +796,7 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots)
         S->G = S->Gc[dec];
         S->Gc[dec] = gold;
         S->f = S->G[ny];
+        S->fresh = (S->dtype == DT_F64 && !S->incremental) ? 1 : 0;
         S->alpha_k = S->c_alpha / sig;
         S->sig_prev = sig;
         S->tau_prev = t;
@@ -1274,29 +1333,29 @@ int pass_blocks_per_cu(int B, int dtype, int max_nw)
 }
 
 template <int B>
-static hipError_t group_b(hipStream_t s, Slot *slots, int nslots, const Tile *tiles, int ntiles,
+static hipError_t group_b(hipStream_t s, Slot *slots, const int *live, int nslots, const Tile *tiles, int ntiles,
                           int dtype, int max_nblk_step, int max_ny, int max_nw, int max_epi,
                           int pass_grid, int nt, hipEvent_t ev0, hipEvent_t ev1)
 {
     const size_t step_lds = (size_t)(B + 1) * (size_t)(max_ny > 0 ? max_ny : 1) * sizeof(double);
-    k_step<B><<<dim3(max_nblk_step, nslots), STEP_BS, step_lds, s>>>(slots);
+    k_step<B><<<dim3(max_nblk_step, nslots), STEP_BS, step_lds, s>>>(slots, live);
     if (ev0) (void)hipEventRecord(ev0, s);
     launch_pass_b<B>(s, slots, tiles, ntiles, dtype, max_nw, pass_grid, nt);
     if (ev1) (void)hipEventRecord(ev1, s);
-    k_epi<B><<<dim3(max_epi, nslots), STEP_BS, 0, s>>>(slots);
-    k_ctrl<B><<<nslots, STEP_BS, 0, s>>>(slots);
+    k_epi<B><<<dim3(max_epi, nslots), STEP_BS, 0, s>>>(slots, live);
+    k_ctrl<B><<<nslots, STEP_BS, 0, s>>>(slots, live);
     return hipGetLastError();
 }
 
-hipError_t launch_group(hipStream_t s, Slot *slots, int nslots, const Tile *tiles, int ntiles,
-                        int B, int dtype, int max_nblk_step, int max_ny, int max_nw,
+hipError_t launch_group(hipStream_t s, Slot *slots, const int *live, int nslots, const Tile *tiles,
+                        int ntiles, int B, int dtype, int max_nblk_step, int max_ny, int max_nw,
                         int max_epi, int pass_grid, int nt, hipEvent_t ev0, hipEvent_t ev1)
 {
     switch (B) {
-    case 1: return group_b<1>(s, slots, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
-    case 2: return group_b<2>(s, slots, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
-    case 3: return group_b<3>(s, slots, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
-    default: return group_b<4>(s, slots, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
+    case 1: return group_b<1>(s, slots, live, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
+    case 2: return group_b<2>(s, slots, live, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
+    case 3: return group_b<3>(s, slots, live, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
+    default: return group_b<4>(s, slots, live, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
     }
 }
 
@@ -1312,10 +1371,10 @@ hipError_t launch_pass_only(hipStream_t s, Slot *slots, const Tile *tiles, int n
     return hipGetLastError();
 }
 
-hipError_t launch_epi_anchor(hipStream_t s, Slot *slots, int nslots, int max_epi)
+hipError_t launch_epi_anchor(hipStream_t s, Slot *slots, const int *live, int nslots, int max_epi)
 {
     // k_epi<1> handles the anchor mode for any B (it only touches candidate 0)
-    k_epi<1><<<dim3(max_epi, nslots), STEP_BS, 0, s>>>(slots);
+    k_epi<1><<<dim3(max_epi, nslots), STEP_BS, 0, s>>>(slots, live);
     return hipGetLastError();
 }
 

@@ -67,6 +67,8 @@ struct Slot {
     double Gref, last_gap;
     int64_t k, ke, trials, passes, restarts, gap_evals, iter_trials;
     int32_t status, mode;
+    int32_t fresh;            // 1 when U and G are exact FP64 values at x (no incremental drift)
+    int32_t anchor_keep_gp;   // 1: the pending anchor refreshes U/G only (no epoch start)
 };
 
 struct Tile {
@@ -77,15 +79,16 @@ struct Tile {
 };
 
 // ---- launch wrappers (kernels.hip) ----
-hipError_t launch_group(hipStream_t s, Slot *slots, int nslots, const Tile *tiles, int ntiles,
-                        int B, int dtype, int max_nblk_step, int max_ny, int max_nw,
+// one trial group for the slots listed in live[0..nslots)
+hipError_t launch_group(hipStream_t s, Slot *slots, const int *live, int nslots, const Tile *tiles,
+                        int ntiles, int B, int dtype, int max_nblk_step, int max_ny, int max_nw,
                         int max_epi, int pass_grid, int nt, hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_pass_only(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles, int B,
                             int dtype, int max_nw, int pass_grid, int nt);
 // persistent pass grid: resident blocks per CU of k_pass for this configuration
 int pass_blocks_per_cu(int B, int dtype, int max_nw);
 size_t pass_lds_bytes(int B, int dtype, int max_nw);
-hipError_t launch_epi_anchor(hipStream_t s, Slot *slots, int nslots, int max_epi);
+hipError_t launch_epi_anchor(hipStream_t s, Slot *slots, const int *live, int nslots, int max_epi);
 hipError_t launch_matvec1(hipStream_t s, const void *Q, int dtype, int n, int ld, int row_base,
                           const double *v, int nw, double *z);
 hipError_t launch_grad(hipStream_t s, const Slot *slot, int n, const double *U, const double *y,

@@ -93,7 +93,7 @@ void tile_shape(int64_t n, int dt, int64_t rows, int *lpr, int *rows_per_tile)
     const int64_t row_bytes = n * elem_size(dt);
     int64_t r = std::max<int64_t>(1, (128 * 1024) / std::max<int64_t>(row_bytes, 1));
     r = std::min<int64_t>(r, std::max<int64_t>(1, rows / 1024));
-    r = round_up(std::max<int64_t>(r, ng), ng);
+    r = round_up(std::max<int64_t>(r, 4 * ng), 4 * ng);   // whole row blocks of up to 4 rows per group
     *lpr = l;
     *rows_per_tile = (int)r;
 }
@@ -119,6 +119,7 @@ struct qcqp_handle {
     Slot hslot{};             // canonical buffer assignment; uploaded at the start of a run
     Slot *dslot = nullptr;    // device copy used by single solves
     Slot *dslot_eval = nullptr;   // device slot of point evaluations (never the running one)
+    int *dlive0 = nullptr;        // device live list {0}: the single slot of a standalone run
     Tile *dtiles = nullptr;
     std::vector<Tile> tiles;  // slot field 0
     int nblk_step = 1;
@@ -144,9 +145,16 @@ struct qcqp_batch {
     Slot *h_poll = nullptr;               // pinned copy of all slots
     Tile *dtiles = nullptr;
     size_t tiles_cap = 0;
+    int *dlive = nullptr;                 // device list of live slot ids (max_slots entries)
+    int nlive = 0;
     int ntiles = 0, max_nblk = 1, max_ny = 1, max_nw = 2, max_epi = 1;
     int pass_grid = 1, nt = 0;
     bool dirty = true;
+    // pass timing (options.timing): kernel seconds and algorithmic bytes streamed
+    std::vector<hipEvent_t> ev;
+    double pass_seconds = 0.0, pass_bytes = 0.0;
+    int64_t passes = 0;
+    std::vector<int64_t> last_passes;     // per slot, device pass counter at the last poll
 };
 
 // ---------------------------------------------------------------------------------------
@@ -402,6 +410,8 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
     for (auto &pr : plan) total += (size_t)round_up(pr.second * 8, 256);
     const size_t slot_off = total;
     total += 2 * round_up(sizeof(Slot), 256);
+    const size_t live_off = total;
+    total += 256;
     // tiles
     int lpr = 16, rpt = 16;
     tile_shape(n, h->dtype, nq * n, &lpr, &rpt);
@@ -428,6 +438,7 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
     }
     h->dslot = reinterpret_cast<Slot *>(h->arena + slot_off);
     h->dslot_eval = reinterpret_cast<Slot *>(h->arena + slot_off + round_up(sizeof(Slot), 256));
+    h->dlive0 = reinterpret_cast<int *>(h->arena + live_off);
     h->dtiles = reinterpret_cast<Tile *>(h->arena + tile_off);
     hipError_t e = hipMemsetAsync(h->arena, 0, total, h->stream);
     if (e == hipSuccess && !h->tiles.empty())
@@ -516,6 +527,8 @@ static void reset_run_scalars(Slot &S)
     S.k = S.ke = S.trials = S.passes = S.restarts = S.gap_evals = S.iter_trials = 0;
     S.status = ST_RUNNING;
     S.mode = MODE_ANCHOR;
+    S.fresh = 0;
+    S.anchor_keep_gp = 0;
 }
 
 // copy x0 (or zeros) and y0 (or zeros) into the canonical iterate buffers
@@ -604,7 +617,7 @@ qcqp_status qcqp_solve(qcqp_handle *h, const double *x0, const double *y0, doubl
     int64_t passes_before = 0;
     for (;;) {
         for (int64_t g = 0; g < poll; ++g) {
-            hipError_t e = launch_group(h->stream, h->dslot, 1, h->dtiles, ntiles, h->B, h->dtype,
+            hipError_t e = launch_group(h->stream, h->dslot, h->dlive0, 1, h->dtiles, ntiles, h->B, h->dtype,
                                         h->nblk_step, (int)std::max<int64_t>(h->ny, 1), (int)h->nw,
                                         (int)(h->m + 1 + h->p), h->pass_grid, h->nt,
                                         timing ? ev[2 * g] : nullptr, timing ? ev[2 * g + 1] : nullptr);
@@ -659,7 +672,7 @@ static qcqp_status eval_loaded_point(qcqp_handle *h)
     HIPCHK(hipMemsetAsync(h->d_ueval, 0, (h->m + 1) * h->n * 8, h->stream));
     HIPCHK(hipMemcpyAsync(h->dslot_eval, &S, sizeof(Slot), hipMemcpyHostToDevice, h->stream));
     HIPCHK(launch_pass_only(h->stream, h->dslot_eval, h->dtiles, (int)h->tiles.size(), h->B, h->dtype, (int)h->nw, h->pass_grid, h->nt));
-    HIPCHK(launch_epi_anchor(h->stream, h->dslot_eval, 1, (int)(h->m + 1 + h->p)));
+    HIPCHK(launch_epi_anchor(h->stream, h->dslot_eval, h->dlive0, 1, (int)(h->m + 1 + h->p)));
     return QCQP_OK;
 }
 
@@ -832,7 +845,9 @@ qcqp_status qcqp_batch_create(const qcqp_options *opt, size_t budget, int64_t ma
     (void)hipGetDevice(&bt->dev);
     bt->handles.assign(max_slots, nullptr);
     bt->finished.assign(max_slots, 0);
-    if (hipMalloc(&bt->dslots, max_slots * sizeof(Slot)) != hipSuccess ||
+    bt->last_passes.assign(max_slots, 0);
+    if (hipMalloc(&bt->dlive, max_slots * sizeof(int)) != hipSuccess ||
+        hipMalloc(&bt->dslots, max_slots * sizeof(Slot)) != hipSuccess ||
         hipHostMalloc((void **)&bt->h_poll, max_slots * sizeof(Slot)) != hipSuccess) {
         if (bt->dslots) (void)hipFree(bt->dslots);
         delete bt;
@@ -898,6 +913,7 @@ qcqp_status qcqp_batch_admit(qcqp_batch *bt, qcqp_handle *h, const double *x0, c
     HIPCHK(hipStreamSynchronize(bt->stream));
     bt->handles[free_slot] = h;
     bt->finished[free_slot] = 0;
+    bt->last_passes[free_slot] = 0;
     h->owner = bt;
     bt->dirty = true;
     *slot = free_slot;
@@ -907,6 +923,7 @@ qcqp_status qcqp_batch_admit(qcqp_batch *bt, qcqp_handle *h, const double *x0, c
 static qcqp_status rebuild_tiles(qcqp_batch *bt)
 {
     std::vector<Tile> all;
+    std::vector<int> live;
     bt->max_nblk = 1;
     bt->max_ny = 1;
     bt->max_nw = 2;
@@ -914,6 +931,7 @@ static qcqp_status rebuild_tiles(qcqp_batch *bt)
     for (int64_t s = 0; s < bt->max_slots; ++s) {
         qcqp_handle *h = bt->handles[s];
         if (!h || bt->finished[s]) continue;
+        live.push_back((int)s);
         for (Tile t : h->tiles) {
             t.slot = (int32_t)s;
             all.push_back(t);
@@ -941,6 +959,10 @@ static qcqp_status rebuild_tiles(qcqp_batch *bt)
     if (!mixed.empty())
         HIPCHK(hipMemcpyAsync(bt->dtiles, mixed.data(), mixed.size() * sizeof(Tile),
                               hipMemcpyHostToDevice, bt->stream));
+    if (!live.empty())
+        HIPCHK(hipMemcpyAsync(bt->dlive, live.data(), live.size() * sizeof(int), hipMemcpyHostToDevice,
+                              bt->stream));
+    bt->nlive = (int)live.size();
     bt->ntiles = (int)mixed.size();
     bt->pass_grid = pass_grid_for(bt->opt.spec_trials, (int)bt->opt.storage, bt->max_nw);
     bt->dirty = false;
@@ -953,17 +975,41 @@ qcqp_status qcqp_batch_step(qcqp_batch *bt, int64_t groups)
     if (!bt || groups < 0) return fail(QCQP_E_INVALID, "bad argument");
     qcqp_status st;
     if (bt->dirty && (st = rebuild_tiles(bt))) return st;
-    if (bt->ntiles > 0) {
+    const bool timing = bt->opt.timing != 0;
+    if (timing && (int64_t)bt->ev.size() < 2 * groups) {
+        while ((int64_t)bt->ev.size() < 2 * groups) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            bt->ev.push_back(e);
+        }
+    }
+    if (bt->nlive > 0) {
         for (int64_t g = 0; g < groups; ++g) {
-            hipError_t e = launch_group(bt->stream, bt->dslots, (int)bt->max_slots, bt->dtiles, bt->ntiles,
+            hipError_t e = launch_group(bt->stream, bt->dslots, bt->dlive, bt->nlive, bt->dtiles, bt->ntiles,
                                         bt->opt.spec_trials, (int)bt->opt.storage, bt->max_nblk,
                                         bt->max_ny, bt->max_nw, bt->max_epi, bt->pass_grid, bt->nt,
-                                        nullptr, nullptr);
+                                        timing ? bt->ev[2 * g] : nullptr, timing ? bt->ev[2 * g + 1] : nullptr);
             if (e != hipSuccess) return fail(QCQP_E_DEVICE, "launch: %s", hipGetErrorString(e));
         }
     }
     HIPCHK(hipMemcpyAsync(bt->h_poll, bt->dslots, bt->max_slots * sizeof(Slot), hipMemcpyDeviceToHost, bt->stream));
     HIPCHK(hipStreamSynchronize(bt->stream));
+    if (timing && bt->nlive > 0) {
+        for (int64_t g = 0; g < groups; ++g) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, bt->ev[2 * g], bt->ev[2 * g + 1]) == hipSuccess) bt->pass_seconds += ms * 1e-3;
+        }
+    }
+    for (int64_t s = 0; s < bt->max_slots; ++s) {
+        qcqp_handle *h = bt->handles[s];
+        if (!h) continue;
+        const int64_t d = bt->h_poll[s].passes - bt->last_passes[s];
+        if (d > 0) {
+            bt->pass_bytes += (double)d * (double)h->nq * (double)h->n * (double)h->n * elem_size(h->dtype);
+            bt->passes += d;
+        }
+        bt->last_passes[s] = bt->h_poll[s].passes;
+    }
     // adaptive restarts pending: evaluate G_xi per slot, then resume
     for (int64_t s = 0; s < bt->max_slots; ++s) {
         qcqp_handle *h = bt->handles[s];
@@ -983,6 +1029,15 @@ qcqp_status qcqp_batch_step(qcqp_batch *bt, int64_t groups)
             }
         }
     }
+    return QCQP_OK;
+}
+
+qcqp_status qcqp_batch_pass_stats(qcqp_batch *bt, double *pass_seconds, double *pass_bytes, int64_t *passes)
+{
+    if (!bt) return fail(QCQP_E_INVALID, "null batch");
+    if (pass_seconds) *pass_seconds = bt->pass_seconds;
+    if (pass_bytes) *pass_bytes = bt->pass_bytes;
+    if (passes) *passes = bt->passes;
     return QCQP_OK;
 }
 
@@ -1007,7 +1062,7 @@ qcqp_status qcqp_batch_fetch(qcqp_batch *bt, int64_t slot, double *x_out, double
         return fail(QCQP_E_INVALID, "no such slot");
     if (!bt->finished[slot]) return fail(QCQP_E_INVALID, "slot %lld is still running", (long long)slot);
     qcqp_handle *h = bt->handles[slot];
-    const Slot &S = bt->h_poll[slot];
+    const Slot S = bt->h_poll[slot];   // a copy: the table entry is marked idle below
     const hipMemcpyKind k = h->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (x_out) HIPCHK(hipMemcpyAsync(x_out, S.x, h->n * 8, k, bt->stream));
     if (y_out && h->ny) HIPCHK(hipMemcpyAsync(y_out, S.y, h->ny * 8, k, bt->stream));
@@ -1046,6 +1101,8 @@ qcqp_status qcqp_batch_destroy(qcqp_batch *bt)
     if (bt->dslots) (void)hipFree(bt->dslots);
     if (bt->h_poll) (void)hipHostFree(bt->h_poll);
     if (bt->dtiles) (void)hipFree(bt->dtiles);
+    if (bt->dlive) (void)hipFree(bt->dlive);
+    for (auto &e : bt->ev) (void)hipEventDestroy(e);
     delete bt;
     return QCQP_OK;
 }
