@@ -32,6 +32,23 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def measured_traffic(key):
+    """HBM bytes per pass launch from the committed FETCH_SIZE/WRITE_SIZE summary, or None when
+    the kernel source changed since those counters were taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "k_pass_traffic_random_qcqp_n2000_m100.md")
+    src = os.path.join(ROOT, "paper_2605_29291_amd", "csrc", "kernels.hip")
+    try:
+        fields = dict(line.split(": ", 1) for line in open(prof).read().splitlines() if ": " in line
+                      and line.split(": ", 1)[0] in ("kernel_source_sha256", key))
+        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if fields.get("kernel_source_sha256", "").strip() != cur:
+            return None
+        return float(fields[key])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def spectral_norm_gpu(Q0):
     import torch
     return float(torch.linalg.eigvalsh(Q0.to(torch.float64)).abs().max())
@@ -144,7 +161,9 @@ def workload_config2(args):
                    "n": 2000, "m": 100, "storage": "float64", "spec_trials": 2,
                    "tau_bar": tau_bar, "gamma0": gamma0},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("traffic_bytes_per_launch_f64"),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "k_pass<DT_F64,2>", "avg_pass_us": r64["avg_pass"] * 1e6,
                      "bytes_per_pass": r64["pass_bytes"], "timed_passes": r64["timed"]},
         "cpu_baseline": cpu,
@@ -420,6 +439,37 @@ def workload_kml(args):
     }
 
 
+def workload_traffic(args):
+    """Dispatches for the HBM-traffic counters (run under rocprofv3 --pmc FETCH_SIZE, then
+    WRITE_SIZE): a plain device copy of known size (the calibration), then the config-2 FP64
+    pass and a BF16 pass exactly as the solves launch them (trial mode, 2 candidates)."""
+    import torch
+    import qcqp_inputs as qi
+    from paper_2605_29291_amd import Solver
+    nbytes = 2 << 30
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").normal_()
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    torch.cuda.empty_cache()
+    out = {"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}
+    inst = qi.random_qcqp_torch(2000, 100, qi.config_seed(2), shift=0.01, device="cuda")
+    s = Solver(inst, device=True, storage="float64", tau_bar=1.0, spec_trials=2)
+    s.time_pass(reps=3)
+    out["f64_pass_bytes"] = 101 * 2000 * 2000 * 8
+    s.close()
+    Qb = inst.Q.to(torch.bfloat16)
+    ib = qi.Instance(2000, 100, 0, Qb, inst.q, inst.c, inst.lb, inst.ub)
+    s = Solver(ib, device=True, storage="bfloat16", tau_bar=1.0, spec_trials=2)
+    s.time_pass(reps=3)
+    out["bf16_pass_bytes"] = 101 * 2000 * 2000 * 2
+    s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -450,6 +500,8 @@ def main():
         out = workload_precision(args)
     elif args.workload == "kml":
         out = workload_kml(args)
+    elif args.workload == "traffic":
+        out = workload_traffic(args)
     else:
         print(json.dumps({"error": f"unknown workload {args.workload}"}))
         sys.exit(2)
