@@ -32,16 +32,25 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def pass_source_hash(csrc):
+    """sha256 over the pass kernel's source and the device layout it reads."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("qpass.hip", "qcqp_device.h"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(key):
     """HBM bytes per pass launch from the committed FETCH_SIZE/WRITE_SIZE summary, or None when
     the kernel source changed since those counters were taken."""
     import hashlib
     prof = os.path.join(ROOT, "profiles", "k_pass_traffic_random_qcqp_n2000_m100.md")
-    src = os.path.join(ROOT, "paper_2605_29291_amd", "csrc", "kernels.hip")
+    csrc = os.path.join(ROOT, "paper_2605_29291_amd", "csrc")
     try:
         fields = dict(line.split(": ", 1) for line in open(prof).read().splitlines() if ": " in line
                       and line.split(": ", 1)[0] in ("kernel_source_sha256", key))
-        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        cur = pass_source_hash(csrc)
         if fields.get("kernel_source_sha256", "").strip() != cur:
             return None
         return float(fields[key])
@@ -253,6 +262,9 @@ def serve_batched(trace, storage, args, budget):
                 reqs[k]["x"], reqs[k]["y"] = x.cpu().numpy(), y.cpu().numpy()
             s.close()
             done += 1
+            if done % 64 == 0:
+                log(f"  batched {storage}: {done}/{len(reqs)} done, {len(slot_req)} resident, "
+                    f"generation {gen:.1f} s")
     total = time.perf_counter() - t0 - gen
     ps = b.pass_stats()
     b.close()
@@ -281,6 +293,8 @@ def serve_fifo(trace, storage, args):
         r["done"] = time.perf_counter() - t0 - gen
         r["info"] = info
         s.close()
+        if (len([q for q in reqs if "done" in q])) % 64 == 0:
+            log(f"  fifo {storage}: {len([q for q in reqs if 'done' in q])}/{len(reqs)} done")
     total = time.perf_counter() - t0 - gen
     return reqs, total, gen
 
@@ -470,6 +484,58 @@ def workload_traffic(args):
     return out
 
 
+def workload_small(args):
+    """Config-1-sized problems (n=100, m=10): latency of one solve, and 100 independent instances
+    served as one batch (one pass kernel per trial group covers all of them)."""
+    import torch
+    import qcqp_inputs as qi
+    from paper_2605_29291_amd import Batch, Solver
+    insts = [qi.random_qcqp(100, 10, qi.config_seed(1, k)) for k in range(100)]
+    tb = [1.0 / float(np.linalg.norm(i.Q[0], 2)) for i in insts]
+    s = Solver(insts[0], device=True, tau_bar=tb[0], gamma0=0.1)
+    for _ in range(args.warmup + 1):
+        s.solve()
+    lat = []
+    for _ in range(max(args.steps, 20)):
+        t = time.perf_counter()
+        x, y, info = s.solve()
+        lat.append(time.perf_counter() - t)
+    s.close()
+    single = dict(p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
+                  solves_per_s=1.0 / float(np.mean(lat)), iters=info["iters"], q_passes=info["q_passes"])
+    log(f"single: {single}")
+    solvers = [Solver(inst, device=True, tau_bar=t, gamma0=0.1) for inst, t in zip(insts, tb)]
+    torch.cuda.synchronize()
+    b = Batch(max_slots=len(insts))
+    t0 = time.perf_counter()
+    for sv in solvers:
+        b.admit(sv)
+    done = 0
+    infos = []
+    while done < len(insts):
+        b.step(16)
+        for slot in b.poll():
+            _, x, y, info = b.fetch(slot)
+            infos.append(info)
+            done += 1
+    wall = time.perf_counter() - t0
+    b.close()
+    batched = dict(instances=len(insts), seconds=wall, solves_per_s=len(insts) / wall,
+                   converged=sum(i["status"] == "ok" for i in infos),
+                   max_rel_kkt=max(i["rel_kkt"] for i in infos))
+    log(f"batched: {batched}")
+    return {
+        "metric": METRIC, "value": batched["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "steps": len(insts), "warmup": args.warmup, "ms_per_step": 1e3 / batched["solves_per_s"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "random convex QCQP n=100 m=10 (0.88 MB FP64 stack, cache-resident), "
+                               "100 instances as one batch; single-solve latency beside"},
+        "roofline": None, "cpu_baseline": None,
+        "latency_ms": {"p50": single["p50_ms"], "p99": single["p99_ms"]},
+        "single": single, "batched": batched,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -502,6 +568,8 @@ def main():
         out = workload_kml(args)
     elif args.workload == "traffic":
         out = workload_traffic(args)
+    elif args.workload == "small":
+        out = workload_small(args)
     else:
         print(json.dumps({"error": f"unknown workload {args.workload}"}))
         sys.exit(2)

@@ -102,7 +102,10 @@ typedef struct {
     int timing;                /* 1: time every Q-pass launch with HIP events (qcqp_info) */
     double inner_tol;          /* G_xi inner box-QP tolerance (1e-12) */
     int64_t max_inner;         /* G_xi inner iteration cap (100000) */
-    void *stream;              /* hipStream_t */
+    int use_graphs;            /* 1: replay HIP-graph-captured chunks of trial groups (1); the
+                                  timing mode always launches eagerly */
+    void *stream;              /* hipStream_t of the caller; the library works on its own
+                                  stream of default priority, ordered after this one */
 } qcqp_options;
 
 typedef struct {

@@ -47,7 +47,7 @@ class Options(C.Structure):
                 ("ada_every", C.c_int64), ("max_iter", C.c_int64), ("tol", C.c_double),
                 ("storage", C.c_int), ("pass_mode", C.c_int), ("spec_trials", C.c_int),
                 ("poll_every", C.c_int64), ("timing", C.c_int), ("inner_tol", C.c_double),
-                ("max_inner", C.c_int64), ("stream", C.c_void_p)]
+                ("max_inner", C.c_int64), ("use_graphs", C.c_int), ("stream", C.c_void_p)]
 
 
 class Info(C.Structure):

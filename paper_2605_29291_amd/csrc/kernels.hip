@@ -53,269 +53,6 @@ __device__ __forceinline__ void block_sum(double (&v)[NV])
 }
 
 // ---------------------------------------------------------------------------------------
-// storage types: one 16-byte vector load per lane per chunk.  Loads go through the global
-// address space (the stack pointer is read from the slot, so the compiler cannot infer it);
-// NT selects non-temporal loads for stacks that cannot stay cache-resident across passes.
-
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-typedef __attribute__((address_space(1))) const u32x4 g_u32x4;
-
-template <bool NT>
-__device__ __forceinline__ u32x4 ld16(const void *base, size_t byte_off)
-{
-    const g_u32x4 *p = (const g_u32x4 *)((const char *)base + byte_off);
-    if constexpr (NT) return __builtin_nontemporal_load(p);
-    else return *p;
-}
-
-template <int DT> struct Store;
-
-template <> struct Store<DT_F64> {
-    static constexpr int V = 2;
-    static constexpr int ES = 8;
-    using acc_t = double;
-    __device__ static __forceinline__ double get(const u32x4 &v, int e)
-    {
-        const unsigned lo = e == 0 ? v.x : v.z, hi = e == 0 ? v.y : v.w;
-        return __hiloint2double((int)hi, (int)lo);
-    }
-};
-
-template <> struct Store<DT_F32> {
-    static constexpr int V = 4;
-    static constexpr int ES = 4;
-    using acc_t = float;
-    __device__ static __forceinline__ float get(const u32x4 &v, int e)
-    {
-        return __uint_as_float(e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w)));
-    }
-};
-
-template <> struct Store<DT_BF16> {
-    static constexpr int V = 8;
-    static constexpr int ES = 2;
-    using acc_t = float;
-    __device__ static __forceinline__ float get(const u32x4 &v, int e)
-    {
-        const uint32_t w = (e >> 1) == 0 ? v.x : ((e >> 1) == 1 ? v.y : ((e >> 1) == 2 ? v.z : v.w));
-        const uint32_t bits = (e & 1) ? (w & 0xffff0000u) : (w << 16);
-        return __uint_as_float(bits);   // bf16 -> fp32 is exact
-    }
-};
-
-template <> struct Store<DT_F16> {
-    static constexpr int V = 8;
-    static constexpr int ES = 2;
-    using acc_t = float;
-    __device__ static __forceinline__ float get(const u32x4 &v, int e)
-    {
-        const uint32_t w = (e >> 1) == 0 ? v.x : ((e >> 1) == 1 ? v.y : ((e >> 1) == 2 ? v.z : v.w));
-        const uint16_t h = (e & 1) ? (uint16_t)(w >> 16) : (uint16_t)(w & 0xffffu);
-        return (float)__builtin_bit_cast(_Float16, h);   // fp16 -> fp32 is exact
-    }
-};
-
-// ---------------------------------------------------------------------------------------
-// Q-stack pass: out_b[uoff + r] = sum_j Q[r, j] * w_b[j] for the stored rows r of a tile.
-// LPR lanes share one row: each lane streams 16-byte vectors of the row (coalesced across
-// the group), UNR loads in flight, multiply-adds against w held in LDS, then a butterfly
-// reduction over the LPR lanes in FP64.  With FP32 accumulation each lane sums at most
-// n / LPR products in FP32 before the FP64 combine.
-
-// Rows per group step (R) and 16-byte loads per batch (UNR) for the trial passes: R rows share
-// each w value read from LDS, which cuts LDS traffic by R for the 16/32-bit types (whose w
-// reads are 2-4 LDS bytes per streamed byte).
-#ifndef QCQP_PASS_R16
-#define QCQP_PASS_R16 4
-#endif
-#ifndef QCQP_PASS_UNR16
-#define QCQP_PASS_UNR16 4
-#endif
-#ifndef QCQP_PASS_R64
-#define QCQP_PASS_R64 1
-#endif
-#ifndef QCQP_PASS_UNR64
-#define QCQP_PASS_UNR64 8
-#endif
-
-template <int DT> struct PassShape {
-    static constexpr int R = DT == DT_F64 ? QCQP_PASS_R64 : QCQP_PASS_R16;
-    static constexpr int UNR = DT == DT_F64 ? QCQP_PASS_UNR64 : QCQP_PASS_UNR16;
-};
-
-template <int DT, typename AT, int B, int LPR, bool NT, int R, int UNR>
-__device__ __forceinline__ void pass_rows(const void *__restrict__ Q, int n, size_t ld, int row0,
-                                          int nrows, const AT *__restrict__ w, int nw,
-                                          double *const (&outs)[B], int uoff)
-{
-    using T = Store<DT>;
-    constexpr int V = T::V;
-    constexpr int ES = T::ES;
-    constexpr int NG = PASS_BS / LPR;
-    constexpr int STRIDE = LPR * V;
-    const int lane = threadIdx.x & (LPR - 1);
-    const int grp = threadIdx.x / LPR;
-    const int rend = row0 + nrows;
-    for (int r = row0 + grp * R; r < rend; r += NG * R) {
-        size_t base[R];
-        bool live[R];
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            live[i] = r + i < rend;
-            base[i] = (size_t)(live[i] ? r + i : r) * ld * ES;
-        }
-        AT acc[R][B];
-#pragma unroll
-        for (int i = 0; i < R; ++i)
-#pragma unroll
-            for (int b = 0; b < B; ++b) acc[i][b] = AT(0);
-        // batches of R x UNR independent 16-byte loads; the last batch is predicated per lane
-        for (int col = lane * V; col < n; col += UNR * STRIDE) {
-            u32x4 v[R][UNR];
-#pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-                const int c = col + u * STRIDE;
-#pragma unroll
-                for (int i = 0; i < R; ++i)
-                    v[i][u] = (c < n && live[i]) ? ld16<NT>(Q, base[i] + (size_t)c * ES)
-                                                 : u32x4{0u, 0u, 0u, 0u};
-            }
-#pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-                const int c = col + u * STRIDE;
-                if (c < n) {
-#pragma unroll
-                    for (int e = 0; e < V; ++e) {
-                        AT wv[B];
-#pragma unroll
-                        for (int b = 0; b < B; ++b) wv[b] = w[b * nw + c + e];
-#pragma unroll
-                        for (int i = 0; i < R; ++i) {
-                            const AT qv = (AT)T::get(v[i][u], e);
-#pragma unroll
-                            for (int b = 0; b < B; ++b) acc[i][b] = fma(qv, wv[b], acc[i][b]);
-                        }
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            double sv[B];
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-                sv[b] = (double)acc[i][b];
-#pragma unroll
-                for (int off = LPR / 2; off > 0; off >>= 1) sv[b] += __shfl_xor(sv[b], off, LPR);
-            }
-            if (lane == 0 && live[i]) {
-#pragma unroll
-                for (int b = 0; b < B; ++b) outs[b][uoff + r + i] = sv[b];
-            }
-        }
-    }
-}
-
-template <int DT, typename AT, int B, bool NT = false, int R = 1, int UNR = 8>
-__device__ __forceinline__ void pass_rows_lpr(int lpr, const void *Q, int n, size_t ld, int row0,
-                                              int nrows, const AT *w, int nw,
-                                              double *const (&outs)[B], int uoff)
-{
-    if (lpr == 64) pass_rows<DT, AT, B, 64, NT, R, UNR>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
-    else if (lpr == 32) pass_rows<DT, AT, B, 32, NT, R, UNR>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
-    else pass_rows<DT, AT, B, 16, NT, R, UNR>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
-}
-
-// The pass kernel runs a persistent grid: block b streams the contiguous tile range
-// [b T / G, (b+1) T / G), so every block gets the same number of equal-byte tiles and the
-// grid finishes together; w is staged into LDS only when the tile's slot changes (tiles are
-// grouped by slot).
-template <int DT, int B, bool NT>
-__global__ void __launch_bounds__(PASS_BS) k_pass(Slot *__restrict__ slots,
-                                                  const Tile *__restrict__ tiles, int ntiles)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    using AT = typename Store<DT>::acc_t;
-    const int G = gridDim.x;
-    const int t0 = (int)(((int64_t)blockIdx.x * ntiles) / G);
-    const int t1 = (int)(((int64_t)(blockIdx.x + 1) * ntiles) / G);
-    int cur = -1;
-    bool active = false, anchor = false, inc = false;
-    int n = 0, nw = 0, uoff = 0;
-    size_t ld = 0;
-    const void *Q = nullptr;
-    double *outs[B];
-#pragma unroll
-    for (int b = 0; b < B; ++b) outs[b] = nullptr;
-    for (int ti = t0; ti < t1; ++ti) {
-        const Tile t = tiles[ti];
-        if (t.slot != cur) {
-            __syncthreads();   // every wave is done with the previous slot's w
-            cur = t.slot;
-            Slot *S = slots + cur;
-            active = S->status == ST_RUNNING;
-            if (active) {
-                anchor = S->mode == MODE_ANCHOR;
-                inc = S->incremental != 0;
-                n = S->n;
-                nw = S->nw;
-                uoff = S->has_q0 ? 0 : n;
-                ld = (size_t)S->ld;
-                Q = S->Q;
-                const double *x = S->x;
-                if (anchor) {
-                    double *w = reinterpret_cast<double *>(smem);
-                    for (int j = threadIdx.x; j < nw; j += PASS_BS) w[j] = j < n ? x[j] : 0.0;
-                    outs[0] = S->Uc[0];
-                } else {
-                    AT *w = reinterpret_cast<AT *>(smem);
-#pragma unroll
-                    for (int b = 0; b < B; ++b) {
-                        const double *xc = S->xc[b];
-                        for (int j = threadIdx.x; j < nw; j += PASS_BS) {
-                            double v = 0.0;
-                            if (j < n) v = inc ? xc[j] - x[j] : xc[j];
-                            w[b * nw + j] = (AT)v;
-                        }
-                        outs[b] = inc ? S->W[b] : S->Uc[b];
-                    }
-                }
-            }
-            __syncthreads();
-        }
-        if (!active) continue;
-        if (anchor) {
-            // direct pass at the iterate, accumulated in FP64 whatever the storage type
-            double *const o1[1] = {outs[0]};
-            pass_rows_lpr<DT, double, 1, NT>(t.lpr, Q, n, ld, t.row0, t.nrows,
-                                             reinterpret_cast<const double *>(smem), nw, o1, uoff);
-        } else {
-            double *const (&co)[B] = outs;
-            pass_rows_lpr<DT, AT, B, NT, PassShape<DT>::R, PassShape<DT>::UNR>(
-                t.lpr, Q, n, ld, t.row0, t.nrows, reinterpret_cast<const AT *>(smem), nw, co, uoff);
-        }
-    }
-}
-
-// plain single-matrix product z = Q_i v (power iteration for the default step size)
-template <int DT>
-__global__ void __launch_bounds__(PASS_BS) k_matvec1(const void *__restrict__ Q, int n, int ld,
-                                                     int row_base, int lpr, int rows_per_block,
-                                                     const double *__restrict__ v, int nw,
-                                                     double *__restrict__ z)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    double *w = reinterpret_cast<double *>(smem);
-    for (int j = threadIdx.x; j < nw; j += PASS_BS) w[j] = j < n ? v[j] : 0.0;
-    __syncthreads();
-    const int r0 = blockIdx.x * rows_per_block;
-    const int nr = min(rows_per_block, n - r0);
-    if (nr <= 0) return;
-    double *const outs[1] = {z - row_base};
-    pass_rows_lpr<DT, double, 1>(lpr, Q, n, (size_t)ld, row_base + r0, nr, w, nw, outs, 0);
-}
-
-// ---------------------------------------------------------------------------------------
 // step kernel: dual step then primal step for B candidate step sizes (eq. (apdb-yx-y)):
 //   sigma = gamma tau, theta = sigma_{k-1}/sigma, s = (1+theta) G^k - theta G^{k-1},
 //   y+ = Pi_Y(y + sigma s)   (lambda >= 0, v free),
@@ -333,6 +70,7 @@ __global__ void __launch_bounds__(STEP_BS) k_step(Slot *__restrict__ slots,
     extern __shared__ double sm[];
     double *ycur = sm;
     double *ynew = sm + ny;
+    __shared__ double s_acc[STEP_WAVES - 1][B + 1][STEP_COLS];
     double tau_b[B], sig_b[B], th_b[B];
     {
         double t = S->tau;
@@ -359,34 +97,53 @@ __global__ void __launch_bounds__(STEP_BS) k_step(Slot *__restrict__ slots,
         }
     }
     __syncthreads();
-    double part[NPART];
+    // block = STEP_COLS columns; wave w sums matrices i = 1 + w, 1 + w + STEP_WAVES, ...
+    const int lane = threadIdx.x % STEP_COLS, wave = threadIdx.x / STEP_COLS;
+    const int j = blockIdx.x * STEP_COLS + lane;
+    const double *U = S->U, *q = S->q;
+    double acc[B], kk = 0.0;
 #pragma unroll
-    for (int f = 0; f < NPART; ++f) part[f] = 0.0;
-    const int j = blockIdx.x * STEP_BS + threadIdx.x;
+    for (int b = 0; b < B; ++b) acc[b] = 0.0;
     if (j < n) {
-        const double *U = S->U, *q = S->q;
-        const double u0 = U[j] + q[j];
-        double acc[B];
-#pragma unroll
-        for (int b = 0; b < B; ++b) acc[b] = u0;
-        double kk = 0.0;
-        for (int i = 1; i <= m; ++i) {
+        for (int i = 1 + wave; i <= m; i += STEP_WAVES) {
             const double t = U[(size_t)i * n + j] + q[(size_t)i * n + j];
 #pragma unroll
             for (int b = 0; b < B; ++b) acc[b] = fma(ynew[b * ny + p + i - 1], t, acc[b]);
             kk = fma(ycur[p + i - 1], t, kk);
         }
+    }
+    if (wave > 0) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) s_acc[wave - 1][b][lane] = acc[b];
+        s_acc[wave - 1][B][lane] = kk;
+    }
+    __syncthreads();
+    double part[NPART];
+#pragma unroll
+    for (int f = 0; f < NPART; ++f) part[f] = 0.0;
+    if (wave == 0 && j < n) {
+        // fixed-order combine of the wave partial sums, then the objective and equality terms
+#pragma unroll
+        for (int w = 1; w < STEP_WAVES; ++w) {
+#pragma unroll
+            for (int b = 0; b < B; ++b) acc[b] += s_acc[w - 1][b][lane];
+            kk += s_acc[w - 1][B][lane];
+        }
+        const double u0 = U[j] + q[j];
         double av = 0.0;
+        double g[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) g[b] = u0 + acc[b];
         for (int l = 0; l < p; ++l) {
             const double a = S->A[(size_t)l * n + j];
 #pragma unroll
-            for (int b = 0; b < B; ++b) acc[b] = fma(ynew[b * ny + l], a, acc[b]);
+            for (int b = 0; b < B; ++b) g[b] = fma(ynew[b * ny + l], a, g[b]);
             av = fma(ycur[l], a, av);
         }
         const double xj = S->x[j], lo = S->lb[j], hi = S->ub[j];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            const double xn = clipd(xj - tau_b[b] * acc[b], lo, hi);
+            const double xn = clipd(xj - tau_b[b] * g[b], lo, hi);
             S->xc[b][j] = xn;
             const double d = xn - xj;
             part[4 + b] = d * d;
@@ -1110,25 +867,6 @@ __global__ void __launch_bounds__(STEP_BS) k_gap_init(int n, const double *__res
     }
 }
 
-// z = H v (FP64); skipped once the inner loop is done unless force != 0
-__global__ void __launch_bounds__(PASS_BS) k_hmv(const double *__restrict__ H, int n, int ldh,
-                                                 int lpr, int rows_per_block,
-                                                 const double *__restrict__ v, int nw,
-                                                 double *__restrict__ z,
-                                                 const double *__restrict__ ctl, int force)
-{
-    if (!force && ctl[3] != 0.0) return;
-    extern __shared__ __align__(16) unsigned char smem[];
-    double *w = reinterpret_cast<double *>(smem);
-    for (int j = threadIdx.x; j < nw; j += PASS_BS) w[j] = j < n ? v[j] : 0.0;
-    __syncthreads();
-    const int r0 = blockIdx.x * rows_per_block;
-    const int nr = min(rows_per_block, n - r0);
-    if (nr <= 0) return;
-    double *const outs[1] = {z};
-    pass_rows_lpr<DT_F64, double, 1>(lpr, H, n, (size_t)ldh, r0, nr, w, nw, outs, 0);
-}
-
 __global__ void __launch_bounds__(STEP_BS) k_fista_u1(const Slot *__restrict__ S,
                                                       const double *__restrict__ x,
                                                       const double *__restrict__ grad,
@@ -1225,28 +963,15 @@ hipError_t launch_gap_setup(hipStream_t s, const Slot *slot, int n, const double
     return hipGetLastError();
 }
 
-static void hmv_shape(int n, int *lpr, int *rpb)
-{
-    const int vpr = (n + 1) / 2;
-    int l = 16;
-    if (vpr >= 4 * 64) l = 64;
-    else if (vpr >= 4 * 32) l = 32;
-    *lpr = l;
-    *rpb = 32;
-}
-
 hipError_t launch_gap_iters(hipStream_t s, const Slot *slot, int n, const double *x,
                             const double *grad, const double *H, int ldh, int nw, double *Z,
                             double *D, double *Dn, double *Hz, double *part, double *ctl,
                             int iters, int64_t max_inner)
 {
-    int lpr, rpb;
-    hmv_shape(n, &lpr, &rpb);
-    const int nblk_r = (n + rpb - 1) / rpb;
     const int nblk = (n + STEP_BS - 1) / STEP_BS;
-    const size_t lds = (size_t)nw * sizeof(double);
     for (int it = 0; it < iters; ++it) {
-        k_hmv<<<nblk_r, PASS_BS, lds, s>>>(H, n, ldh, lpr, rpb, Z, nw, Hz, ctl, 0);
+        hipError_t e = launch_hmv(s, H, n, ldh, Z, nw, Hz, ctl, 0);
+        if (e != hipSuccess) return e;
         k_fista_u1<<<nblk, STEP_BS, 0, s>>>(slot, x, grad, Hz, Z, D, Dn, ctl, part);
         k_fista_sc<<<1, STEP_BS, 0, s>>>(nblk, part, ctl, max_inner);
         k_fista_u2<<<nblk, STEP_BS, 0, s>>>(n, Dn, D, Z, ctl);
@@ -1257,80 +982,14 @@ hipError_t launch_gap_iters(hipStream_t s, const Slot *slot, int n, const double
 hipError_t launch_gap_finish(hipStream_t s, int n, const double *grad, const double *H, int ldh,
                              int nw, const double *D, double *HD, double *ctl)
 {
-    int lpr, rpb;
-    hmv_shape(n, &lpr, &rpb);
-    const int nblk_r = (n + rpb - 1) / rpb;
-    k_hmv<<<nblk_r, PASS_BS, (size_t)nw * sizeof(double), s>>>(H, n, ldh, lpr, rpb, D, nw, HD, ctl, 1);
+    hipError_t e = launch_hmv(s, H, n, ldh, D, nw, HD, ctl, 1);
+    if (e != hipSuccess) return e;
     k_gap_px<<<1, STEP_BS, 0, s>>>(n, grad, D, HD, ctl);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------
 // launch wrappers
-
-size_t pass_lds_bytes(int B, int dtype, int max_nw)
-{
-    const size_t accsz = dtype == DT_F64 ? sizeof(double) : sizeof(float);
-    size_t lds = (size_t)max_nw * sizeof(double);
-    const size_t trial = (size_t)B * max_nw * accsz;
-    return trial > lds ? trial : lds;
-}
-
-template <int DT, int B>
-static void launch_pass_dt(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles, size_t lds,
-                           int grid, int nt)
-{
-    if (nt) k_pass<DT, B, true><<<grid, PASS_BS, lds, s>>>(slots, tiles, ntiles);
-    else k_pass<DT, B, false><<<grid, PASS_BS, lds, s>>>(slots, tiles, ntiles);
-}
-
-template <int B>
-static void launch_pass_b(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles, int dtype,
-                          int max_nw, int grid, int nt)
-{
-    const size_t lds = pass_lds_bytes(B, dtype, max_nw);
-    if (grid > ntiles) grid = ntiles;
-    if (grid < 1) grid = 1;
-    switch (dtype) {
-    case DT_F64: launch_pass_dt<DT_F64, B>(s, slots, tiles, ntiles, lds, grid, nt); break;
-    case DT_F32: launch_pass_dt<DT_F32, B>(s, slots, tiles, ntiles, lds, grid, nt); break;
-    case DT_BF16: launch_pass_dt<DT_BF16, B>(s, slots, tiles, ntiles, lds, grid, nt); break;
-    default: launch_pass_dt<DT_F16, B>(s, slots, tiles, ntiles, lds, grid, nt); break;
-    }
-}
-
-template <int DT, int B>
-static int occ_dt(size_t lds)
-{
-    int a = 0, b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_pass<DT, B, false>, PASS_BS, lds) != hipSuccess) a = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_pass<DT, B, true>, PASS_BS, lds) != hipSuccess) b = 1;
-    return a < b ? a : b;
-}
-
-template <int B>
-static int occ_b(int dtype, size_t lds)
-{
-    switch (dtype) {
-    case DT_F64: return occ_dt<DT_F64, B>(lds);
-    case DT_F32: return occ_dt<DT_F32, B>(lds);
-    case DT_BF16: return occ_dt<DT_BF16, B>(lds);
-    default: return occ_dt<DT_F16, B>(lds);
-    }
-}
-
-int pass_blocks_per_cu(int B, int dtype, int max_nw)
-{
-    const size_t lds = pass_lds_bytes(B, dtype, max_nw);
-    int o = 1;
-    switch (B) {
-    case 1: o = occ_b<1>(dtype, lds); break;
-    case 2: o = occ_b<2>(dtype, lds); break;
-    case 3: o = occ_b<3>(dtype, lds); break;
-    default: o = occ_b<4>(dtype, lds); break;
-    }
-    return o < 1 ? 1 : o;
-}
 
 template <int B>
 static hipError_t group_b(hipStream_t s, Slot *slots, const int *live, int nslots, const Tile *tiles, int ntiles,
@@ -1340,7 +999,7 @@ static hipError_t group_b(hipStream_t s, Slot *slots, const int *live, int nslot
     const size_t step_lds = (size_t)(B + 1) * (size_t)(max_ny > 0 ? max_ny : 1) * sizeof(double);
     k_step<B><<<dim3(max_nblk_step, nslots), STEP_BS, step_lds, s>>>(slots, live);
     if (ev0) (void)hipEventRecord(ev0, s);
-    launch_pass_b<B>(s, slots, tiles, ntiles, dtype, max_nw, pass_grid, nt);
+    (void)launch_pass_only(s, slots, tiles, ntiles, B, dtype, max_nw, pass_grid, nt);
     if (ev1) (void)hipEventRecord(ev1, s);
     k_epi<B><<<dim3(max_epi, nslots), STEP_BS, 0, s>>>(slots, live);
     k_ctrl<B><<<nslots, STEP_BS, 0, s>>>(slots, live);
@@ -1359,42 +1018,10 @@ hipError_t launch_group(hipStream_t s, Slot *slots, const int *live, int nslots,
     }
 }
 
-hipError_t launch_pass_only(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles, int B,
-                            int dtype, int max_nw, int pass_grid, int nt)
-{
-    switch (B) {
-    case 1: launch_pass_b<1>(s, slots, tiles, ntiles, dtype, max_nw, pass_grid, nt); break;
-    case 2: launch_pass_b<2>(s, slots, tiles, ntiles, dtype, max_nw, pass_grid, nt); break;
-    case 3: launch_pass_b<3>(s, slots, tiles, ntiles, dtype, max_nw, pass_grid, nt); break;
-    default: launch_pass_b<4>(s, slots, tiles, ntiles, dtype, max_nw, pass_grid, nt); break;
-    }
-    return hipGetLastError();
-}
-
 hipError_t launch_epi_anchor(hipStream_t s, Slot *slots, const int *live, int nslots, int max_epi)
 {
     // k_epi<1> handles the anchor mode for any B (it only touches candidate 0)
     k_epi<1><<<dim3(max_epi, nslots), STEP_BS, 0, s>>>(slots, live);
-    return hipGetLastError();
-}
-
-hipError_t launch_matvec1(hipStream_t s, const void *Q, int dtype, int n, int ld, int row_base,
-                          const double *v, int nw, double *z)
-{
-    const int vec = dtype == DT_F64 ? 2 : (dtype == DT_F32 ? 4 : 8);
-    const int vpr = (n + vec - 1) / vec;
-    int lpr = 16;
-    if (vpr >= 4 * 64) lpr = 64;
-    else if (vpr >= 4 * 32) lpr = 32;
-    const int rows_per_block = 32;
-    const int nblk = (n + rows_per_block - 1) / rows_per_block;
-    const size_t lds = (size_t)nw * sizeof(double);
-    switch (dtype) {
-    case DT_F64: k_matvec1<DT_F64><<<nblk, PASS_BS, lds, s>>>(Q, n, ld, row_base, lpr, rows_per_block, v, nw, z); break;
-    case DT_F32: k_matvec1<DT_F32><<<nblk, PASS_BS, lds, s>>>(Q, n, ld, row_base, lpr, rows_per_block, v, nw, z); break;
-    case DT_BF16: k_matvec1<DT_BF16><<<nblk, PASS_BS, lds, s>>>(Q, n, ld, row_base, lpr, rows_per_block, v, nw, z); break;
-    default: k_matvec1<DT_F16><<<nblk, PASS_BS, lds, s>>>(Q, n, ld, row_base, lpr, rows_per_block, v, nw, z); break;
-    }
     return hipGetLastError();
 }
 
@@ -1435,48 +1062,6 @@ hipError_t launch_restart_decision(hipStream_t s, Slot *slot, double gap, int fi
 {
     k_restart_decision<<<1, STEP_BS, 0, s>>>(slot, gap, first);
     return hipGetLastError();
-}
-
-template <int DT, int B>
-static hipError_t set_attr_one(int max_lds)
-{
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass<DT, B, false>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass<DT, B, true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-    return e;
-}
-
-hipError_t prepare_kernels(int max_lds)
-{
-    hipError_t e = hipSuccess;
-#define QCQP_ATTR(DT)                                    \
-    if (e == hipSuccess) e = set_attr_one<DT, 1>(max_lds);      \
-    if (e == hipSuccess) e = set_attr_one<DT, 2>(max_lds);      \
-    if (e == hipSuccess) e = set_attr_one<DT, 3>(max_lds);      \
-    if (e == hipSuccess) e = set_attr_one<DT, 4>(max_lds);
-    QCQP_ATTR(DT_F64)
-    QCQP_ATTR(DT_F32)
-    QCQP_ATTR(DT_BF16)
-    QCQP_ATTR(DT_F16)
-#undef QCQP_ATTR
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_hmv),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_matvec1<DT_F64>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_matvec1<DT_F32>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_matvec1<DT_BF16>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_matvec1<DT_F16>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-    return e;
 }
 
 }  // namespace qcqp

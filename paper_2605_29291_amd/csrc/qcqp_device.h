@@ -20,6 +20,8 @@ namespace qcqp {
 constexpr int MAXB = 4;            // max speculative candidates per pass
 constexpr int NPART = 4 + MAXB;    // step-kernel partials per block: rx2, s0, s1, s2, dd[b]
 constexpr int STEP_BS = 256;       // threads per block of the vector kernels
+constexpr int STEP_COLS = 64;      // columns per step-kernel block (one per lane of a wave)
+constexpr int STEP_WAVES = STEP_BS / STEP_COLS;   // waves splitting the matrices of a column
 constexpr int PASS_BS = 256;       // threads per block of the pass kernel
 
 enum SlotStatus : int32_t {
@@ -108,6 +110,8 @@ hipError_t launch_gap_iters(hipStream_t s, const Slot *slot, int n, const double
                             int iters, int64_t max_inner);
 hipError_t launch_gap_finish(hipStream_t s, int n, const double *grad, const double *H, int ldh,
                              int nw, const double *D, double *HD, double *ctl);
+hipError_t launch_hmv(hipStream_t s, const double *H, int n, int ldh, const double *v, int nw,
+                      double *z, const double *ctl, int force);
 hipError_t prepare_kernels(int max_lds_bytes);
 
 }  // namespace qcqp

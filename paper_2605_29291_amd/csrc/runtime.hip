@@ -71,6 +71,29 @@ qcqp_status ensure_prepared()
     return QCQP_OK;
 }
 
+// order the library's work stream after everything already queued on the caller's stream
+hipError_t join_streams(hipStream_t work, hipStream_t user, hipEvent_t ev)
+{
+    hipError_t e = hipEventRecord(ev, user);
+    if (e == hipSuccess) e = hipStreamWaitEvent(work, ev, 0);
+    return e;
+}
+
+// capture the launches `fn` enqueues on `s` into an instantiated graph
+template <typename F>
+hipError_t capture_graph(hipStream_t s, F fn, hipGraphExec_t *out)
+{
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t el = fn(s);
+    e = hipStreamEndCapture(s, &g);
+    if (el != hipSuccess) e = el;
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+}
+
 double now_s()
 {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -109,7 +132,11 @@ int pass_grid_for(int B, int dtype, int max_nw)
 
 struct qcqp_handle {
     int dev = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;     // the library's own work stream (default priority)
+    hipStream_t ustream = nullptr;    // the caller's stream (options.stream)
+    hipEvent_t ev_join = nullptr;
+    hipGraphExec_t gexec = nullptr;   // captured chunk of trial groups (solve)
+    int64_t gexec_groups = 0;
     qcqp_options opt{};
     int64_t n = 0, m = 0, p = 0, ny = 0, nq = 0, ld = 0, nw = 0;
     int has_q0 = 1, on_device = 0, dtype = DT_F64, incremental = 0, B = 1;
@@ -138,7 +165,11 @@ struct qcqp_batch {
     size_t budget = 0;
     int64_t max_slots = 0;
     int dev = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;     // own work stream
+    hipStream_t ustream = nullptr;    // caller's stream
+    hipEvent_t ev_join = nullptr;
+    hipGraphExec_t gexec = nullptr;   // captured chunk of trial groups for the current live set
+    int64_t gexec_groups = 0;
     std::vector<qcqp_handle *> handles;   // per slot, nullptr = free
     std::vector<int> finished;            // per slot: status already reported finished
     Slot *dslots = nullptr;
@@ -191,6 +222,7 @@ void qcqp_options_default(qcqp_options *o)
     o->timing = 0;
     o->inner_tol = 1e-12;
     o->max_inner = 100000;
+    o->use_graphs = 1;
     o->stream = nullptr;
 }
 
@@ -224,6 +256,13 @@ static qcqp_status validate_options(const qcqp_options *o)
 
 static void free_handle_memory(qcqp_handle *h)
 {
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    h->ev_join = nullptr;
+    if (h->stream) (void)hipStreamDestroy(h->stream);
+    h->stream = nullptr;
     if (h->dQ) (void)hipFree(h->dQ);
     if (h->arena) (void)hipFree(h->arena);
     if (h->h_poll) (void)hipHostFree(h->h_poll);
@@ -288,12 +327,26 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
     h->n = n; h->m = m; h->p = p; h->ny = p + m; h->nq = nq; h->has_q0 = has_q0;
     h->on_device = P->on_device ? 1 : 0;
     h->dtype = (int)o.storage;
-    h->stream = (hipStream_t)o.stream;
+    h->ustream = (hipStream_t)o.stream;
     h->B = o.spec_trials;
     h->incremental = o.pass_mode == QCQP_PASS_INCREMENTAL ||
                      (o.pass_mode == QCQP_PASS_AUTO && o.storage != QCQP_F64);
     if (hipGetDevice(&h->dev) != hipSuccess) { delete h; return fail(QCQP_E_DEVICE, "no HIP device"); }
     if ((st = ensure_prepared())) { delete h; return st; }
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
+        if (h->stream) (void)hipStreamDestroy(h->stream);
+        delete h;
+        return fail(QCQP_E_DEVICE, "stream creation");
+    }
+    // inputs written on the caller's stream are complete before the library reads them
+    if (hipEventRecord(h->ev_join, h->ustream) != hipSuccess ||
+        hipStreamWaitEvent(h->stream, h->ev_join, 0) != hipSuccess) {
+        (void)hipStreamDestroy(h->stream);
+        (void)hipEventDestroy(h->ev_join);
+        delete h;
+        return fail(QCQP_E_DEVICE, "stream join");
+    }
 
     // ---- host-side validation of the small vectors (copied to host when on device) ----
     std::vector<double> hq((m + 1) * n), hc(m + 1), hlb(n), hub(n), hA(p * n), hb(p);
@@ -372,7 +425,7 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
 
     // ---- arena for vectors and state ----
     const int B = h->B;
-    h->nblk_step = (int)((n + STEP_BS - 1) / STEP_BS);
+    h->nblk_step = (int)((n + STEP_COLS - 1) / STEP_COLS);
     const int64_t ny = h->ny, U1 = (m + 1) * n;
     std::vector<std::pair<double **, int64_t>> plan;
     Slot &S = h->hslot;
@@ -593,6 +646,7 @@ qcqp_status qcqp_solve(qcqp_handle *h, const double *x0, const double *y0, doubl
     if (h->owner) return fail(QCQP_E_INVALID, "handle is admitted to a batch");
     const double t0 = now_s();
     qcqp_status st;
+    HIPCHK(join_streams(h->stream, h->ustream, h->ev_join));
     if ((st = load_start(h, x0, y0))) return st;
     Slot S0 = h->hslot;
     reset_run_scalars(S0);
@@ -615,15 +669,27 @@ qcqp_status qcqp_solve(qcqp_handle *h, const double *x0, const double *y0, doubl
     Slot &snap = *h->h_poll;
     qcqp_status result = QCQP_OK;
     int64_t passes_before = 0;
-    for (;;) {
+    auto launch_chunk = [&](hipStream_t s, bool with_events) -> hipError_t {
         for (int64_t g = 0; g < poll; ++g) {
-            hipError_t e = launch_group(h->stream, h->dslot, h->dlive0, 1, h->dtiles, ntiles, h->B, h->dtype,
+            hipError_t e = launch_group(s, h->dslot, h->dlive0, 1, h->dtiles, ntiles, h->B, h->dtype,
                                         h->nblk_step, (int)std::max<int64_t>(h->ny, 1), (int)h->nw,
                                         (int)(h->m + 1 + h->p), h->pass_grid, h->nt,
-                                        timing ? ev[2 * g] : nullptr, timing ? ev[2 * g + 1] : nullptr);
-            if (e != hipSuccess) { result = fail(QCQP_E_DEVICE, "launch: %s", hipGetErrorString(e)); break; }
+                                        with_events ? ev[2 * g] : nullptr,
+                                        with_events ? ev[2 * g + 1] : nullptr);
+            if (e != hipSuccess) return e;
         }
-        if (result) break;
+        return hipSuccess;
+    };
+    const bool graphs = h->opt.use_graphs && !timing;
+    if (graphs && (!h->gexec || h->gexec_groups != poll)) {
+        if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+        HIPCHK(capture_graph(h->stream, [&](hipStream_t s) { return launch_chunk(s, false); }, &h->gexec));
+        h->gexec_groups = poll;
+    }
+    for (;;) {
+        hipError_t el = graphs ? hipGraphLaunch(h->gexec, h->stream) : launch_chunk(h->stream, timing);
+        if (el != hipSuccess) { result = fail(QCQP_E_DEVICE, "launch: %s", hipGetErrorString(el)); break; }
         hipError_t e = hipMemcpyAsync(&snap, h->dslot, sizeof(Slot), hipMemcpyDeviceToHost, h->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
         if (e != hipSuccess) { result = fail(QCQP_E_DEVICE, "poll: %s", hipGetErrorString(e)); break; }
@@ -747,6 +813,8 @@ qcqp_status qcqp_eval_operator(qcqp_handle *h, const double *x, const double *y,
 {
     g_err.clear();
     if (!h || !x) return fail(QCQP_E_INVALID, "null argument");
+    if (h->owner) return fail(QCQP_E_INVALID, "handle is admitted to a batch");
+    HIPCHK(join_streams(h->stream, h->ustream, h->ev_join));
     qcqp_status st;
     if ((st = eval_point(h, x, y))) return st;
     if (grad_x) HIPCHK(launch_grad(h->stream, h->dslot_eval, (int)h->n, h->d_ueval, h->d_ye, h->d_grad));
@@ -763,6 +831,8 @@ qcqp_status qcqp_eval_kkt(qcqp_handle *h, const double *x, const double *y, doub
 {
     g_err.clear();
     if (!h || !x || !out6) return fail(QCQP_E_INVALID, "null argument");
+    if (h->owner) return fail(QCQP_E_INVALID, "handle is admitted to a batch");
+    HIPCHK(join_streams(h->stream, h->ustream, h->ev_join));
     qcqp_status st;
     if ((st = eval_point(h, x, y))) return st;
     HIPCHK(launch_kkt(h->stream, h->dslot_eval, (int)h->n, h->d_xe, h->d_ye, h->d_ueval, h->d_geval,
@@ -779,6 +849,7 @@ qcqp_status qcqp_eval_gap(qcqp_handle *h, const double *x, const double *y, doub
     if (!h || !x || !out4) return fail(QCQP_E_INVALID, "null argument");
     if (!(xi > 0.0)) return fail(QCQP_E_INVALID, "xi must be > 0");
     if (h->owner) return fail(QCQP_E_INVALID, "handle is admitted to a batch");
+    HIPCHK(join_streams(h->stream, h->ustream, h->ev_join));
     qcqp_status st = load_point(h, x, y, h->on_device != 0);
     if (st) return st;
     return gap_at_device_point(h, h->d_xe, h->d_ye, xi, out4);
@@ -802,6 +873,7 @@ qcqp_status qcqp_time_pass(qcqp_handle *h, int64_t reps, double *avg_seconds)
     g_err.clear();
     if (!h || !avg_seconds || reps < 1) return fail(QCQP_E_INVALID, "bad argument");
     if (h->owner) return fail(QCQP_E_INVALID, "handle is admitted to a batch");
+    HIPCHK(join_streams(h->stream, h->ustream, h->ev_join));
     Slot S = h->hslot;
     reset_run_scalars(S);
     S.mode = MODE_TRIAL;
@@ -841,7 +913,13 @@ qcqp_status qcqp_batch_create(const qcqp_options *opt, size_t budget, int64_t ma
     bt->opt = o;
     bt->budget = budget;
     bt->max_slots = max_slots;
-    bt->stream = (hipStream_t)o.stream;
+    bt->ustream = (hipStream_t)o.stream;
+    if (hipStreamCreateWithFlags(&bt->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&bt->ev_join, hipEventDisableTiming) != hipSuccess) {
+        if (bt->stream) (void)hipStreamDestroy(bt->stream);
+        delete bt;
+        return fail(QCQP_E_DEVICE, "stream creation");
+    }
     (void)hipGetDevice(&bt->dev);
     bt->handles.assign(max_slots, nullptr);
     bt->finished.assign(max_slots, 0);
@@ -897,8 +975,9 @@ qcqp_status qcqp_batch_admit(qcqp_batch *bt, qcqp_handle *h, const double *x0, c
     if (free_slot < 0) return fail(QCQP_E_NO_ROOM, "no free slot");
     if (bt->budget && batch_resident(bt) + h->q_bytes + h->arena_bytes > bt->budget)
         return fail(QCQP_E_NO_ROOM, "HBM budget exhausted");
-    // the handle's own stream work must be ordered before the batch stream's
+    // the handle's own stream work, and the caller's writes of x0 / y0, come first
     HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(join_streams(bt->stream, bt->ustream, bt->ev_join));
     hipStream_t saved = h->stream;
     h->stream = bt->stream;
     qcqp_status st = load_start(h, x0, y0);
@@ -964,6 +1043,8 @@ static qcqp_status rebuild_tiles(qcqp_batch *bt)
                               bt->stream));
     bt->nlive = (int)live.size();
     bt->ntiles = (int)mixed.size();
+    if (bt->gexec) (void)hipGraphExecDestroy(bt->gexec);   // launch shapes changed
+    bt->gexec = nullptr;
     bt->pass_grid = pass_grid_for(bt->opt.spec_trials, (int)bt->opt.storage, bt->max_nw);
     bt->dirty = false;
     return QCQP_OK;
@@ -984,13 +1065,30 @@ qcqp_status qcqp_batch_step(qcqp_batch *bt, int64_t groups)
         }
     }
     if (bt->nlive > 0) {
-        for (int64_t g = 0; g < groups; ++g) {
-            hipError_t e = launch_group(bt->stream, bt->dslots, bt->dlive, bt->nlive, bt->dtiles, bt->ntiles,
-                                        bt->opt.spec_trials, (int)bt->opt.storage, bt->max_nblk,
-                                        bt->max_ny, bt->max_nw, bt->max_epi, bt->pass_grid, bt->nt,
-                                        timing ? bt->ev[2 * g] : nullptr, timing ? bt->ev[2 * g + 1] : nullptr);
-            if (e != hipSuccess) return fail(QCQP_E_DEVICE, "launch: %s", hipGetErrorString(e));
+        auto launch_chunk = [&](hipStream_t s, bool with_events) -> hipError_t {
+            for (int64_t g = 0; g < groups; ++g) {
+                hipError_t e = launch_group(s, bt->dslots, bt->dlive, bt->nlive, bt->dtiles, bt->ntiles,
+                                            bt->opt.spec_trials, (int)bt->opt.storage, bt->max_nblk,
+                                            bt->max_ny, bt->max_nw, bt->max_epi, bt->pass_grid, bt->nt,
+                                            with_events ? bt->ev[2 * g] : nullptr,
+                                            with_events ? bt->ev[2 * g + 1] : nullptr);
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
+        };
+        hipError_t e;
+        if (bt->opt.use_graphs && !timing) {
+            if (!bt->gexec || bt->gexec_groups != groups) {
+                if (bt->gexec) (void)hipGraphExecDestroy(bt->gexec);
+                bt->gexec = nullptr;
+                HIPCHK(capture_graph(bt->stream, [&](hipStream_t s) { return launch_chunk(s, false); }, &bt->gexec));
+                bt->gexec_groups = groups;
+            }
+            e = hipGraphLaunch(bt->gexec, bt->stream);
+        } else {
+            e = launch_chunk(bt->stream, timing);
         }
+        if (e != hipSuccess) return fail(QCQP_E_DEVICE, "launch: %s", hipGetErrorString(e));
     }
     HIPCHK(hipMemcpyAsync(bt->h_poll, bt->dslots, bt->max_slots * sizeof(Slot), hipMemcpyDeviceToHost, bt->stream));
     HIPCHK(hipStreamSynchronize(bt->stream));
@@ -1103,6 +1201,9 @@ qcqp_status qcqp_batch_destroy(qcqp_batch *bt)
     if (bt->dtiles) (void)hipFree(bt->dtiles);
     if (bt->dlive) (void)hipFree(bt->dlive);
     for (auto &e : bt->ev) (void)hipEventDestroy(e);
+    if (bt->gexec) (void)hipGraphExecDestroy(bt->gexec);
+    if (bt->ev_join) (void)hipEventDestroy(bt->ev_join);
+    if (bt->stream) (void)hipStreamDestroy(bt->stream);
     delete bt;
     return QCQP_OK;
 }

@@ -100,3 +100,31 @@ def test_admission_respects_hbm_budget():
     assert b2.admit(solvers[2]) is not None
     assert b2.admit(Solver(insts[0], **_opts(insts[0], "float64"))) is None   # no free slot
     b2.close()
+
+
+def test_adaptive_restarts_inside_a_batch():
+    """A slot whose schedule asks for the smoothed gap is parked, evaluated by the host-side
+    G_xi path and resumed; the result matches the same solve alone."""
+    from paper_2605_29291_amd import Batch, Solver
+    insts = [qi.random_qcqp(n, m, seed=7000 + n, shift=0.01) for n, m in ((120, 8), (90, 5))]
+    kw = dict(restart="adaptive", ada_first=5, ada_every=10, c_nm=0)
+    alone = []
+    for inst in insts:
+        s = Solver(inst, tau_bar=tau_bar_of(inst), gamma0=0.1, **kw)
+        x, y, info = s.solve()
+        assert info["gap_evals"] >= 1
+        alone.append((to_np(x), info))
+    b = Batch(max_slots=4, restart="adaptive")
+    slots = {b.admit(Solver(inst, tau_bar=tau_bar_of(inst), gamma0=0.1, **kw)): k
+             for k, inst in enumerate(insts)}
+    got = {}
+    while len(got) < len(insts):
+        b.step(4)
+        for slot in b.poll():
+            _, x, y, info = b.fetch(slot)
+            got[slots[slot]] = (to_np(x), info)
+    b.close()
+    for k in range(len(insts)):
+        np.testing.assert_array_equal(got[k][0], alone[k][0])
+        assert got[k][1]["gap_evals"] == alone[k][1]["gap_evals"]
+        assert got[k][1]["status"] == "ok"

@@ -147,3 +147,38 @@ def test_edge_cases_and_errors():
     s1 = _solver(one, tau_bar=1.0)
     x1, _, info1 = s1.solve()
     assert info1["status"] == "ok" and abs(to_np(x1)[0] - 10.0) < 1e-9
+
+
+def test_graph_replays_match_eager_launches():
+    """Chunks of trial groups replayed from a captured HIP graph give bitwise the eager result,
+    on every replay, with eager work and synchronisations between the replays."""
+    import torch
+    from paper_2605_29291_amd import Batch, Solver
+    inst = qi.random_qcqp(180, 9, seed=71, shift=0.01)
+    tb = tau_bar_of(inst)
+    eager = _solver(inst, **gpu_opts(tb, use_graphs=0, poll_every=8))
+    xe, ye, ie = eager.solve()
+    xe, ye = to_np(xe), to_np(ye)
+    g = _solver(inst, **gpu_opts(tb, use_graphs=1, poll_every=8))
+    rng = np.random.default_rng(0)
+    for rep in range(3):
+        announce(f"graph replay {rep}")
+        x, y, info = g.solve()
+        np.testing.assert_array_equal(to_np(x), xe)
+        np.testing.assert_array_equal(to_np(y), ye)
+        assert info["trials"] == ie["trials"] and info["q_passes"] == ie["q_passes"]
+        g.eval_operator(rng.uniform(-1, 1, inst.n))          # eager work between replays
+        torch.cuda.synchronize()
+    # batch: graph-captured steps against eager steps
+    res = []
+    for use in (0, 1):
+        b = Batch(max_slots=4, use_graphs=use)
+        s = _solver(inst, **gpu_opts(tb))
+        slot = b.admit(s)
+        while not b.poll():
+            b.step(3)
+        _, x, y, info = b.fetch(slot)
+        res.append((to_np(x), info["trials"]))
+        b.close()
+    np.testing.assert_array_equal(res[0][0], res[1][0])
+    np.testing.assert_array_equal(res[0][0], xe)
