@@ -105,7 +105,25 @@ __global__ void __launch_bounds__(STEP_BS) k_step(Slot *__restrict__ slots,
 #pragma unroll
     for (int b = 0; b < B; ++b) acc[b] = 0.0;
     if (j < n) {
-        for (int i = 1 + wave; i <= m; i += STEP_WAVES) {
+        // 4 matrices per step so 8 independent loads are in flight; the multiply-adds keep the
+        // ascending order of i
+        int i = 1 + wave;
+        for (; i + 3 * STEP_WAVES <= m; i += 4 * STEP_WAVES) {
+            double t[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const size_t o = (size_t)(i + u * STEP_WAVES) * n + j;
+                t[u] = U[o] + q[o];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int ii = i + u * STEP_WAVES;
+#pragma unroll
+                for (int b = 0; b < B; ++b) acc[b] = fma(ynew[b * ny + p + ii - 1], t[u], acc[b]);
+                kk = fma(ycur[p + ii - 1], t[u], kk);
+            }
+        }
+        for (; i <= m; i += STEP_WAVES) {
             const double t = U[(size_t)i * n + j] + q[(size_t)i * n + j];
 #pragma unroll
             for (int b = 0; b < B; ++b) acc[b] = fma(ynew[b * ny + p + i - 1], t, acc[b]);
@@ -376,74 +394,70 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
         return;
     }
 
-    // ---- 1. relative KKT residual of the iterate (x^k, y^k) ----
-    double tot[NPART];
+    // ---- 1+2. one fixed-order block reduction of everything the decision needs:
+    //   step partials (KKT pieces of the iterate, ||d_b||^2), ||min(lambda,-g)||^2,
+    //   ||([g]+, Ax-b)||^2, and per candidate 1/2 d'Q(lambda+)d terms, ||dG||^2, ||dy||^2 ----
+    constexpr int NR = NPART + 2 + 3 * B;
+    double r[NR];
 #pragma unroll
-    for (int f = 0; f < NPART; ++f) tot[f] = 0.0;
-    for (int blk = tid; blk < S->nblk_step; blk += STEP_BS) {
-#pragma unroll
-        for (int f = 0; f < NPART; ++f) tot[f] += S->part[(size_t)blk * NPART + f];
-    }
-    block_sum<NPART>(tot);
-    double kv[3] = {0.0, 0.0, 0.0};   // ||min(lambda,-g)||^2, ||([g]+, Ax-b)||^2, max violation
+    for (int f = 0; f < NR; ++f) r[f] = 0.0;
+    double mx = 0.0;
     {
+        const double *part = S->part;
+        const int nblk = S->nblk_step;
+        for (int blk = tid; blk < nblk; blk += STEP_BS) {
+#pragma unroll
+            for (int f = 0; f < NPART; ++f) r[f] += part[(size_t)blk * NPART + f];
+        }
         const double *G = S->G, *y = S->y;
-        double mx = 0.0;
         for (int l = tid; l < ny; l += STEP_BS) {
             const double gl = G[l];
             if (l < p) {
-                kv[1] += gl * gl;
+                r[NPART + 1] += gl * gl;
                 mx = fmax(mx, fabs(gl));
             } else {
                 const double lam = y[l];
                 const double mn = lam < -gl ? lam : -gl;
-                kv[0] += mn * mn;
+                r[NPART] += mn * mn;
                 if (gl > 0.0) {
-                    kv[1] += gl * gl;
+                    r[NPART + 1] += gl * gl;
                     mx = fmax(mx, gl);
                 }
             }
         }
-        kv[2] = mx;
-        // max is order independent; reuse the sum tree on the square-free value via a max pass
-        __shared__ double s_mx[STEP_BS];
-        s_mx[tid] = mx;
-        __syncthreads();
-        if (tid == 0) {
-            double mm = 0.0;
-            for (int t = 0; t < STEP_BS; ++t) mm = fmax(mm, s_mx[t]);
-            kv[2] = mm;
-        }
-        __syncthreads();
-        double kk2[2] = {kv[0], kv[1]};
-        block_sum<2>(kk2);
-        kv[0] = kk2[0];
-        kv[1] = kk2[1];
-    }
-
-    // ---- 2. test quantities per candidate ----
-    double tq[3 * B];   // quad, ||dG||^2, ||dy||^2
-#pragma unroll
-    for (int k = 0; k < 3 * B; ++k) tq[k] = 0.0;
-    {
-        const double *y = S->y;
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const double *e = S->e + b * (m + 1);
             const double *yc = S->yc[b];
+            const double *dg = S->dG[b];
+            double *t = r + NPART + 2 + 3 * b;
             for (int i = tid; i <= m; i += STEP_BS) {
                 const double wgt = (i == 0) ? 1.0 : yc[p + i - 1];
-                tq[3 * b] = fma(wgt, e[i], tq[3 * b]);
+                t[0] = fma(wgt, e[i], t[0]);
             }
-            const double *dg = S->dG[b];
             for (int l = tid; l < ny; l += STEP_BS) {
-                tq[3 * b + 1] = fma(dg[l], dg[l], tq[3 * b + 1]);
+                t[1] = fma(dg[l], dg[l], t[1]);
                 const double dy = yc[l] - y[l];
-                tq[3 * b + 2] = fma(dy, dy, tq[3 * b + 2]);
+                t[2] = fma(dy, dy, t[2]);
             }
         }
     }
-    block_sum<3 * B>(tq);
+    __shared__ double s_mx[STEP_BS];
+    s_mx[tid] = mx;
+    block_sum<NR>(r);              // includes the barrier that publishes s_mx
+    double tot[NPART], kv[3], tq[3 * B];
+#pragma unroll
+    for (int f = 0; f < NPART; ++f) tot[f] = r[f];
+    kv[0] = r[NPART];
+    kv[1] = r[NPART + 1];
+    kv[2] = 0.0;
+#pragma unroll
+    for (int k2 = 0; k2 < 3 * B; ++k2) tq[k2] = r[NPART + 2 + k2];
+    if (tid == 0) {
+        double mm = 0.0;
+        for (int t = 0; t < STEP_BS; ++t) mm = fmax(mm, s_mx[t]);
+        kv[2] = mm;
+    }
 
     if (tid == 0) {
         const double rel_dual = sqrt(tot[0]) / (1.0 + sqrt(tot[1]) + sqrt(tot[2]) + sqrt(tot[3]));

@@ -1,0 +1,96 @@
+"""Parity at the benchmark workloads' full sizes, in the launch configuration the benchmark uses.
+
+The oracle cannot run whole solves at these sizes within a test, so it checks what it can compute
+in one pass: every row of the operator (or the relative KKT residual of the GPU's solution, which
+needs one pass) on exactly the stored instance.
+  * n=4000, m=200, BF16 and FP16 stacks (6.4 GB): the GPU solution's relative KKT, evaluated by the
+    oracle in FP64 on the stored values, is <= 1e-6;
+  * kernel-learning QCQP, 8000 points (n=8001, m=5, Q_0 absent, p=1), FP32 and BF16: operator
+    parity (U, g, f, grad) at 1e-12;
+  * serving requests of the full size range, solved together in one batch: oracle KKT <= 1e-6.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_common import announce, oracle, qi, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _host_instance(inst):
+    import torch
+    Qh = inst.Q.cpu()
+    return qi.Instance(inst.n, inst.m, inst.p, Qh, inst.q, inst.c, inst.lb, inst.ub, inst.A, inst.b,
+                       inst.has_q0, inst.name)
+
+
+@pytest.mark.parametrize("storage", ["bfloat16", "float16"])
+def test_precision_workload_full_size_kkt(storage):
+    import torch
+    from paper_2605_29291_amd import Solver
+    announce(f"full size n=4000 m=200 {storage}")
+    sd = {"bfloat16": torch.bfloat16, "float16": torch.float16}[storage]
+    inst = qi.random_qcqp_torch(4000, 200, qi.config_seed(3), shift=0.01, device="cuda", store_dtype=sd)
+    s = Solver(inst, device=True, storage=storage, tau_bar=0.0, gamma0=0.1)
+    x, y, info = s.solve()
+    s.close()
+    assert info["status"] == "ok", info
+    host = _host_instance(inst)
+    del inst
+    torch.cuda.empty_cache()
+    announce("oracle KKT evaluation (one host pass over the stored stack)")
+    kk = oracle.kkt(oracle.Problem(host), to_np(x), to_np(y))
+    assert kk["rel_kkt"] <= 1e-6, kk
+    assert abs(kk["rel_kkt"] - info["rel_kkt"]) <= 1e-9
+
+
+@pytest.mark.parametrize("storage", ["float32", "bfloat16"])
+def test_kml_workload_full_size_operator(storage):
+    import torch
+    from paper_2605_29291_amd import Solver
+    announce(f"kml full size {storage}")
+    sd = {"float32": torch.float32, "bfloat16": torch.bfloat16}[storage]
+    inst = qi.kml_qcqp(npts=8000, seed=qi.config_seed(4), device="cuda", store_dtype=sd)
+    s = Solver(inst, device=True, storage=storage, tau_bar=1.0)
+    rng = np.random.default_rng(4)
+    x = np.concatenate([rng.uniform(0, 1, 8000), [3.0]])
+    y = np.concatenate([[0.3], rng.uniform(0, 2, 5)])
+    out = s.eval_operator(x, y)
+    s.close()
+    host = _host_instance(inst)
+    del inst
+    torch.cuda.empty_cache()
+    ref = oracle.operator(oracle.Problem(host), x, y)
+    U = to_np(out["U"])
+    assert np.max(np.abs(U - ref["U"])) <= 1e-12 * np.max(np.abs(ref["U"])) * 10
+    np.testing.assert_allclose(to_np(out["g"]), ref["G"][1:], rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(to_np(out["grad"]), ref["grad"], rtol=1e-11,
+                               atol=1e-12 * np.max(np.abs(ref["grad"])))
+
+
+def test_serving_requests_full_size_range_in_one_batch():
+    import torch
+    from paper_2605_29291_amd import Batch, Solver
+    trace = qi.serving_trace(6, qi.config_seed(5))
+    b = Batch(max_slots=8, storage="bfloat16")
+    slot_req = {}
+    insts = []
+    for k, r in enumerate(trace):
+        announce(f"request n={r['n']} m={r['m']}")
+        inst = qi.random_qcqp_torch(r["n"], r["m"], r["seed"], device="cuda", store_dtype=torch.bfloat16)
+        slot_req[b.admit(Solver(inst, device=True, storage="bfloat16", tau_bar=0.0, gamma0=0.1))] = k
+        insts.append(_host_instance(inst))
+        del inst
+    torch.cuda.empty_cache()
+    got = {}
+    while len(got) < len(trace):
+        b.step(4)
+        for slot in b.poll():
+            _, x, y, info = b.fetch(slot)
+            got[slot_req[slot]] = (to_np(x), to_np(y), info)
+    b.close()
+    for k, host in enumerate(insts):
+        x, y, info = got[k]
+        assert info["status"] == "ok"
+        kk = oracle.kkt(oracle.Problem(host), x, y)
+        assert kk["rel_kkt"] <= 1e-6, (k, kk)
