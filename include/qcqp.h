@@ -78,14 +78,18 @@ typedef struct {
 /* Method parameters (Algorithm 1, the APDB-yx rules of §3.2, Algorithm 2, eq. (ada_restart)).
  * qcqp_options_default fills the §5 settings for rAPDB-yx, non-monotone. */
 typedef struct {
-    qcqp_variant variant;      /* only QCQP_YX runs on the GPU; QCQP_XY returns QCQP_E_INVALID */
+    qcqp_variant variant;      /* QCQP_YX: eq. (apdb-yx-y) of §3.2 (dual step first, default);
+                                  QCQP_XY: Algorithm 1 (primal step first, momentum on
+                                  grad_x Phi, test function of eq. (backtracking)) */
     int c_nm;                  /* 0 monotone, 1 non-monotone step rule (Remark in §3.1) */
     double eta;                /* backtracking factor, in (0,1) (0.7) */
     double tau_bar;            /* initial primal step; <= 0: 1/||Q_0||_2 estimated on the GPU
                                   (or 1/max_i||Q_i||_2 when Q_0 is absent) */
     double gamma0;             /* sigma/tau ratio gamma_0 > 0 (0.1) */
     double mu;                 /* strong-convexity modulus of f, >= 0 (0) */
-    double c_alpha, c_beta, delta;  /* yx: c_alpha > 0, delta in [0,1), c_alpha + delta <= 1 */
+    double c_alpha, c_beta, delta;  /* yx: c_alpha > 0, delta in [0,1), c_alpha + delta <= 1
+                                       (c_beta unused); xy: c_alpha > 0, c_beta > 0, delta >= 0,
+                                       c_alpha + c_beta + delta < 1 (§5 uses 0.25, 0.3, 0.4) */
     qcqp_restart restart;
     int64_t restart_every;     /* K-hat for fixed restarts (400) */
     int restart_from_average;  /* 0: restart at the last iterate (as in §5); 1: Algorithm 2's average */
@@ -132,14 +136,15 @@ void qcqp_options_default(qcqp_options *o);
 const char *qcqp_last_error(void);
 
 /* Create a handle: validate the problem and options (Assumption on the sets in §2:
- * lb <= ub finite; eta in (0,1); yx parameter ranges of Lemma (APDB-yx convergence) in §3.2),
+ * lb <= ub finite; eta in (0,1); the parameter ranges of Algorithm 1 (xy) or of Lemma
+ * (APDB-yx convergence) in §3.2 (yx)),
  * allocate device memory, copy the data and convert Q to options.storage once with
  * round-to-nearest-even.  Errors: QCQP_E_INVALID (nothing allocated), QCQP_E_NOMEM,
  * QCQP_E_DEVICE.  *out is set only on success. */
 qcqp_status qcqp_create(const qcqp_problem *prob, const qcqp_options *opt, qcqp_handle **out);
 
-/* Run rAPDB (Algorithm 2 around APDB-yx) from x0 (n; NULL -> Pi_X(0)) and y0 (p+m in the
- * order (v, lambda); NULL -> 0; lambda is projected onto R^m_+) until the relative KKT
+/* Run rAPDB (Algorithm 2 around APDB-yx or APDB-xy) from x0 (n; NULL -> Pi_X(0)) and y0
+ * (p+m in the order (v, lambda); NULL -> 0; lambda is projected onto R^m_+) until the relative KKT
  * residual is <= tol or max_iter iterations.  Writes x_out (n) and y_out (p+m, may be NULL),
  * and *info when non-NULL.  Returns QCQP_OK, QCQP_E_NOT_CONVERGED (outputs still written),
  * QCQP_E_NUMERICAL or an error code.  The iteration is device-resident: the host only

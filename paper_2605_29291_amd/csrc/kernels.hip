@@ -5,7 +5,9 @@
 //   eq. (qcqp-coupling), §2.1 .... Phi, grad_x Phi = Q_0x+q_0+sum lambda_i (Q_ix+q_i)+A'v,
 //                                   grad_y Phi = (Ax-b, g(x))
 //   eq. (apdb-yx-y), §3.2 ......... APDB-yx updates and its test function E_k
-//   Algorithm 1, §3 ............... backtracking loop, tau/gamma rule, ergodic averages
+//   Algorithm 1, §3 ............... APDB-xy updates and the test function E_k of
+//                                   eq. (backtracking); backtracking loop, tau/gamma rule,
+//                                   ergodic averages (both variants)
 //   Remark (non-monotone), §3.1 ... c_nm = 1 step rule
 //   Algorithm 2, §4.1 ............. fixed-frequency restarts
 //   Theorem (metric subregularity), §4.3 ... residual r(x,v,lambda) behind the KKT stop test
@@ -64,7 +66,7 @@ __global__ void __launch_bounds__(STEP_BS) k_step(Slot *__restrict__ slots,
                                                   const int *__restrict__ live)
 {
     Slot *S = slots + live[blockIdx.y];
-    if (S->status != ST_RUNNING || S->mode != MODE_TRIAL) return;
+    if (S->variant != VAR_YX || S->status != ST_RUNNING || S->mode != MODE_TRIAL) return;
     if ((int)blockIdx.x >= S->nblk_step) return;
     const int n = S->n, m = S->m, p = S->p, ny = S->ny;
     extern __shared__ double sm[];
@@ -167,6 +169,95 @@ __global__ void __launch_bounds__(STEP_BS) k_step(Slot *__restrict__ slots,
             part[4 + b] = d * d;
         }
         const double gk = u0 + kk + av;
+        const double r = xj - clipd(xj - gk, lo, hi);
+        part[0] = r * r;
+        part[1] = u0 * u0;
+        part[2] = kk * kk;
+        part[3] = av * av;
+    }
+    block_sum<NPART>(part);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int f = 0; f < NPART; ++f) S->part[(size_t)blockIdx.x * NPART + f] = part[f];
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// APDB-xy step kernel (Algorithm 1): the primal step comes first, with momentum on grad_x Phi:
+//   sigma = gamma tau, theta = sigma_{k-1}/sigma,
+//   s = (1+theta) grad_x Phi(x^k,y^k) - theta grad_x Phi(x^{k-1},y^{k-1}),
+//   x+ = Pi_X(x - tau s),
+// for B candidate step sizes.  grad_x Phi(x^k,y^k) is recomputed from the cached U^k (it is the
+// gradient the KKT residual of the iterate needs anyway) and kept in gxk; gxp holds the one of
+// the previous iterate, except at the first iteration of an epoch, where x^{-1} = x^0.
+
+template <int B>
+__global__ void __launch_bounds__(STEP_BS) k_step_xy(Slot *__restrict__ slots,
+                                                     const int *__restrict__ live)
+{
+    Slot *S = slots + live[blockIdx.y];
+    if (S->variant != VAR_XY || S->status != ST_RUNNING || S->mode != MODE_TRIAL) return;
+    if ((int)blockIdx.x >= S->nblk_step) return;
+    const int n = S->n, m = S->m, p = S->p, ny = S->ny;
+    extern __shared__ double sm[];
+    double *ycur = sm;
+    __shared__ double s_acc[STEP_WAVES - 1][STEP_COLS];
+    double tau_b[B], th_b[B];
+    {
+        double t = S->tau;
+        const double gam = S->gam, sp = S->sig_prev, eta = S->eta;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            tau_b[b] = t;
+            th_b[b] = sp / (gam * t);
+            t *= eta;
+        }
+    }
+    const double *y = S->y;
+    for (int l = threadIdx.x; l < ny; l += STEP_BS) ycur[l] = y[l];
+    __syncthreads();
+    const int lane = threadIdx.x % STEP_COLS, wave = threadIdx.x / STEP_COLS;
+    const int j = blockIdx.x * STEP_COLS + lane;
+    const double *U = S->U, *q = S->q;
+    double kk = 0.0;
+    if (j < n) {
+        int i = 1 + wave;
+        for (; i + 3 * STEP_WAVES <= m; i += 4 * STEP_WAVES) {
+            double t[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const size_t o = (size_t)(i + u * STEP_WAVES) * n + j;
+                t[u] = U[o] + q[o];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) kk = fma(ycur[p + i + u * STEP_WAVES - 1], t[u], kk);
+        }
+        for (; i <= m; i += STEP_WAVES)
+            kk = fma(ycur[p + i - 1], U[(size_t)i * n + j] + q[(size_t)i * n + j], kk);
+    }
+    if (wave > 0) s_acc[wave - 1][lane] = kk;
+    __syncthreads();
+    double part[NPART];
+#pragma unroll
+    for (int f = 0; f < NPART; ++f) part[f] = 0.0;
+    if (wave == 0 && j < n) {
+#pragma unroll
+        for (int w = 1; w < STEP_WAVES; ++w) kk += s_acc[w - 1][lane];
+        const double u0 = U[j] + q[j];
+        double av = 0.0;
+        for (int l = 0; l < p; ++l) av = fma(ycur[l], S->A[(size_t)l * n + j], av);
+        const double gk = u0 + kk + av;                 // grad_x Phi(x^k, y^k)
+        const double gp = S->ke == 0 ? gk : S->gxp[j];   // grad_x Phi(x^{k-1}, y^{k-1})
+        S->gxk[j] = gk;
+        const double xj = S->x[j], lo = S->lb[j], hi = S->ub[j];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const double sdir = (1.0 + th_b[b]) * gk - th_b[b] * gp;
+            const double xn = clipd(xj - tau_b[b] * sdir, lo, hi);
+            S->xc[b][j] = xn;
+            const double d = xn - xj;
+            part[4 + b] = d * d;
+        }
         const double r = xj - clipd(xj - gk, lo, hi);
         part[0] = r * r;
         part[1] = u0 * u0;
@@ -307,6 +398,110 @@ __global__ void __launch_bounds__(STEP_BS) k_epi(Slot *__restrict__ slots,
 }
 
 // ---------------------------------------------------------------------------------------
+// APDB-xy post kernel (Algorithm 1), after the pass and the epilogue have given
+// U+ = [Q_i x+] and grad_y Phi(x+) = (Ax+ - b, g(x+)) of every candidate:
+//   y+ = Pi_Y(y + sigma grad_y Phi(x+))   (lambda >= 0, v free),
+// and, per column j, the two gradient differences of the test function E_k:
+//   a_j = [grad_x Phi(x+,y+) - grad_x Phi(x+,y)]_j = sum_i (l+_i - l_i)(Q_i x+ + q_i)_j + [A'(v+ - v)]_j
+//   c_j = [grad_x Phi(x+,y) - grad_x Phi(x,y)]_j  = (Q_0 d)_j + sum_i l_i (Q_i d)_j ,  d = x+ - x,
+// with Q_i d = U+_i - U_i (direct pass) or the pass output W_i itself (incremental pass).
+// Per block: |a|^2 and |c|^2 of its columns, per candidate.
+
+template <int B>
+__global__ void __launch_bounds__(STEP_BS) k_post_xy(Slot *__restrict__ slots,
+                                                     const int *__restrict__ live)
+{
+    Slot *S = slots + live[blockIdx.y];
+    if (S->variant != VAR_XY || S->status != ST_RUNNING || S->mode != MODE_TRIAL) return;
+    if ((int)blockIdx.x >= S->nblk_step) return;
+    const int n = S->n, m = S->m, p = S->p, ny = S->ny;
+    extern __shared__ double sm[];
+    double *ycur = sm;
+    double *ynew = sm + ny;
+    __shared__ double s_acc[STEP_WAVES - 1][2 * B][STEP_COLS];
+    double sig_b[B];
+    {
+        double t = S->tau;
+        const double gam = S->gam, eta = S->eta;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            sig_b[b] = gam * t;
+            t *= eta;
+        }
+    }
+    const double *y = S->y;
+    for (int l = threadIdx.x; l < ny; l += STEP_BS) {
+        const double yl = y[l];
+        ycur[l] = yl;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            double v = yl + sig_b[b] * S->Gc[b][l];
+            if (l >= p) v = v < 0.0 ? 0.0 : v;
+            ynew[b * ny + l] = v;
+            if (blockIdx.x == 0) S->yc[b][l] = v;
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x % STEP_COLS, wave = threadIdx.x / STEP_COLS;
+    const int j = blockIdx.x * STEP_COLS + lane;
+    const bool inc = S->incremental != 0;
+    const double *U = S->U, *q = S->q;
+    double a[B], c[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) a[b] = c[b] = 0.0;
+    if (j < n) {
+        for (int i = 1 + wave; i <= m; i += STEP_WAVES) {
+            const size_t o = (size_t)i * n + j;
+            const double u = U[o], qv = q[o];
+            const double lam = ycur[p + i - 1];
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const double un = S->Uc[b][o];
+                const double du = inc ? S->W[b][o] : un - u;
+                a[b] = fma(ynew[b * ny + p + i - 1] - lam, un + qv, a[b]);
+                c[b] = fma(lam, du, c[b]);
+            }
+        }
+    }
+    if (wave > 0) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            s_acc[wave - 1][2 * b][lane] = a[b];
+            s_acc[wave - 1][2 * b + 1][lane] = c[b];
+        }
+    }
+    __syncthreads();
+    double part[2 * B];
+#pragma unroll
+    for (int f = 0; f < 2 * B; ++f) part[f] = 0.0;
+    if (wave == 0 && j < n) {
+#pragma unroll
+        for (int w = 1; w < STEP_WAVES; ++w) {
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                a[b] += s_acc[w - 1][2 * b][lane];
+                c[b] += s_acc[w - 1][2 * b + 1][lane];
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const double c0 = inc ? S->W[b][j] : S->Uc[b][j] - U[j];
+            const double cb = c0 + c[b];
+            double ab = a[b];
+            for (int l = 0; l < p; ++l)
+                ab = fma(ynew[b * ny + l] - ycur[l], S->A[(size_t)l * n + j], ab);
+            part[2 * b] = ab * ab;
+            part[2 * b + 1] = cb * cb;
+        }
+    }
+    block_sum<2 * B>(part);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int f = 0; f < 2 * B; ++f) S->part2[(size_t)blockIdx.x * NPART2 + f] = part[f];
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // control kernel (one block per slot, FP64)
 
 __device__ __forceinline__ void swap_ptr(double *&a, double *&b)
@@ -346,7 +541,9 @@ __device__ void restart_epoch(Slot *S, int rs)
         S->tau_prev = S->tau_bar;
         S->sig_prev = S->gamma0 * S->tau_bar;
         S->gam = S->gamma0;
-        S->alpha_k = S->c_alpha / S->sig_prev;
+        // alpha_0, beta_0 from tau_{-1}, sigma_{-1}
+        S->alpha_k = S->c_alpha / (S->variant == VAR_XY ? S->tau_prev : S->sig_prev);
+        S->beta_k = S->gamma0 * S->c_beta / S->sig_prev;
         S->T = 0.0;
         S->ke = 0;
         S->restarts += 1;
@@ -425,18 +622,29 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
                 }
             }
         }
+        const bool xy = S->variant == VAR_XY;
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            const double *e = S->e + b * (m + 1);
             const double *yc = S->yc[b];
-            const double *dg = S->dG[b];
             double *t = r + NPART + 2 + 3 * b;
-            for (int i = tid; i <= m; i += STEP_BS) {
-                const double wgt = (i == 0) ? 1.0 : yc[p + i - 1];
-                t[0] = fma(wgt, e[i], t[0]);
+            if (xy) {
+                // xy: |a_b|^2 and |c_b|^2 from the post kernel's block partials
+                const double *p2 = S->part2;
+                for (int blk = tid; blk < nblk; blk += STEP_BS) {
+                    t[0] += p2[(size_t)blk * NPART2 + 2 * b];
+                    t[1] += p2[(size_t)blk * NPART2 + 2 * b + 1];
+                }
+            } else {
+                // yx: sum_i w_i d'(Q_i d) with w = (1, lambda+), and |dG|^2
+                const double *e = S->e + b * (m + 1);
+                const double *dg = S->dG[b];
+                for (int i = tid; i <= m; i += STEP_BS) {
+                    const double wgt = (i == 0) ? 1.0 : yc[p + i - 1];
+                    t[0] = fma(wgt, e[i], t[0]);
+                }
+                for (int l = tid; l < ny; l += STEP_BS) t[1] = fma(dg[l], dg[l], t[1]);
             }
             for (int l = tid; l < ny; l += STEP_BS) {
-                t[1] = fma(dg[l], dg[l], t[1]);
                 const double dy = yc[l] - y[l];
                 t[2] = fma(dy, dy, t[2]);
             }
@@ -492,15 +700,26 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
         if (dec == -1) {
             double t = S->tau;
             const double gam = S->gam, sp = S->sig_prev, eta = S->eta;
+            const bool xy = S->variant == VAR_XY;
             for (int b = 0; b < B; ++b) {
                 const double sig = gam * t;
                 const double th = sp / sig;
-                const double alpha_next = S->c_alpha / sig;          // alpha_{k+1} = c_a / sigma_k
-                const double dd = tot[4 + b], dg2 = tq[3 * b + 1], dy2 = tq[3 * b + 2];
+                const double dd = tot[4 + b], dy2 = tq[3 * b + 2];
                 const double Dp = 0.5 * dd, Dd = 0.5 * dy2;
-                const double quad = 0.5 * tq[3 * b];                  // 1/2 d'Q(lambda+)d
-                const double E = quad - Dp / t + dg2 / (2.0 * alpha_next) -
-                                 (1.0 / sig - th * S->alpha_k) * Dd;
+                double E;
+                if (xy) {
+                    // Algorithm 1: alpha_{k+1} = c_a / tau_k, beta_{k+1} = gamma_0 c_b / sigma_k;
+                    // E_k of eq. (backtracking) with the two gradient differences of k_post_xy
+                    const double alpha_next = S->c_alpha / t;
+                    const double beta_next = S->gamma0 * S->c_beta / sig;
+                    E = tq[3 * b] / (2.0 * alpha_next) - Dd / sig + tq[3 * b + 1] / (2.0 * beta_next) -
+                        (1.0 / t - th * (S->alpha_k + S->beta_k)) * Dp;
+                } else {
+                    const double alpha_next = S->c_alpha / sig;      // alpha_{k+1} = c_a / sigma_k
+                    const double quad = 0.5 * tq[3 * b];              // 1/2 d'Q(lambda+)d
+                    E = quad - Dp / t + tq[3 * b + 1] / (2.0 * alpha_next) -
+                        (1.0 / sig - th * S->alpha_k) * Dd;
+                }
                 const double rhs = -(S->delta / t) * Dp - (S->delta / sig) * Dd;
                 if (E <= rhs) {
                     dec = b;
@@ -568,7 +787,15 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
         S->Gc[dec] = gold;
         S->f = S->G[ny];
         S->fresh = (S->dtype == DT_F64 && !S->incremental) ? 1 : 0;
-        S->alpha_k = S->c_alpha / sig;
+        if (S->variant == VAR_XY) {
+            // grad_x Phi(x^k, y^k) becomes the previous iterate's; the next step kernel
+            // recomputes the new one from U
+            swap_ptr(S->gxp, S->gxk);
+            S->alpha_k = S->c_alpha / t;
+            S->beta_k = S->gamma0 * S->c_beta / sig;
+        } else {
+            S->alpha_k = S->c_alpha / sig;
+        }
         S->sig_prev = sig;
         S->tau_prev = t;
         S->tau = tau_next;
@@ -1007,28 +1234,32 @@ hipError_t launch_gap_finish(hipStream_t s, int n, const double *grad, const dou
 
 template <int B>
 static hipError_t group_b(hipStream_t s, Slot *slots, const int *live, int nslots, const Tile *tiles, int ntiles,
-                          int dtype, int max_nblk_step, int max_ny, int max_nw, int max_epi,
+                          int dtype, int variants, int max_nblk_step, int max_ny, int max_nw, int max_epi,
                           int pass_grid, int nt, hipEvent_t ev0, hipEvent_t ev1)
 {
     const size_t step_lds = (size_t)(B + 1) * (size_t)(max_ny > 0 ? max_ny : 1) * sizeof(double);
-    k_step<B><<<dim3(max_nblk_step, nslots), STEP_BS, step_lds, s>>>(slots, live);
+    const dim3 vgrid(max_nblk_step, nslots);
+    if (variants & HAS_YX) k_step<B><<<vgrid, STEP_BS, step_lds, s>>>(slots, live);
+    if (variants & HAS_XY) k_step_xy<B><<<vgrid, STEP_BS, step_lds, s>>>(slots, live);
     if (ev0) (void)hipEventRecord(ev0, s);
     (void)launch_pass_only(s, slots, tiles, ntiles, B, dtype, max_nw, pass_grid, nt);
     if (ev1) (void)hipEventRecord(ev1, s);
     k_epi<B><<<dim3(max_epi, nslots), STEP_BS, 0, s>>>(slots, live);
+    if (variants & HAS_XY) k_post_xy<B><<<vgrid, STEP_BS, step_lds, s>>>(slots, live);
     k_ctrl<B><<<nslots, STEP_BS, 0, s>>>(slots, live);
     return hipGetLastError();
 }
 
 hipError_t launch_group(hipStream_t s, Slot *slots, const int *live, int nslots, const Tile *tiles,
-                        int ntiles, int B, int dtype, int max_nblk_step, int max_ny, int max_nw,
-                        int max_epi, int pass_grid, int nt, hipEvent_t ev0, hipEvent_t ev1)
+                        int ntiles, int B, int dtype, int variants, int max_nblk_step, int max_ny,
+                        int max_nw, int max_epi, int pass_grid, int nt, hipEvent_t ev0,
+                        hipEvent_t ev1)
 {
     switch (B) {
-    case 1: return group_b<1>(s, slots, live, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
-    case 2: return group_b<2>(s, slots, live, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
-    case 3: return group_b<3>(s, slots, live, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
-    default: return group_b<4>(s, slots, live, nslots, tiles, ntiles, dtype, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
+    case 1: return group_b<1>(s, slots, live, nslots, tiles, ntiles, dtype, variants, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
+    case 2: return group_b<2>(s, slots, live, nslots, tiles, ntiles, dtype, variants, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
+    case 3: return group_b<3>(s, slots, live, nslots, tiles, ntiles, dtype, variants, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
+    default: return group_b<4>(s, slots, live, nslots, tiles, ntiles, dtype, variants, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
     }
 }
 

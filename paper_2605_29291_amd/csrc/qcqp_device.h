@@ -1,12 +1,15 @@
 // Device-side data layout shared by the HIP kernels and the host runtime of the rAPDB library.
 //
-// One "slot" is one resident QCQP solve.  A trial group (one backtracking test of APDB-yx,
-// §3.2, for every running slot) is four launches on one stream:
-//   k_step  : dual step + cone projection (eq. (apdb-yx-y)), primal step + box projection,
-//             for spec_trials candidate step sizes tau * eta^b; KKT partials of the iterate;
+// One "slot" is one resident QCQP solve.  A trial group (one backtracking test for every
+// running slot) is four launches on one stream (five when a slot runs APDB-xy):
+//   k_step  : APDB-yx (eq. (apdb-yx-y), §3.2): dual step + cone projection, then primal step +
+//             box projection, for spec_trials candidate step sizes tau * eta^b;
+//   k_step_xy: APDB-xy (Algorithm 1): primal step with momentum on grad_x Phi + box projection;
+//             both compute the KKT partials of the iterate;
 //   k_pass  : the Q-stack pass -- one streamed GEMV over the stacked ((m+1) n) x n matrix per
 //             slot, all candidates at once, x (or the step d) staged in LDS;
 //   k_epi   : per-matrix dot products (g_i, f, d'(Q_i d)) with fixed-order block reductions;
+//   k_post_xy: APDB-xy only: dual step at the new x and the gradient differences of its E_k;
 //   k_ctrl  : FP64 test E_k <= rhs per candidate in order, acceptance, step-size/momentum/
 //             averaging bookkeeping (Algorithm 1), fixed restarts (Algorithm 2), KKT stop.
 // The host never reads per-trial data: it enqueues groups and polls a status word.
@@ -19,6 +22,7 @@ namespace qcqp {
 
 constexpr int MAXB = 4;            // max speculative candidates per pass
 constexpr int NPART = 4 + MAXB;    // step-kernel partials per block: rx2, s0, s1, s2, dd[b]
+constexpr int NPART2 = 2 * MAXB;   // xy post-kernel partials per block: |a_b|^2, |c_b|^2
 constexpr int STEP_BS = 256;       // threads per block of the vector kernels
 constexpr int STEP_COLS = 64;      // columns per step-kernel block (one per lane of a wave)
 constexpr int STEP_WAVES = STEP_BS / STEP_COLS;   // waves splitting the matrices of a column
@@ -40,15 +44,20 @@ enum SlotMode : int32_t {
 
 enum StoreType : int32_t { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2, DT_F16 = 3 };
 
+enum Variant : int32_t { VAR_YX = 0, VAR_XY = 1 };
+
+// bit mask of the variants present among the slots of a launch
+constexpr int HAS_YX = 1, HAS_XY = 2;
+
 struct Slot {
     // ---- constants (set at admission) ----
     int32_t n, m, p, ny;          // ny = p + m
     int32_t nq, has_q0;           // stored matrices nq = m + has_q0
     int32_t ld, dtype;            // row stride (elements) and storage type of Q
     int32_t c_nm, restart, restart_from_avg, incremental;
-    int32_t B, nblk_step, nw, pad0;   // nw = n rounded up to the pass vector width
+    int32_t B, nblk_step, nw, variant;   // nw = n rounded up to the pass vector width
     int64_t restart_every, ada_first, ada_every, max_iter;
-    double eta, tau_bar, gamma0, mu, c_alpha, delta, tol, q_restart;
+    double eta, tau_bar, gamma0, mu, c_alpha, c_beta, delta, tol, q_restart;
     double cnorm, bnorm;          // ||c_{1..m}||, ||b||  (KKT scales)
     const void *Q;
     const double *q, *c, *A, *b, *lb, *ub;
@@ -62,8 +71,10 @@ struct Slot {
     double *e;                    // MAXB x (m+1): d_b'(Q_i d_b)
     double *cx, *cy;              // weighted sums for the ergodic average
     double *part;                 // nblk_step x NPART step partials
+    double *gxk, *gxp;            // xy: grad_x Phi at (x^k, y^k) and at (x^{k-1}, y^{k-1}), n
+    double *part2;                // xy: nblk_step x NPART2 post-kernel partials
     // ---- mutable scalars ----
-    double tau, tau_prev, sig_prev, gam, sig0, alpha_k, T;
+    double tau, tau_prev, sig_prev, gam, sig0, alpha_k, beta_k, T;
     double kkt[4];                // rel_kkt, rel_dual, rel_pri, rel_comp of the iterate
     double f, maxviol;
     double Gref, last_gap;
@@ -81,10 +92,11 @@ struct Tile {
 };
 
 // ---- launch wrappers (kernels.hip) ----
-// one trial group for the slots listed in live[0..nslots)
+// one trial group for the slots listed in live[0..nslots); variants = HAS_YX | HAS_XY mask
 hipError_t launch_group(hipStream_t s, Slot *slots, const int *live, int nslots, const Tile *tiles,
-                        int ntiles, int B, int dtype, int max_nblk_step, int max_ny, int max_nw,
-                        int max_epi, int pass_grid, int nt, hipEvent_t ev0, hipEvent_t ev1);
+                        int ntiles, int B, int dtype, int variants, int max_nblk_step, int max_ny,
+                        int max_nw, int max_epi, int pass_grid, int nt, hipEvent_t ev0,
+                        hipEvent_t ev1);
 hipError_t launch_pass_only(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles, int B,
                             int dtype, int max_nw, int pass_grid, int nt);
 // persistent pass grid: resident blocks per CU of k_pass for this configuration

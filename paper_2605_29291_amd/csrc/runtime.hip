@@ -3,7 +3,8 @@
 //
 // Paper: "Restarted Accelerated Primal-Dual Algorithms with Adaptive Stepsizes for Nonlinear
 // Conic Constrained Convex Optimization" (arXiv 2605.29291); the method is Algorithm 2
-// (rAPDB) around the APDB-yx routine of §3.2; see kernels.hip for the per-kernel mapping.
+// (rAPDB) around the APDB-yx routine of §3.2 or the APDB-xy routine of Algorithm 1; see
+// kernels.hip for the per-kernel mapping.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -179,6 +180,7 @@ struct qcqp_batch {
     int *dlive = nullptr;                 // device list of live slot ids (max_slots entries)
     int nlive = 0;
     int ntiles = 0, max_nblk = 1, max_ny = 1, max_nw = 2, max_epi = 1;
+    int variants = HAS_YX;                // HAS_YX | HAS_XY over the live slots
     int pass_grid = 1, nt = 0;
     bool dirty = true;
     // pass timing (options.timing): kernel seconds and algorithmic bytes streamed
@@ -228,14 +230,20 @@ void qcqp_options_default(qcqp_options *o)
 
 static qcqp_status validate_options(const qcqp_options *o)
 {
-    if (o->variant != QCQP_YX)
-        return fail(QCQP_E_INVALID, "only the APDB-yx routine runs on the GPU (variant=%d)", (int)o->variant);
+    if (o->variant != QCQP_YX && o->variant != QCQP_XY)
+        return fail(QCQP_E_INVALID, "unknown variant %d", (int)o->variant);
     if (!(o->eta > 0.0 && o->eta < 1.0)) return fail(QCQP_E_INVALID, "eta must lie in (0,1)");
     if (!(o->gamma0 > 0.0) || !std::isfinite(o->gamma0)) return fail(QCQP_E_INVALID, "gamma0 must be > 0");
     if (!(o->tau_bar >= 0.0) || !std::isfinite(o->tau_bar)) return fail(QCQP_E_INVALID, "tau_bar must be >= 0");
     if (!(o->mu >= 0.0)) return fail(QCQP_E_INVALID, "mu must be >= 0");
-    if (!(o->c_alpha > 0.0 && o->delta >= 0.0 && o->delta < 1.0 && o->c_alpha + o->delta <= 1.0))
+    if (o->variant == QCQP_YX &&
+        !(o->c_alpha > 0.0 && o->delta >= 0.0 && o->delta < 1.0 && o->c_alpha + o->delta <= 1.0))
         return fail(QCQP_E_INVALID, "APDB-yx needs c_alpha > 0, delta in [0,1), c_alpha + delta <= 1");
+    // Algorithm 1 admits c_alpha, c_beta >= 0; a zero one divides a generally nonzero squared
+    // gradient difference by alpha = 0 or beta = 0, and no trial could pass
+    if (o->variant == QCQP_XY &&
+        !(o->c_alpha > 0.0 && o->c_beta > 0.0 && o->delta >= 0.0 && o->c_alpha + o->c_beta + o->delta < 1.0))
+        return fail(QCQP_E_INVALID, "APDB-xy needs c_alpha > 0, c_beta > 0, delta >= 0, c_alpha + c_beta + delta < 1");
     if (o->c_nm != 0 && o->c_nm != 1) return fail(QCQP_E_INVALID, "c_nm must be 0 or 1");
     if (o->restart < QCQP_RESTART_NONE || o->restart > QCQP_RESTART_ADAPTIVE)
         return fail(QCQP_E_INVALID, "unknown restart mode");
@@ -452,6 +460,11 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
     plan.push_back({&S.cx, n});
     plan.push_back({&S.cy, ny + 1});
     plan.push_back({&S.part, (int64_t)h->nblk_step * NPART});
+    if (o.variant == QCQP_XY) {
+        plan.push_back({&S.gxk, n});
+        plan.push_back({&S.gxp, n});
+        plan.push_back({&S.part2, (int64_t)h->nblk_step * NPART2});
+    }
     plan.push_back({&h->d_ueval, U1});
     plan.push_back({&h->d_geval, ny + 1});
     plan.push_back({&h->d_grad, n});
@@ -518,9 +531,11 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
     S.nq = (int32_t)nq; S.has_q0 = has_q0; S.ld = (int32_t)h->ld; S.dtype = h->dtype;
     S.c_nm = o.c_nm; S.restart = (int32_t)o.restart; S.restart_from_avg = o.restart_from_average ? 1 : 0;
     S.incremental = h->incremental; S.B = B; S.nblk_step = h->nblk_step; S.nw = (int32_t)h->nw;
+    S.variant = o.variant == QCQP_XY ? VAR_XY : VAR_YX;
     S.restart_every = o.restart_every; S.ada_first = o.ada_first; S.ada_every = o.ada_every;
     S.max_iter = o.max_iter;
-    S.eta = o.eta; S.gamma0 = o.gamma0; S.mu = o.mu; S.c_alpha = o.c_alpha; S.delta = o.delta;
+    S.eta = o.eta; S.gamma0 = o.gamma0; S.mu = o.mu; S.c_alpha = o.c_alpha; S.c_beta = o.c_beta;
+    S.delta = o.delta;
     S.tol = o.tol; S.q_restart = o.q_restart;
     double cn = 0.0, bn = 0.0;
     for (int64_t i = 1; i <= m; ++i) cn += hc[i] * hc[i];
@@ -570,7 +585,9 @@ static void reset_run_scalars(Slot &S)
     S.sig_prev = S.gamma0 * S.tau_bar;
     S.gam = S.gamma0;
     S.sig0 = 0.0;
-    S.alpha_k = S.c_alpha / S.sig_prev;
+    // alpha_0, beta_0 from tau_{-1}, sigma_{-1} (Algorithm 1, first line)
+    S.alpha_k = S.c_alpha / (S.variant == VAR_XY ? S.tau_prev : S.sig_prev);
+    S.beta_k = S.gamma0 * S.c_beta / S.sig_prev;
     S.T = 0.0;
     for (double &v : S.kkt) v = NAN;
     S.f = NAN;
@@ -672,7 +689,7 @@ qcqp_status qcqp_solve(qcqp_handle *h, const double *x0, const double *y0, doubl
     auto launch_chunk = [&](hipStream_t s, bool with_events) -> hipError_t {
         for (int64_t g = 0; g < poll; ++g) {
             hipError_t e = launch_group(s, h->dslot, h->dlive0, 1, h->dtiles, ntiles, h->B, h->dtype,
-                                        h->nblk_step, (int)std::max<int64_t>(h->ny, 1), (int)h->nw,
+                                        h->hslot.variant == VAR_XY ? HAS_XY : HAS_YX, h->nblk_step, (int)std::max<int64_t>(h->ny, 1), (int)h->nw,
                                         (int)(h->m + 1 + h->p), h->pass_grid, h->nt,
                                         with_events ? ev[2 * g] : nullptr,
                                         with_events ? ev[2 * g + 1] : nullptr);
@@ -1007,6 +1024,7 @@ static qcqp_status rebuild_tiles(qcqp_batch *bt)
     bt->max_ny = 1;
     bt->max_nw = 2;
     bt->max_epi = 1;
+    bt->variants = 0;
     for (int64_t s = 0; s < bt->max_slots; ++s) {
         qcqp_handle *h = bt->handles[s];
         if (!h || bt->finished[s]) continue;
@@ -1019,6 +1037,7 @@ static qcqp_status rebuild_tiles(qcqp_batch *bt)
         bt->max_ny = std::max<int>(bt->max_ny, (int)h->ny);
         bt->max_nw = std::max<int>(bt->max_nw, (int)h->nw);
         bt->max_epi = std::max<int>(bt->max_epi, (int)(h->m + 1 + h->p));
+        bt->variants |= h->hslot.variant == VAR_XY ? HAS_XY : HAS_YX;
     }
     // tiles stay grouped by slot: the persistent pass grid gives each block a contiguous
     // range, so a block restages the iterate only at slot boundaries
@@ -1068,7 +1087,8 @@ qcqp_status qcqp_batch_step(qcqp_batch *bt, int64_t groups)
         auto launch_chunk = [&](hipStream_t s, bool with_events) -> hipError_t {
             for (int64_t g = 0; g < groups; ++g) {
                 hipError_t e = launch_group(s, bt->dslots, bt->dlive, bt->nlive, bt->dtiles, bt->ntiles,
-                                            bt->opt.spec_trials, (int)bt->opt.storage, bt->max_nblk,
+                                            bt->opt.spec_trials, (int)bt->opt.storage, bt->variants,
+                                            bt->max_nblk,
                                             bt->max_ny, bt->max_nw, bt->max_epi, bt->pass_grid, bt->nt,
                                             with_events ? bt->ev[2 * g] : nullptr,
                                             with_events ? bt->ev[2 * g + 1] : nullptr);
