@@ -5,7 +5,9 @@ smoke check and the benchmark's CPU-baseline leg may import this package.  It sh
 the GPU library.
 
 Conventions (same as the instance generators): Q is (m+1, n, n) (or (m, n, n) with has_q0 False)
-in float64 / float32 / bfloat16 / float16; y = (v, lambda) with v in R^p and lambda in R^m_+.
+in float64 / float32 / bfloat16 / float16; y = (v, lambda) with v in R^p and lambda in R^m_+
+(or in the unit simplex, lambda_set="simplex"), optionally restricted to a ball (ball: ||y|| <= B;
+ball_v / ball_l: ||v|| <= B_v, ||lambda|| <= B_lambda); the objective's Hessian is Q_0 + q0_shift I.
 """
 from __future__ import annotations
 
@@ -25,7 +27,9 @@ class _Problem(C.Structure):
     _fields_ = [("n", C.c_int64), ("m", C.c_int64), ("p", C.c_int64),
                 ("Q", C.c_void_p), ("q_dtype", C.c_int32), ("has_q0", C.c_int32),
                 ("q", C.c_void_p), ("c", C.c_void_p), ("A", C.c_void_p), ("b", C.c_void_p),
-                ("lb", C.c_void_p), ("ub", C.c_void_p)]
+                ("lb", C.c_void_p), ("ub", C.c_void_p),
+                ("lambda_set", C.c_int32), ("pad0", C.c_int32), ("q0_shift", C.c_double),
+                ("ball", C.c_double), ("ball_v", C.c_double), ("ball_l", C.c_double)]
 
 
 class _Options(C.Structure):
@@ -57,11 +61,13 @@ def lib():
         vp = C.c_void_p
         L.orc_operator.argtypes = [C.POINTER(_Problem), vp, vp, vp, vp, vp, vp]
         L.orc_grad_from_u.argtypes = [C.POINTER(_Problem), vp, vp, vp]
+        L.orc_project_dual.argtypes = [C.POINTER(_Problem), vp]
         L.orc_kkt.argtypes = [C.POINTER(_Problem), vp, vp, vp]
         L.orc_gap.argtypes = [C.POINTER(_Problem), vp, vp, C.c_double, C.c_double, C.c_int64, vp]
         L.orc_solve.argtypes = [C.POINTER(_Problem), C.POINTER(_Options), vp, vp, vp, vp,
                                 C.POINTER(_Info), vp, C.c_int64]
-        for f in (L.orc_operator, L.orc_grad_from_u, L.orc_kkt, L.orc_gap, L.orc_solve):
+        for f in (L.orc_operator, L.orc_grad_from_u, L.orc_project_dual, L.orc_kkt, L.orc_gap,
+                  L.orc_solve):
             f.restype = C.c_int
         _LIB = L
     return _LIB
@@ -117,10 +123,16 @@ class Problem:
     """Keeps contiguous host copies alive and exposes the C struct."""
 
     def __init__(self, inst=None, *, Q=None, q=None, c=None, lb=None, ub=None, A=None, b=None,
-                 has_q0=True):
+                 has_q0=True, lambda_set="nonneg", q0_shift=0.0, ball=0.0, ball_v=0.0,
+                 ball_l=0.0):
         if inst is not None:
             Q, q, c, lb, ub, A, b, has_q0 = (inst.Q, inst.q, inst.c, inst.lb, inst.ub, inst.A,
                                              inst.b, inst.has_q0)
+            lambda_set = getattr(inst, "lambda_set", lambda_set)
+            q0_shift = getattr(inst, "q0_shift", q0_shift)
+        self.lambda_set = lambda_set
+        self.q0_shift = float(q0_shift)
+        self.ball, self.ball_v, self.ball_l = float(ball), float(ball_v), float(ball_l)
         Qh, dt = _host_q(Q)
         self.Q = Qh
         self.q = np.ascontiguousarray(q, dtype=np.float64)
@@ -143,7 +155,9 @@ class Problem:
                            self.q.ctypes.data, self.c.ctypes.data,
                            self.A.ctypes.data if self.A is not None else None,
                            self.b.ctypes.data if self.b is not None else None,
-                           self.lb.ctypes.data, self.ub.ctypes.data)
+                           self.lb.ctypes.data, self.ub.ctypes.data,
+                           {"nonneg": 0, "simplex": 1}[self.lambda_set], 0, self.q0_shift,
+                           self.ball, self.ball_v, self.ball_l)
 
     @property
     def ny(self):
@@ -184,6 +198,13 @@ def operator(P: Problem, x, y=None):
     gx = np.empty(P.n)
     lib().orc_operator(C.byref(P._c), _ptr(x), _ptr(y), _ptr(U), _ptr(G), _ptr(f), _ptr(gx))
     return dict(U=U, G=G[:P.ny].copy(), f=float(f[0]), grad=gx)
+
+
+def project_dual(P: Problem, y):
+    """Euclidean projection of y = (v, lambda) onto the problem's dual domain Y-hat."""
+    out = np.array(y, dtype=np.float64, copy=True)
+    lib().orc_project_dual(C.byref(P._c), _ptr(out))
+    return out
 
 
 def grad_from_u(P: Problem, U, y):

@@ -22,7 +22,13 @@
  *   - rAPDB-ada: restart test eq. (ada_restart) on the self-centred smoothed duality gap
  *     (Definition "Smoothed duality gap", §4), evaluated as in the Remark of §4.2;
  *   - the KKT residual r(x,v,lambda) of Theorem (metric subregularity sufficient condition),
- *     §4.3, used in relative form for termination.
+ *     §4.3, used in relative form for termination;
+ *   - the restricted dual domain Y-hat = Y ∩ B of problem (R-min-max), §3.2: the ball of
+ *     eq. (defcalB) or the separable balls of the Remark after it (off unless requested, as in
+ *     the experiments of §5);
+ *   - a min-max problem whose lambda ranges over the unit simplex and whose objective carries
+ *     rho ||x||^2 / 2 (the kernel-learning form (min-max-KML) of §5, rho = 2 lambda_KML), with
+ *     its equality constraint b'x = 0 entering Phi through the multiplier v.
  *
  * Everything is naive loops in double precision: no blocking, no reordering beyond what the
  * definitions state.  Q may be supplied as float64, float32, bfloat16 or float16; each element
@@ -42,6 +48,10 @@
  *        with gradient restart, step 1/L with L a Gershgorin bound; tolerance inner_tol.
  *   (R7) termination: relative KKT residual (see orc_kkt) <= tol, checked at every iterate
  *        before an iteration is taken; or k >= max_iter.
+ *   (R8) the projection onto Y-hat is the projection onto the cone R^p x R^m_+ scaled back onto
+ *        the ball (exact for a cone and a ball centred at 0); with a simplex, only a ball on v.
+ *   (R9) with lambda on the simplex, the lambda-part of the KKT residual is the natural residual
+ *        || lambda - Pi_simplex(lambda + g(x)) || and g is no constraint (rel_pri covers Ax - b).
  */
 #include <math.h>
 #include <stdint.h>
@@ -60,7 +70,14 @@ typedef struct {
     const double *c;    /* m+1: c[0] = r_0, c[i] = r_i */
     const double *A;    /* p x n or NULL */
     const double *b;    /* p or NULL */
-    const double *lb, *ub;
+    const double *lb, *ub;   /* lb <= ub; infinite entries allowed (e.g. x >= 0) */
+    /* the dual domain Y-hat = Y ∩ B and the objective's identity part (all zero = plain QCQP) */
+    int32_t lambda_set;      /* 0: lambda in R^m_+ (K* of the QCQP, §2.1); 1: unit simplex */
+    int32_t pad0;
+    double q0_shift;         /* rho >= 0: the objective's Hessian is Q_0 + rho I */
+    double ball;             /* B > 0: ||y|| <= B, the set of eq. (defcalB); 0: none */
+    double ball_v, ball_l;   /* > 0: ||v|| <= B_v, ||lambda|| <= B_lambda (the separable form of
+                                the Remark after eq. (defcalB)); 0: none */
 } orc_problem;
 
 typedef struct {
@@ -144,6 +161,7 @@ static void stack_matvec(const orc_problem *P, const double *x, double *U)
             if (i > 0 || P->has_q0) {
                 for (int64_t j = 0; j < n; ++j) s += qel(P, i, r, j) * x[j];
             }
+            if (i == 0) s += P->q0_shift * x[r];      /* (Q_0 + rho I) x */
             U[i * n + r] = s;
         }
     }
@@ -175,11 +193,64 @@ static void grad_x(const orc_problem *P, const double *U, const double *y, doubl
         for (int64_t j = 0; j < n; ++j) gx[j] += y[l] * P->A[l * n + j];
 }
 
-/* Euclidean projection onto Y = R^p x R^m_+ (K* = R^m_+ for the QCQP, §2.1) */
+/* Euclidean projection of z (k entries) onto the unit simplex {w >= 0, sum w = 1}: sort z in
+ * decreasing order u_1 >= ... >= u_k, take the largest j with u_j > (u_1 + ... + u_j - 1)/j,
+ * theta = (u_1 + ... + u_j - 1)/j and w = max(z - theta, 0) (the sorting method of Held, Wolfe
+ * and Crowder, 1974; also Duchi et al., 2008). */
+static int cmp_desc(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return x < y ? 1 : (x > y ? -1 : 0);
+}
+
+static void project_simplex(double *z, int64_t k)
+{
+    if (k <= 0) return;
+    double *u = malloc(sizeof(double) * k);
+    if (!u) { for (int64_t i = 0; i < k; ++i) z[i] = NAN; return; }
+    memcpy(u, z, sizeof(double) * k);
+    qsort(u, (size_t)k, sizeof(double), cmp_desc);
+    double cum = 0.0, theta = 0.0;
+    for (int64_t j = 0; j < k; ++j) {
+        cum += u[j];
+        double t = (cum - 1.0) / (double)(j + 1);
+        if (u[j] > t) theta = t;
+    }
+    free(u);
+    for (int64_t i = 0; i < k; ++i) z[i] = z[i] > theta ? z[i] - theta : 0.0;
+}
+
+/* scale w (k entries) back onto the ball of radius r when it lies outside */
+static void scale_to_ball(double *w, int64_t k, double r)
+{
+    double s = sqrt(nrm2sq(w, k));
+    if (s > r) {
+        double f = r / s;
+        for (int64_t i = 0; i < k; ++i) w[i] *= f;
+    }
+}
+
+/* Euclidean projection onto the dual domain Y-hat = Y ∩ B, y = (v, lambda):
+ *   Y = R^p x K*, with K* = R^m_+ for the QCQP (§2.1), or R^p x (unit simplex) for a min-max
+ *   problem whose lambda ranges over a simplex;
+ *   B = {||y|| <= B} (eq. (defcalB)) or {||v|| <= B_v} x {||lambda|| <= B_lambda} (the Remark
+ *   after it), or the whole space.
+ * R^p x R^m_+ is a closed convex cone, and the projection onto the intersection of such a cone
+ * with a ball centred at 0 is the cone projection scaled back onto the ball; the separable ball
+ * treats v and lambda the same way one block at a time. */
 static void project_y(const orc_problem *P, double *y)
 {
-    for (int64_t i = 0; i < P->m; ++i)
-        if (y[P->p + i] < 0.0) y[P->p + i] = 0.0;
+    const int64_t p = P->p, m = P->m;
+    double *lam = y + p;
+    if (P->lambda_set == 1) {
+        project_simplex(lam, m);
+    } else {
+        for (int64_t i = 0; i < m; ++i)
+            if (lam[i] < 0.0) lam[i] = 0.0;
+    }
+    if (P->ball > 0.0) scale_to_ball(y, p + m, P->ball);
+    if (P->ball_v > 0.0) scale_to_ball(y, p, P->ball_v);
+    if (P->ball_l > 0.0) scale_to_ball(lam, m, P->ball_l);
 }
 
 /* ------------------------------------------------------------------------------------------ */
@@ -190,6 +261,10 @@ static void project_y(const orc_problem *P, double *y)
  * rel_dual = r_x / (1 + ||Q_0x+q_0|| + ||sum lambda_i (Q_i x + q_i)|| + ||A'v||)
  * rel_comp = r_l / (1 + ||c_{1..m}||)
  * rel_pri  = || ([g]_+, Ax-b) || / (1 + ||c_{1..m}|| + ||b||)
+ * When lambda ranges over the unit simplex, g is not a constraint: r_l is the natural residual
+ * || lambda - Pi_simplex(lambda + g(x)) || of the inner maximisation (for R^m_+ the same formula
+ * gives min(lambda, -g)), and rel_pri and max_violation cover Ax - b only.
+ * The Q_0 and q_0 terms include the identity part rho x.
  * out = {rel_kkt, rel_dual, rel_pri, rel_comp, f, max_violation}                              */
 static void kkt_eval(const orc_problem *P, const double *x, const double *y, const double *U,
                      const double *Gy, double fval, double *out)
@@ -209,12 +284,25 @@ static void kkt_eval(const orc_problem *P, const double *x, const double *y, con
         s2 += a2 * a2;
     }
     double rl = 0, pri = 0, cn = 0, bn = 0, maxv = 0;
-    for (int64_t i = 0; i < m; ++i) {
-        double g = Gy[p + i], lam = y[p + i];
-        double mn = lam < -g ? lam : -g;
-        rl += mn * mn;
-        if (g > 0) { pri += g * g; if (g > maxv) maxv = g; }
-        cn += P->c[i + 1] * P->c[i + 1];
+    if (P->lambda_set == 1) {
+        double *w = malloc(sizeof(double) * (m > 0 ? m : 1));
+        if (!w) { for (int k = 0; k < 6; ++k) out[k] = NAN; return; }
+        for (int64_t i = 0; i < m; ++i) w[i] = y[p + i] + Gy[p + i];
+        project_simplex(w, m);
+        for (int64_t i = 0; i < m; ++i) {
+            double d = y[p + i] - w[i];
+            rl += d * d;
+            cn += P->c[i + 1] * P->c[i + 1];
+        }
+        free(w);
+    } else {
+        for (int64_t i = 0; i < m; ++i) {
+            double g = Gy[p + i], lam = y[p + i];
+            double mn = lam < -g ? lam : -g;
+            rl += mn * mn;
+            if (g > 0) { pri += g * g; if (g > maxv) maxv = g; }
+            cn += P->c[i + 1] * P->c[i + 1];
+        }
     }
     for (int64_t l = 0; l < p; ++l) {
         pri += Gy[l] * Gy[l];
@@ -261,21 +349,26 @@ static int gap_eval(const orc_problem *P, const double *x, const double *y, doub
     constraint_values(P, x, U, Gy, &fval);
     grad_x(P, U, y, gx);
 
-    /* y-part, closed form */
+    /* y-part, closed form: the maximiser is y' = Pi_{Y-hat}(y + grad_y Phi / (2 xi)) */
     double Py = 0.0;
-    for (int64_t l = 0; l < p + m; ++l) {
-        double yp = y[l] + Gy[l] / (2.0 * xi);
-        if (l >= p && yp < 0.0) yp = 0.0;
-        double dl = yp - y[l];
-        Py += Gy[l] * dl - xi * dl * dl;
+    {
+        double *yp = malloc(sizeof(double) * (p + m + 1));
+        if (!yp) { free(U); free(Gy); free(gx); free(H); free(D); free(Dn); free(Z); free(gz); return -1; }
+        for (int64_t l = 0; l < p + m; ++l) yp[l] = y[l] + Gy[l] / (2.0 * xi);
+        project_y(P, yp);
+        for (int64_t l = 0; l < p + m; ++l) {
+            double dl = yp[l] - y[l];
+            Py += Gy[l] * dl - xi * dl * dl;
+        }
+        free(yp);
     }
 
-    /* x-part: H = Q(lambda) + 2 xi I */
+    /* x-part: H = Q(lambda) + 2 xi I, with Q(lambda) = Q_0 + rho I + sum lambda_i Q_i */
     for (int64_t r = 0; r < n; ++r)
         for (int64_t j = 0; j < n; ++j) {
             double h = qel(P, 0, r, j);
             for (int64_t i = 1; i <= m; ++i) h += y[p + i - 1] * qel(P, i, r, j);
-            H[r * n + j] = h + (r == j ? 2.0 * xi : 0.0);
+            H[r * n + j] = h + (r == j ? 2.0 * xi + P->q0_shift : 0.0);
         }
     double L = 0.0;   /* Gershgorin bound on lambda_max(H) */
     for (int64_t r = 0; r < n; ++r) {
@@ -326,6 +419,13 @@ int orc_operator(const orc_problem *P, const double *x, const double *y, double 
     stack_matvec(P, x, U);
     constraint_values(P, x, U, Gy, fval);
     if (gx) grad_x(P, U, y, gx);
+    return 0;
+}
+
+/* projection of y (p + m entries) onto the dual domain Y-hat, in place (test access) */
+int orc_project_dual(const orc_problem *P, double *y)
+{
+    project_y(P, y);
     return 0;
 }
 
@@ -594,7 +694,11 @@ static int validate(const orc_problem *P, const orc_options *o)
         if (!(o->c_alpha >= 0 && o->c_beta > 0 && o->delta >= 0 && s > 0 && s < 1)) return -1;
     }
     for (int64_t j = 0; j < P->n; ++j)
-        if (!(P->lb[j] <= P->ub[j])) return -1;
+        if (!(P->lb[j] <= P->ub[j]) || P->lb[j] == INFINITY || P->ub[j] == -INFINITY) return -1;
+    if (P->lambda_set != 0 && P->lambda_set != 1) return -1;
+    if (P->lambda_set == 1 && (P->m < 1 || P->ball > 0.0 || P->ball_l > 0.0)) return -1;
+    if (!(P->q0_shift >= 0.0 && P->ball >= 0.0 && P->ball_v >= 0.0 && P->ball_l >= 0.0)) return -1;
+    if (P->ball > 0.0 && (P->ball_v > 0.0 || P->ball_l > 0.0)) return -1;
     if (o->restart == 1 && o->restart_every < 1) return -1;
     if (o->restart == 2 && (o->ada_every < 1 || !(o->xi > 0) || !(o->q_restart > 0 && o->q_restart < 1)))
         return -1;
