@@ -53,12 +53,19 @@ typedef enum { QCQP_RESTART_NONE = 0, QCQP_RESTART_FIXED = 1, QCQP_RESTART_ADAPT
  *                and the start re-anchor U with a direct pass accumulated in FP64.
  *   AUTO:        DIRECT for FP64 storage, INCREMENTAL otherwise. */
 typedef enum { QCQP_PASS_AUTO = 0, QCQP_PASS_DIRECT = 1, QCQP_PASS_INCREMENTAL = 2 } qcqp_pass_mode;
+/* Where lambda ranges: R^m_+ (K* of the QCQP's cone, §2.1), or the unit simplex, which turns the
+ * problem into min_x max_{lambda in simplex} f(x) + sum_i lambda_i g_i(x) + <v, Ax - b> (the
+ * kernel-learning form (min-max-KML) of §5). */
+typedef enum { QCQP_LAMBDA_NONNEG = 0, QCQP_LAMBDA_SIMPLEX = 1 } qcqp_lambda_set;
 
 typedef struct qcqp_handle qcqp_handle;
 typedef struct qcqp_batch qcqp_batch;
 
-/* Problem data, eq. (QCQP).  Ownership: qcqp_create copies (and converts) everything into
- * library-owned device memory; the caller may free its buffers as soon as it returns. */
+/* Problem data, eq. (QCQP), or the saddle problem min_{x in X} max_{y in Y-hat} Phi(x, y) of
+ * eq. (qcqp-coupling) restricted as in problem (R-min-max) of §3.2.  Ownership: qcqp_create
+ * copies (and converts) everything into library-owned device memory; the caller may free its
+ * buffers as soon as it returns.  A zero-initialised tail (lambda_set .. ball_lambda) gives the
+ * plain QCQP. */
 typedef struct {
     int64_t n, m, p;           /* n > 0, m >= 0, 0 <= p < n (rank(A) = p is assumed, not checked) */
     const void *Q;             /* (m + has_q0) matrices, each n rows of ldq elements, row-major,
@@ -71,8 +78,18 @@ typedef struct {
     const double *c;           /* m+1: c_0 then c_1..c_m */
     const double *A;           /* p x n row-major, NULL iff p == 0 */
     const double *b;           /* p, NULL iff p == 0 */
-    const double *lb, *ub;     /* n each, finite, lb <= ub */
+    const double *lb, *ub;     /* n each, lb <= ub, lb < +inf, ub > -inf; infinite bounds are
+                                  allowed (e.g. x >= 0), finite ones keep X compact as the
+                                  paper assumes */
     int on_device;             /* 1: all pointers here and in later calls are device memory */
+    qcqp_lambda_set lambda_set;  /* R^m_+ (default) or the unit simplex (needs m >= 1) */
+    double q0_shift;           /* rho >= 0: the objective is 1/2 x'(Q_0 + rho I)x + q_0'x + c_0,
+                                  so an identity part costs no stored matrix */
+    double ball;               /* B > 0: y restricted to ||y|| <= B (eq. (defcalB)); 0: off */
+    double ball_v, ball_lambda;  /* > 0: ||v|| <= B_v, ||lambda|| <= B_lambda, the separable
+                                  form of the Remark after eq. (defcalB); 0: off.  Not combined
+                                  with `ball`; with the simplex only ball_v is allowed.
+                                  The experiments of §5 impose no ball. */
 } qcqp_problem;
 
 /* Method parameters (Algorithm 1, the APDB-yx rules of §3.2, Algorithm 2, eq. (ada_restart)).

@@ -123,13 +123,17 @@ class Problem:
     """Keeps contiguous host copies alive and exposes the C struct."""
 
     def __init__(self, inst=None, *, Q=None, q=None, c=None, lb=None, ub=None, A=None, b=None,
-                 has_q0=True, lambda_set="nonneg", q0_shift=0.0, ball=0.0, ball_v=0.0,
+                 has_q0=True, lambda_set=None, q0_shift=None, ball=0.0, ball_v=0.0,
                  ball_l=0.0):
         if inst is not None:
             Q, q, c, lb, ub, A, b, has_q0 = (inst.Q, inst.q, inst.c, inst.lb, inst.ub, inst.A,
                                              inst.b, inst.has_q0)
-            lambda_set = getattr(inst, "lambda_set", lambda_set)
-            q0_shift = getattr(inst, "q0_shift", q0_shift)
+            if lambda_set is None:
+                lambda_set = getattr(inst, "lambda_set", None)
+            if q0_shift is None:
+                q0_shift = getattr(inst, "q0_shift", None)
+        lambda_set = "nonneg" if lambda_set is None else lambda_set
+        q0_shift = 0.0 if q0_shift is None else q0_shift
         self.lambda_set = lambda_set
         self.q0_shift = float(q0_shift)
         self.ball, self.ball_v, self.ball_l = float(ball), float(ball_v), float(ball_l)

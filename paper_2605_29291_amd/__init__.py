@@ -50,10 +50,17 @@ class Solver:
     """One QCQP resident on the GPU (a qcqp_handle)."""
 
     def __init__(self, inst=None, *, Q=None, q=None, c=None, lb=None, ub=None, A=None, b=None,
-                 has_q0=True, device=None, **options):
+                 has_q0=True, lambda_set=None, q0_shift=None, ball=0.0, ball_v=0.0,
+                 ball_lambda=0.0, device=None, **options):
         if inst is not None:
             Q, q, c, lb, ub, A, b, has_q0 = (inst.Q, inst.q, inst.c, inst.lb, inst.ub, inst.A,
                                              inst.b, inst.has_q0)
+            if lambda_set is None:
+                lambda_set = getattr(inst, "lambda_set", None)
+            if q0_shift is None:
+                q0_shift = getattr(inst, "q0_shift", None)
+        lambda_set = "nonneg" if lambda_set is None else lambda_set
+        q0_shift = 0.0 if q0_shift is None else q0_shift
         L = load()
         torch = _torch()
         if device is None:
@@ -99,7 +106,9 @@ class Solver:
                 qptr = Qa.ctypes.data
         prob = abi.Problem(self.n, self.m, self.p, qptr, qcode, 0, 1 if has_q0 else 0,
                            vec(q), vec(c), vec(A) if self.p else None, vec(b) if self.p else None,
-                           vec(lb), vec(ub), 1 if self.on_device else 0)
+                           vec(lb), vec(ub), 1 if self.on_device else 0,
+                           {"nonneg": 0, "simplex": 1}[lambda_set], float(q0_shift), float(ball),
+                           float(ball_v), float(ball_lambda))
         if "stream" not in options:
             options["stream"] = _current_stream()
         self.options = abi.default_options(**options)

@@ -34,7 +34,9 @@ class Problem(C.Structure):
     _fields_ = [("n", C.c_int64), ("m", C.c_int64), ("p", C.c_int64),
                 ("Q", C.c_void_p), ("Q_dtype", C.c_int), ("ldq", C.c_int64), ("has_q0", C.c_int),
                 ("q", C.c_void_p), ("c", C.c_void_p), ("A", C.c_void_p), ("b", C.c_void_p),
-                ("lb", C.c_void_p), ("ub", C.c_void_p), ("on_device", C.c_int)]
+                ("lb", C.c_void_p), ("ub", C.c_void_p), ("on_device", C.c_int),
+                ("lambda_set", C.c_int), ("q0_shift", C.c_double), ("ball", C.c_double),
+                ("ball_v", C.c_double), ("ball_lambda", C.c_double)]
 
 
 class Options(C.Structure):

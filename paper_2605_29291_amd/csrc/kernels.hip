@@ -55,9 +55,101 @@ __device__ __forceinline__ void block_sum(double (&v)[NV])
 }
 
 // ---------------------------------------------------------------------------------------
+// projections onto the dual domain (called by every thread of a block; results visible to the
+// whole block on return)
+
+// w (k entries, LDS or global) onto the unit simplex: w <- max(w - theta, 0) with
+// sum max(w - theta, 0) = 1.  theta by Michelot's iteration: start from the mean rule over all
+// entries, then repeat theta <- (sum_{w_i > theta} w_i - 1) / #{w_i > theta} until the count
+// stops changing (theta only grows, so at most k rounds; one fixed-order block sum each).
+__device__ void simplex_block(double *w, int k)
+{
+    const int tid = threadIdx.x;
+    __shared__ double s_th[2];
+    double v[2] = {0.0, 0.0};
+    for (int l = tid; l < k; l += STEP_BS) v[0] += w[l];
+    block_sum<2>(v);
+    if (tid == 0) s_th[0] = (v[0] - 1.0) / (double)k;
+    __syncthreads();
+    double theta = s_th[0], cnt = (double)k;
+    __syncthreads();
+    for (int round = 0; round <= k; ++round) {
+        double u[2] = {0.0, 0.0};
+        for (int l = tid; l < k; l += STEP_BS) {
+            const double a = w[l];
+            if (a > theta) {
+                u[0] += a;
+                u[1] += 1.0;
+            }
+        }
+        block_sum<2>(u);
+        if (tid == 0) {
+            s_th[0] = (u[0] - 1.0) / u[1];
+            s_th[1] = u[1];
+        }
+        __syncthreads();
+        const double nt = s_th[0], nc = s_th[1];
+        __syncthreads();
+        theta = nt;
+        if (nc == cnt) break;
+        cnt = nc;
+    }
+    for (int l = tid; l < k; l += STEP_BS) {
+        const double a = w[l];
+        w[l] = a > theta ? a - theta : 0.0;
+    }
+    __syncthreads();
+}
+
+// y = (v, lambda) (ny entries) onto Y-hat = Y ∩ B (problem (R-min-max), §3.2): lambda onto
+// R^m_+ or the simplex, then the ball ||y|| <= B (eq. (defcalB)) or ||v|| <= B_v,
+// ||lambda|| <= B_lambda (the separable form): scaled back when outside, which is the exact
+// projection for the cone R^p x R^m_+ intersected with a ball centred at 0.
+__device__ void project_dual_block(const Slot *S, double *w)
+{
+    const int p = S->p, m = S->m, ny = S->ny, tid = threadIdx.x;
+    if (S->lambda_set == LAMBDA_SIMPLEX) {
+        simplex_block(w + p, m);
+    } else {
+        for (int l = p + tid; l < ny; l += STEP_BS)
+            if (w[l] < 0.0) w[l] = 0.0;
+        __syncthreads();
+    }
+    const double B = S->ball, Bv = S->ball_v, Bl = S->ball_l;
+    if (B > 0.0 || Bv > 0.0 || Bl > 0.0) {
+        __shared__ double s_f[2];
+        double v[2] = {0.0, 0.0};
+        for (int l = tid; l < ny; l += STEP_BS) v[l < p ? 0 : 1] += w[l] * w[l];
+        block_sum<2>(v);
+        if (tid == 0) {
+            double fv = 1.0, fl = 1.0;
+            if (B > 0.0) {
+                const double r = sqrt(v[0] + v[1]);
+                if (r > B) fv = fl = B / r;
+            }
+            if (Bv > 0.0) {
+                const double r = sqrt(v[0]);
+                if (r > Bv) fv = Bv / r;
+            }
+            if (Bl > 0.0) {
+                const double r = sqrt(v[1]);
+                if (r > Bl) fl = Bl / r;
+            }
+            s_f[0] = fv;
+            s_f[1] = fl;
+        }
+        __syncthreads();
+        const double fv = s_f[0], fl = s_f[1];
+        if (fv != 1.0 || fl != 1.0)
+            for (int l = tid; l < ny; l += STEP_BS) w[l] *= (l < p ? fv : fl);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // step kernel: dual step then primal step for B candidate step sizes (eq. (apdb-yx-y)):
 //   sigma = gamma tau, theta = sigma_{k-1}/sigma, s = (1+theta) G^k - theta G^{k-1},
-//   y+ = Pi_Y(y + sigma s)   (lambda >= 0, v free),
+//   y+ = Pi_{Y-hat}(y + sigma s)   (lambda in R^m_+ or the simplex, v free, optional ball),
 //   x+ = Pi_X(x - tau grad_x Phi(x^k, y+)),  grad from the cached U^k = [Q_i x^k].
 // Also the KKT partials of the iterate (x^k, y^k).
 
@@ -92,13 +184,18 @@ __global__ void __launch_bounds__(STEP_BS) k_step(Slot *__restrict__ slots,
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const double s = (1.0 + th_b[b]) * gl - th_b[b] * gpl;
-            double v = yl + sig_b[b] * s;
-            if (l >= p) v = v < 0.0 ? 0.0 : v;
-            ynew[b * ny + l] = v;
-            if (blockIdx.x == 0) S->yc[b][l] = v;
+            ynew[b * ny + l] = yl + sig_b[b] * s;
         }
     }
     __syncthreads();
+#pragma unroll
+    for (int b = 0; b < B; ++b) project_dual_block(S, ynew + b * ny);
+    if (blockIdx.x == 0) {
+        for (int l = threadIdx.x; l < ny; l += STEP_BS) {
+#pragma unroll
+            for (int b = 0; b < B; ++b) S->yc[b][l] = ynew[b * ny + l];
+        }
+    }
     // block = STEP_COLS columns; wave w sums matrices i = 1 + w, 1 + w + STEP_WAVES, ...
     const int lane = threadIdx.x % STEP_COLS, wave = threadIdx.x / STEP_COLS;
     const int j = blockIdx.x * STEP_COLS + lane;
@@ -292,17 +389,26 @@ __global__ void __launch_bounds__(STEP_BS) k_epi(Slot *__restrict__ slots,
     const bool inc = S->incremental != 0;
     const double *x = S->x;
     const int tid = threadIdx.x;
+    // identity part of the objective: row 0 becomes (Q_0 + rho I) x (or (Q_0 + rho I) d), set in
+    // place so every later reader of U_0 / W_0 sees it; without Q_0 the pass never writes row 0
+    const double rho = row == 0 ? S->q0_shift : 0.0;
+    const double keep0 = S->has_q0 ? 1.0 : 0.0;
     if (row <= m) {
         const int gi = row == 0 ? ny : p + row - 1;
         const double *q = S->q + (size_t)row * n;
         const double ci = S->c[row];
         const size_t off = (size_t)row * n;
         if (anchor) {
-            const double *u = S->Uc[0] + off;
+            double *u = S->Uc[0] + off;
             double v[2] = {0.0, 0.0};
             for (int j = tid; j < n; j += STEP_BS) {
                 const double xj = x[j];
-                v[0] = fma(xj, u[j], v[0]);
+                double uj = u[j];
+                if (rho != 0.0) {
+                    uj = fma(rho, xj, keep0 * uj);
+                    u[j] = uj;
+                }
+                v[0] = fma(xj, uj, v[0]);
                 v[1] = fma(q[j], xj, v[1]);
             }
             block_sum<2>(v);
@@ -317,7 +423,11 @@ __global__ void __launch_bounds__(STEP_BS) k_epi(Slot *__restrict__ slots,
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
                     const double d = S->xc[b][j] - xj;
-                    const double wv = S->W[b][off + j];
+                    double wv = S->W[b][off + j];
+                    if (rho != 0.0) {
+                        wv = fma(rho, d, keep0 * wv);
+                        S->W[b][off + j] = wv;
+                    }
                     v[3 * b + 0] = fma(d, wv, v[3 * b + 0]);
                     v[3 * b + 1] = fma(d, uj, v[3 * b + 1]);
                     v[3 * b + 2] = fma(qj, d, v[3 * b + 2]);
@@ -345,7 +455,11 @@ __global__ void __launch_bounds__(STEP_BS) k_epi(Slot *__restrict__ slots,
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
                     const double xn = S->xc[b][j];
-                    const double un = S->Uc[b][off + j];
+                    double un = S->Uc[b][off + j];
+                    if (rho != 0.0) {
+                        un = fma(rho, xn, keep0 * un);
+                        S->Uc[b][off + j] = un;
+                    }
                     v[3 * b + 0] = fma(xn - xj, un - uj, v[3 * b + 0]);
                     v[3 * b + 1] = fma(xn, un, v[3 * b + 1]);
                     v[3 * b + 2] = fma(qj, xn, v[3 * b + 2]);
@@ -400,7 +514,7 @@ __global__ void __launch_bounds__(STEP_BS) k_epi(Slot *__restrict__ slots,
 // ---------------------------------------------------------------------------------------
 // APDB-xy post kernel (Algorithm 1), after the pass and the epilogue have given
 // U+ = [Q_i x+] and grad_y Phi(x+) = (Ax+ - b, g(x+)) of every candidate:
-//   y+ = Pi_Y(y + sigma grad_y Phi(x+))   (lambda >= 0, v free),
+//   y+ = Pi_{Y-hat}(y + sigma grad_y Phi(x+))   (as in the yx step kernel),
 // and, per column j, the two gradient differences of the test function E_k:
 //   a_j = [grad_x Phi(x+,y+) - grad_x Phi(x+,y)]_j = sum_i (l+_i - l_i)(Q_i x+ + q_i)_j + [A'(v+ - v)]_j
 //   c_j = [grad_x Phi(x+,y) - grad_x Phi(x,y)]_j  = (Q_0 d)_j + sum_i l_i (Q_i d)_j ,  d = x+ - x,
@@ -434,14 +548,17 @@ __global__ void __launch_bounds__(STEP_BS) k_post_xy(Slot *__restrict__ slots,
         const double yl = y[l];
         ycur[l] = yl;
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
-            double v = yl + sig_b[b] * S->Gc[b][l];
-            if (l >= p) v = v < 0.0 ? 0.0 : v;
-            ynew[b * ny + l] = v;
-            if (blockIdx.x == 0) S->yc[b][l] = v;
-        }
+        for (int b = 0; b < B; ++b) ynew[b * ny + l] = yl + sig_b[b] * S->Gc[b][l];
     }
     __syncthreads();
+#pragma unroll
+    for (int b = 0; b < B; ++b) project_dual_block(S, ynew + b * ny);
+    if (blockIdx.x == 0) {
+        for (int l = threadIdx.x; l < ny; l += STEP_BS) {
+#pragma unroll
+            for (int b = 0; b < B; ++b) S->yc[b][l] = ynew[b * ny + l];
+        }
+    }
     const int lane = threadIdx.x % STEP_COLS, wave = threadIdx.x / STEP_COLS;
     const int j = blockIdx.x * STEP_COLS + lane;
     const bool inc = S->incremental != 0;
@@ -594,6 +711,15 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
     // ---- 1+2. one fixed-order block reduction of everything the decision needs:
     //   step partials (KKT pieces of the iterate, ||d_b||^2), ||min(lambda,-g)||^2,
     //   ||([g]+, Ax-b)||^2, and per candidate 1/2 d'Q(lambda+)d terms, ||dG||^2, ||dy||^2 ----
+    // lambda on the simplex: the lambda-part of the KKT residual is the natural residual
+    // lambda - Pi_simplex(lambda + g(x)); the projected point is staged in LDS
+    extern __shared__ double wsm[];
+    const bool simplex = S->lambda_set == LAMBDA_SIMPLEX;
+    if (simplex) {
+        for (int l = tid; l < m; l += STEP_BS) wsm[l] = S->y[p + l] + S->G[p + l];
+        __syncthreads();
+        simplex_block(wsm, m);
+    }
     constexpr int NR = NPART + 2 + 3 * B;
     double r[NR];
 #pragma unroll
@@ -612,6 +738,9 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
             if (l < p) {
                 r[NPART + 1] += gl * gl;
                 mx = fmax(mx, fabs(gl));
+            } else if (simplex) {
+                const double d = y[l] - wsm[l - p];
+                r[NPART] += d * d;
             } else {
                 const double lam = y[l];
                 const double mn = lam < -gl ? lam : -gl;
@@ -819,20 +948,19 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
 }
 
 // ---------------------------------------------------------------------------------------
-// start: clip x^0 into X, project lambda^0 onto R^m_+, clear the averages; the first group
-// is an anchor pass.
+// start: clip x^0 into X, project y^0 onto Y-hat, clear the averages; the first group is an
+// anchor pass.
 
 __global__ void __launch_bounds__(STEP_BS) k_start(Slot *__restrict__ S)
 {
-    const int n = S->n, ny = S->ny, p = S->p;
+    const int n = S->n, ny = S->ny;
     for (int j = threadIdx.x; j < n; j += STEP_BS) {
         S->x[j] = clipd(S->x[j], S->lb[j], S->ub[j]);
         S->cx[j] = 0.0;
     }
-    for (int l = threadIdx.x; l < ny; l += STEP_BS) {
-        if (l >= p && S->y[l] < 0.0) S->y[l] = 0.0;
-        S->cy[l] = 0.0;
-    }
+    for (int l = threadIdx.x; l < ny; l += STEP_BS) S->cy[l] = 0.0;
+    __syncthreads();
+    project_dual_block(S, S->y);
 }
 
 // adaptive restart decision after the host evaluated G_xi at the iterate (eq. (ada_restart)):
@@ -912,12 +1040,19 @@ __global__ void __launch_bounds__(STEP_BS) k_kkt_fin(const Slot *__restrict__ S,
                                                      const double *__restrict__ part,
                                                      double *__restrict__ out6)
 {
-    const int ny = S->ny, p = S->p;
+    const int ny = S->ny, p = S->p, m = S->m;
     const int tid = threadIdx.x;
     double tot[4] = {0.0, 0.0, 0.0, 0.0};
     for (int blk = tid; blk < nblk; blk += STEP_BS)
         for (int f = 0; f < 4; ++f) tot[f] += part[(size_t)blk * 4 + f];
     block_sum<4>(tot);
+    extern __shared__ double wsm[];
+    const bool simplex = S->lambda_set == LAMBDA_SIMPLEX;
+    if (simplex) {
+        for (int l = tid; l < m; l += STEP_BS) wsm[l] = y[p + l] + G[p + l];
+        __syncthreads();
+        simplex_block(wsm, m);
+    }
     double kv[2] = {0.0, 0.0};
     double mx = 0.0;
     for (int l = tid; l < ny; l += STEP_BS) {
@@ -925,6 +1060,9 @@ __global__ void __launch_bounds__(STEP_BS) k_kkt_fin(const Slot *__restrict__ S,
         if (l < p) {
             kv[1] += gl * gl;
             mx = fmax(mx, fabs(gl));
+        } else if (simplex) {
+            const double d = y[l] - wsm[l - p];
+            kv[0] += d * d;
         } else {
             const double lam = y[l];
             const double mn = lam < -gl ? lam : -gl;
@@ -1038,20 +1176,23 @@ __global__ void __launch_bounds__(STEP_BS) k_gap_py(const Slot *__restrict__ S,
                                                     const double *__restrict__ G, double xi,
                                                     double *__restrict__ ctl)
 {
-    const int ny = S->ny, p = S->p;
+    // maximiser y' = Pi_{Y-hat}(y + grad_y Phi / (2 xi)), staged in LDS
+    extern __shared__ double yp[];
+    const int ny = S->ny;
+    for (int l = threadIdx.x; l < ny; l += STEP_BS) yp[l] = y[l] + G[l] / (2.0 * xi);
+    __syncthreads();
+    project_dual_block(S, yp);
     double v[1] = {0.0};
     for (int l = threadIdx.x; l < ny; l += STEP_BS) {
-        double yp = y[l] + G[l] / (2.0 * xi);
-        if (l >= p && yp < 0.0) yp = 0.0;
-        const double d = yp - y[l];
+        const double d = yp[l] - y[l];
         v[0] += G[l] * d - xi * d * d;
     }
     block_sum<1>(v);
     if (threadIdx.x == 0) ctl[9] = v[0];
 }
 
-// H = Q(lambda) + 2 xi I (row r per block), rowabs[r] = sum_j |H_rj|; matrices with a zero
-// multiplier are skipped (they contribute nothing)
+// H = Q(lambda) + 2 xi I (row r per block), Q(lambda) = Q_0 + rho I + sum lambda_i Q_i,
+// rowabs[r] = sum_j |H_rj|; matrices with a zero multiplier are skipped (they contribute nothing)
 __global__ void __launch_bounds__(STEP_BS) k_form_h(const Slot *__restrict__ S,
                                                     const double *__restrict__ y, double xi,
                                                     double *__restrict__ H, int ldh,
@@ -1072,7 +1213,7 @@ __global__ void __launch_bounds__(STEP_BS) k_form_h(const Slot *__restrict__ S,
             const size_t mat = (size_t)(i - 1 + has_q0);
             h += w * load_any(S->Q, dt, (mat * n + r) * ld + j);
         }
-        if (j == r) h += 2.0 * xi;
+        if (j == r) h += 2.0 * xi + S->q0_shift;
         H[(size_t)r * ldh + j] = h;
         v[0] += fabs(h);
     }
@@ -1194,11 +1335,11 @@ __global__ void __launch_bounds__(STEP_BS) k_gap_px(int n, const double *__restr
     if (threadIdx.x == 0) ctl[10] = -v[0];
 }
 
-hipError_t launch_gap_setup(hipStream_t s, const Slot *slot, int n, const double *y,
+hipError_t launch_gap_setup(hipStream_t s, const Slot *slot, int n, int ny, const double *y,
                             const double *G, const double *grad, double xi, double *H, int ldh,
                             double *rowabs, double tol, double *ctl)
 {
-    k_gap_py<<<1, STEP_BS, 0, s>>>(slot, y, G, xi, ctl);
+    k_gap_py<<<1, STEP_BS, (size_t)(ny > 0 ? ny : 1) * sizeof(double), s>>>(slot, y, G, xi, ctl);
     k_form_h<<<n, STEP_BS, 0, s>>>(slot, y, xi, H, ldh, rowabs);
     k_gap_init<<<1, STEP_BS, 0, s>>>(n, grad, rowabs, tol, ctl);
     return hipGetLastError();
@@ -1246,7 +1387,7 @@ static hipError_t group_b(hipStream_t s, Slot *slots, const int *live, int nslot
     if (ev1) (void)hipEventRecord(ev1, s);
     k_epi<B><<<dim3(max_epi, nslots), STEP_BS, 0, s>>>(slots, live);
     if (variants & HAS_XY) k_post_xy<B><<<vgrid, STEP_BS, step_lds, s>>>(slots, live);
-    k_ctrl<B><<<nslots, STEP_BS, 0, s>>>(slots, live);
+    k_ctrl<B><<<nslots, STEP_BS, (size_t)(max_ny > 0 ? max_ny : 1) * sizeof(double), s>>>(slots, live);
     return hipGetLastError();
 }
 
@@ -1277,12 +1418,13 @@ hipError_t launch_grad(hipStream_t s, const Slot *slot, int n, const double *U, 
     return hipGetLastError();
 }
 
-hipError_t launch_kkt(hipStream_t s, const Slot *slot, int n, const double *x, const double *y,
-                      const double *U, const double *G, double *part, double *out6)
+hipError_t launch_kkt(hipStream_t s, const Slot *slot, int n, int ny, const double *x,
+                      const double *y, const double *U, const double *G, double *part,
+                      double *out6)
 {
     const int nblk = (n + STEP_BS - 1) / STEP_BS;
     k_kkt_part<<<nblk, STEP_BS, 0, s>>>(slot, x, y, U, part);
-    k_kkt_fin<<<1, STEP_BS, 0, s>>>(slot, nblk, y, G, part, out6);
+    k_kkt_fin<<<1, STEP_BS, (size_t)(ny > 0 ? ny : 1) * sizeof(double), s>>>(slot, nblk, y, G, part, out6);
     return hipGetLastError();
 }
 

@@ -46,6 +46,8 @@ enum StoreType : int32_t { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2, DT_F16 = 3 };
 
 enum Variant : int32_t { VAR_YX = 0, VAR_XY = 1 };
 
+enum LambdaSet : int32_t { LAMBDA_NONNEG = 0, LAMBDA_SIMPLEX = 1 };
+
 // bit mask of the variants present among the slots of a launch
 constexpr int HAS_YX = 1, HAS_XY = 2;
 
@@ -56,6 +58,9 @@ struct Slot {
     int32_t ld, dtype;            // row stride (elements) and storage type of Q
     int32_t c_nm, restart, restart_from_avg, incremental;
     int32_t B, nblk_step, nw, variant;   // nw = n rounded up to the pass vector width
+    int32_t lambda_set, pad1;     // dual domain of lambda: R^m_+ or the unit simplex
+    double q0_shift;              // rho: the objective's Hessian is Q_0 + rho I
+    double ball, ball_v, ball_l;  // dual ball radii (0 = none): ||y||, ||v||, ||lambda||
     int64_t restart_every, ada_first, ada_every, max_iter;
     double eta, tau_bar, gamma0, mu, c_alpha, c_beta, delta, tol, q_restart;
     double cnorm, bnorm;          // ||c_{1..m}||, ||b||  (KKT scales)
@@ -102,18 +107,21 @@ hipError_t launch_pass_only(hipStream_t s, Slot *slots, const Tile *tiles, int n
 // persistent pass grid: resident blocks per CU of k_pass for this configuration
 int pass_blocks_per_cu(int B, int dtype, int max_nw);
 size_t pass_lds_bytes(int B, int dtype, int max_nw);
+// rows one lane group of the trial pass streams at a time for this storage type
+int pass_rows_per_step(int dtype);
 hipError_t launch_epi_anchor(hipStream_t s, Slot *slots, const int *live, int nslots, int max_epi);
 hipError_t launch_matvec1(hipStream_t s, const void *Q, int dtype, int n, int ld, int row_base,
                           const double *v, int nw, double *z);
 hipError_t launch_grad(hipStream_t s, const Slot *slot, int n, const double *U, const double *y,
                        double *out);
-hipError_t launch_kkt(hipStream_t s, const Slot *slot, int n, const double *x, const double *y,
-                      const double *U, const double *G, double *part, double *out6);
+hipError_t launch_kkt(hipStream_t s, const Slot *slot, int n, int ny, const double *x,
+                      const double *y, const double *U, const double *G, double *part,
+                      double *out6);
 hipError_t launch_convert(hipStream_t s, const void *src, int src_dtype, int64_t ld_src,
                           void *dst, int dst_dtype, int64_t ld_dst, int64_t rows, int64_t n);
 hipError_t launch_start(hipStream_t s, Slot *slot);
 hipError_t launch_restart_decision(hipStream_t s, Slot *slot, double gap, int first);
-hipError_t launch_gap_setup(hipStream_t s, const Slot *slot, int n, const double *y,
+hipError_t launch_gap_setup(hipStream_t s, const Slot *slot, int n, int ny, const double *y,
                             const double *G, const double *grad, double xi, double *H, int ldh,
                             double *rowabs, double tol, double *ctl);
 hipError_t launch_gap_iters(hipStream_t s, const Slot *slot, int n, const double *x,

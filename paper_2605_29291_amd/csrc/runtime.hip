@@ -104,20 +104,20 @@ constexpr double CACHE_RESIDENT_BYTES = 256e6;   // Infinity Cache (MALL) of one
 
 // Lanes per row and rows per tile for a stack of `rows` rows of n elements of type dt.
 // A lane should issue at least one full batch of 8 loads per row, so short rows share a wave
-// (32 or 16 lanes per row).  Tiles hold ~128 KB of the stack (a multiple of the rows one block
-// covers at once), and there are at least ~1024 of them when the stack allows it, so that the
-// persistent grid splits into equal contiguous ranges.
+// (32 or 16 lanes per row).  Tiles hold ~128 KB of the stack, rounded to whole block steps
+// (every lane group streams its R rows), and there are at least ~1024 of them when the stack
+// allows it, so that the persistent grid splits into nearly equal contiguous ranges.
 void tile_shape(int64_t n, int dt, int64_t rows, int *lpr, int *rows_per_tile)
 {
     const int64_t vpr = (n + vec_width(dt) - 1) / vec_width(dt);   // 16-byte vectors per row
     int l = 16;
     if (vpr >= 8 * 64) l = 64;
     else if (vpr >= 8 * 32) l = 32;
-    const int ng = PASS_BS / l;
+    const int step = (PASS_BS / l) * pass_rows_per_step(dt);   // rows one block covers at once
     const int64_t row_bytes = n * elem_size(dt);
     int64_t r = std::max<int64_t>(1, (128 * 1024) / std::max<int64_t>(row_bytes, 1));
     r = std::min<int64_t>(r, std::max<int64_t>(1, rows / 1024));
-    r = round_up(std::max<int64_t>(r, 4 * ng), 4 * ng);   // whole row blocks of up to 4 rows per group
+    r = round_up(std::max<int64_t>(r, step), step);
     *lpr = l;
     *rows_per_tile = (int)r;
 }
@@ -326,6 +326,18 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
     if (p > 0 && (!P->A || !P->b)) return fail(QCQP_E_INVALID, "A and b are required when p > 0");
     if ((P->has_q0 || m > 0) && !P->Q) return fail(QCQP_E_INVALID, "Q is required");
     if (P->Q_dtype < QCQP_F64 || P->Q_dtype > QCQP_F16) return fail(QCQP_E_INVALID, "unknown Q_dtype");
+    if (P->lambda_set != QCQP_LAMBDA_NONNEG && P->lambda_set != QCQP_LAMBDA_SIMPLEX)
+        return fail(QCQP_E_INVALID, "unknown lambda_set");
+    if (P->lambda_set == QCQP_LAMBDA_SIMPLEX && m < 1) return fail(QCQP_E_INVALID, "the simplex needs m >= 1");
+    if (!(P->q0_shift >= 0.0) || !std::isfinite(P->q0_shift)) return fail(QCQP_E_INVALID, "q0_shift must be finite and >= 0");
+    if (!(P->ball >= 0.0 && P->ball_v >= 0.0 && P->ball_lambda >= 0.0) ||
+        !std::isfinite(P->ball) || !std::isfinite(P->ball_v) || !std::isfinite(P->ball_lambda))
+        return fail(QCQP_E_INVALID, "ball radii must be finite and >= 0");
+    if (P->ball > 0.0 && (P->ball_v > 0.0 || P->ball_lambda > 0.0))
+        return fail(QCQP_E_INVALID, "use either the joint ball or the separable balls");
+    // the simplex is compact already and not a cone: a ball on lambda would need another projection
+    if (P->lambda_set == QCQP_LAMBDA_SIMPLEX && (P->ball > 0.0 || P->ball_lambda > 0.0))
+        return fail(QCQP_E_INVALID, "with the simplex only the ball on v is supported");
     const int has_q0 = P->has_q0 ? 1 : 0;
     const int64_t nq = m + has_q0;
 
@@ -371,9 +383,10 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
         return st;
     }
     for (int64_t j = 0; j < n; ++j)
-        if (!std::isfinite(hlb[j]) || !std::isfinite(hub[j]) || !(hlb[j] <= hub[j])) {
+        if (!(hlb[j] <= hub[j]) || hlb[j] == INFINITY || hub[j] == -INFINITY) {
             delete h;
-            return fail(QCQP_E_INVALID, "box bounds must be finite with lb <= ub (index %lld)", (long long)j);
+            return fail(QCQP_E_INVALID, "box bounds need lb <= ub, lb < +inf, ub > -inf (index %lld)",
+                        (long long)j);
         }
     for (double v : hq) if (!std::isfinite(v)) { delete h; return fail(QCQP_E_INVALID, "non-finite q"); }
     for (double v : hc) if (!std::isfinite(v)) { delete h; return fail(QCQP_E_INVALID, "non-finite c"); }
@@ -532,6 +545,11 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
     S.c_nm = o.c_nm; S.restart = (int32_t)o.restart; S.restart_from_avg = o.restart_from_average ? 1 : 0;
     S.incremental = h->incremental; S.B = B; S.nblk_step = h->nblk_step; S.nw = (int32_t)h->nw;
     S.variant = o.variant == QCQP_XY ? VAR_XY : VAR_YX;
+    S.lambda_set = P->lambda_set == QCQP_LAMBDA_SIMPLEX ? LAMBDA_SIMPLEX : LAMBDA_NONNEG;
+    S.q0_shift = P->q0_shift;
+    S.ball = P->ball;
+    S.ball_v = P->ball_v;
+    S.ball_l = P->ball_lambda;
     S.restart_every = o.restart_every; S.ada_first = o.ada_first; S.ada_every = o.ada_every;
     S.max_iter = o.max_iter;
     S.eta = o.eta; S.gamma0 = o.gamma0; S.mu = o.mu; S.c_alpha = o.c_alpha; S.c_beta = o.c_beta;
@@ -544,13 +562,16 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
     S.bnorm = std::sqrt(bn);
     S.Q = h->dQ; S.q = dq; S.c = dc; S.A = dA; S.b = db; S.lb = dlb; S.ub = dub;
 
-    // ---- default initial step: 1 / ||Q_0||_2 (or 1 / max_i ||Q_i||_2 without Q_0) ----
+    // ---- default initial step: 1 / ||Q_0 + rho I||_2 (or 1 / max_i ||Q_i||_2 when the
+    //      objective has no quadratic part) ----
     double tau_bar = o.tau_bar;
     if (!(tau_bar > 0.0)) {
         double L = 0.0;
-        if (nq > 0) {
-            const int first = 0, last = has_q0 ? 0 : (int)nq - 1;
-            for (int mat = first; mat <= last; ++mat) {
+        if (has_q0 || P->q0_shift > 0.0) {
+            if (has_q0 && (st = power_norm(h, 0, &L))) { free_handle_memory(h); delete h; return st; }
+            L += P->q0_shift;     // Q_0 is positive semidefinite
+        } else {
+            for (int mat = 0; mat < (int)nq; ++mat) {
                 double lm = 0.0;
                 if ((st = power_norm(h, mat, &lm))) { free_handle_memory(h); delete h; return st; }
                 L = std::max(L, lm);
@@ -802,7 +823,7 @@ static qcqp_status gap_at_device_point(qcqp_handle *h, const double *x_dev, cons
     double *rowabs = v0, *Z = v0 + vs, *D = v0 + 2 * vs, *Dn = v0 + 3 * vs, *Hz = v0 + 4 * vs;
     double *part = v0 + 6 * vs, *ctl = part + 2 * nblk;
     HIPCHK(hipMemsetAsync(Z, 0, 2 * vs * 8, h->stream));   // Z and D
-    HIPCHK(launch_gap_setup(h->stream, h->dslot_eval, (int)n, h->d_ye, h->d_geval, h->d_grad, xi, H,
+    HIPCHK(launch_gap_setup(h->stream, h->dslot_eval, (int)n, (int)h->ny, h->d_ye, h->d_geval, h->d_grad, xi, H,
                             (int)ldh, rowabs, h->opt.inner_tol, ctl));
     const int chunk = 32;
     for (int64_t done_it = 0;;) {
@@ -852,7 +873,7 @@ qcqp_status qcqp_eval_kkt(qcqp_handle *h, const double *x, const double *y, doub
     HIPCHK(join_streams(h->stream, h->ustream, h->ev_join));
     qcqp_status st;
     if ((st = eval_point(h, x, y))) return st;
-    HIPCHK(launch_kkt(h->stream, h->dslot_eval, (int)h->n, h->d_xe, h->d_ye, h->d_ueval, h->d_geval,
+    HIPCHK(launch_kkt(h->stream, h->dslot_eval, (int)h->n, (int)h->ny, h->d_xe, h->d_ye, h->d_ueval, h->d_geval,
                       h->d_kpart, h->d_out6));
     HIPCHK(hipMemcpyAsync(h->h_out, h->d_out6, 6 * 8, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));

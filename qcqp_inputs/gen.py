@@ -37,6 +37,8 @@ class Instance:
     b: np.ndarray | None = None   # (p,)
     has_q0: bool = True
     name: str = ""
+    lambda_set: str = "nonneg"   # "nonneg" (QCQP) or "simplex" (min-max over a simplex)
+    q0_shift: float = 0.0        # the objective's Hessian is Q_0 + q0_shift I
 
     def q_as_float64_numpy(self) -> np.ndarray:
         Q = self.Q
@@ -162,6 +164,72 @@ def kml_qcqp(npts: int = 8000, dim: int = 20, bandwidths=(0.5, 1.0, 2.0, 4.0, 8.
     b = np.zeros(1)
     Qout = Q if (device is not None) else Q.numpy()
     return Instance(n, m, 1, Qout, q, c, lb, ub, A, b, False, f"kml_n{npts}_s{seed}")
+
+
+def kml_minmax(npts: int = 4000, dim: int = 200, density: float = 0.1, lam: float = 1.0,
+               seed: int = 0, device=None, store_dtype=None) -> Instance:
+    """The kernel-learning min-max problem of §5 (min-max-KML) as a saddle problem of this form:
+
+        min_{x >= 0}  max_{y in simplex, v}  lam ||x||^2 - 2 1'x + sum_i y_i (c / r_i) x'H(K_i)x + v b'x
+
+    with H(K) = diag(b) K diag(b), the three kernels of §5 -- polynomial (1 + a'a')^2, Gaussian
+    exp(-0.5 ||a - a'||^2 / 0.1) and linear a'a' -- each normalised to unit diagonal (so
+    r_i = tr K_i = npts), c = sum_i r_i, and the constraint <b, x> = 0 entering through the free
+    multiplier v (p = 1).  In the library's terms: has_q0 = False, q0_shift = 2 lam (the
+    objective's Hessian 2 lam I costs no stored matrix), q_0 = -2 1, Q_i = 2 (c / r_i) H(K_i),
+    q_i = 0, c_i = 0, lambda_set = "simplex", lb = 0, ub = +inf; strongly convex in x with
+    mu = 2 lam.
+
+    Data: a synthetic stand-in for the SIDO0 molecular descriptors (which are not available
+    here): `dim` binary features per point, drawn Bernoulli with a rate that differs between the
+    two classes (labels +-1, balanced), then mean-centred and divided by their standard
+    deviation per column, as §5 describes.
+    """
+    import torch
+    rng = np.random.Generator(np.random.PCG64(seed))
+    half = npts // 2
+    base = rng.uniform(0.5 * density, 1.5 * density, dim)
+    shift = rng.uniform(-0.5, 0.5, dim) * density
+    p_pos = np.clip(base + shift, 0.01, 0.99)
+    p_neg = np.clip(base - shift, 0.01, 0.99)
+    X = np.concatenate([(rng.random((half, dim)) < p_pos).astype(float),
+                        (rng.random((npts - half, dim)) < p_neg).astype(float)])
+    lab = np.concatenate([np.ones(half), -np.ones(npts - half)])
+    perm = rng.permutation(npts)
+    X, lab = X[perm], lab[perm]
+    sd_ = X.std(0)
+    sd_[sd_ == 0] = 1.0
+    X = (X - X.mean(0)) / sd_
+    dev = device or "cpu"
+    sd = store_dtype or torch.float64
+    Xt = torch.from_numpy(X).to(dev)
+    bt = torch.from_numpy(lab).to(dev)
+    G = Xt @ Xt.T
+    sq = torch.diagonal(G).clone()
+    m = 3
+    Q = torch.empty((m, npts, npts), dtype=sd, device=dev)
+    c_total = 3.0 * npts             # sum of the traces of the normalised kernels
+    for i in range(m):
+        if i == 0:
+            K = (1.0 + G) ** 2
+        elif i == 1:
+            K = torch.exp(-0.5 * (sq[:, None] + sq[None, :] - 2.0 * G).clamp_min_(0.0) / 0.1)
+        else:
+            K = G.clone()
+        dg = torch.sqrt(torch.diagonal(K).clamp_min(1e-300))
+        K = K / dg[:, None] / dg[None, :]
+        H = bt[:, None] * K * bt[None, :]
+        H = 0.5 * (H + H.T)
+        Q[i] = (2.0 * c_total / npts * H).to(sd)
+        del K, H
+    q = np.zeros((m + 1, npts))
+    q[0] = -2.0
+    c = np.zeros(m + 1)
+    lb = np.zeros(npts)
+    ub = np.full(npts, np.inf)
+    Qout = Q if (device is not None) else Q.numpy()
+    return Instance(npts, m, 1, Qout, q, c, lb, ub, lab[None, :].copy(), np.zeros(1), False,
+                    f"kmlmm_n{npts}_s{seed}", lambda_set="simplex", q0_shift=2.0 * lam)
 
 
 def serving_trace(num: int, seed: int, n_range=(200, 3000), m_range=(5, 200), rate=None):

@@ -7,6 +7,8 @@ needs one pass) on exactly the stored instance.
     oracle in FP64 on the stored values, is <= 1e-6;
   * kernel-learning QCQP, 8000 points (n=8001, m=5, Q_0 absent, p=1), FP32 and BF16: operator
     parity (U, g, f, grad) at 1e-12;
+  * the paper's kernel-learning min-max form, n=4000 (lambda on the simplex, x >= 0, mu = 2),
+    FP64 and BF16: oracle natural-residual KKT of the GPU solution <= 1e-6;
   * serving requests of the full size range, solved together in one batch: oracle KKT <= 1e-6.
 """
 import numpy as np
@@ -18,10 +20,8 @@ pytestmark = pytest.mark.gpu
 
 
 def _host_instance(inst):
-    import torch
-    Qh = inst.Q.cpu()
-    return qi.Instance(inst.n, inst.m, inst.p, Qh, inst.q, inst.c, inst.lb, inst.ub, inst.A, inst.b,
-                       inst.has_q0, inst.name)
+    import dataclasses
+    return dataclasses.replace(inst, Q=inst.Q.cpu())
 
 
 @pytest.mark.parametrize("storage", ["bfloat16", "float16"])
@@ -66,6 +66,31 @@ def test_kml_workload_full_size_operator(storage):
     np.testing.assert_allclose(to_np(out["g"]), ref["G"][1:], rtol=1e-11, atol=1e-12)
     np.testing.assert_allclose(to_np(out["grad"]), ref["grad"], rtol=1e-11,
                                atol=1e-12 * np.max(np.abs(ref["grad"])))
+
+
+@pytest.mark.parametrize("storage", ["float64", "bfloat16"])
+def test_kml_minmax_full_size_kkt(storage):
+    """The paper's kernel-learning min-max form at its n = 4000 size: lambda on the 3-simplex,
+    x >= 0, b'x = 0 through v, mu = 2; the oracle's natural-residual KKT of the GPU solution."""
+    import torch
+    from paper_2605_29291_amd import Solver
+    announce(f"kml min-max full size n=4000 {storage}")
+    sd = {"float64": torch.float64, "bfloat16": torch.bfloat16}[storage]
+    inst = qi.kml_minmax(4000, seed=qi.config_seed(4), device="cuda", store_dtype=sd)
+    s = Solver(inst, device=True, storage=storage, tau_bar=0.5, gamma0=0.1, mu=2.0,
+               restart_every=200)
+    x, y, info = s.solve()
+    s.close()
+    assert info["status"] == "ok", info
+    host = _host_instance(inst)
+    del inst
+    torch.cuda.empty_cache()
+    kk = oracle.kkt(oracle.Problem(host), to_np(x), to_np(y))
+    assert kk["rel_kkt"] <= 1e-6, kk
+    assert abs(kk["rel_kkt"] - info["rel_kkt"]) <= 1e-9
+    lam = to_np(y)[1:]
+    assert np.all(lam >= 0) and abs(lam.sum() - 1.0) <= 1e-12
+    assert np.all(to_np(x) >= 0)
 
 
 def test_serving_requests_full_size_range_in_one_batch():
