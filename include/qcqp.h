@@ -57,6 +57,13 @@ typedef enum { QCQP_PASS_AUTO = 0, QCQP_PASS_DIRECT = 1, QCQP_PASS_INCREMENTAL =
  * problem into min_x max_{lambda in simplex} f(x) + sum_i lambda_i g_i(x) + <v, Ax - b> (the
  * kernel-learning form (min-max-KML) of §5). */
 typedef enum { QCQP_LAMBDA_NONNEG = 0, QCQP_LAMBDA_SIMPLEX = 1 } qcqp_lambda_set;
+/* When a solve stops.
+ *   KKT:   the relative KKT residual (built from r(x,v,lambda) of the Theorem in §4.3) <= tol.
+ *   PAPER: the criterion of the experiments of §5.1 for a known optimal value f_star,
+ *          max{ |f(x) - f*| / (1 + |f*|), (sum_i max(g_i(x), 0) + sum_l |(Ax - b)_l|) / (m + p) }
+ *          <= tol (the printed mean violation when p = 0; with lambda on the simplex only the
+ *          equalities count). */
+typedef enum { QCQP_STOP_KKT = 0, QCQP_STOP_PAPER = 1 } qcqp_stop_rule;
 
 typedef struct qcqp_handle qcqp_handle;
 typedef struct qcqp_batch qcqp_batch;
@@ -115,7 +122,7 @@ typedef struct {
     int64_t ada_first;         /* first G_xi evaluation, global k (50) */
     int64_t ada_every;         /* later checks at global k % ada_every == 0 (500) */
     int64_t max_iter;          /* iteration cap (50000) */
-    double tol;                /* relative KKT tolerance (1e-6) */
+    double tol;                /* tolerance of the stop rule (1e-6) */
     qcqp_dtype storage;        /* HBM storage type of the Q stack (F64) */
     qcqp_pass_mode pass_mode;  /* AUTO */
     int spec_trials;           /* backtracking candidates evaluated per Q pass, 1..4 (2) */
@@ -127,6 +134,8 @@ typedef struct {
                                   timing mode always launches eagerly */
     void *stream;              /* hipStream_t of the caller; the library works on its own
                                   stream of default priority, ordered after this one */
+    qcqp_stop_rule stop_rule;  /* KKT (default) or PAPER */
+    double f_star;             /* the optimal value the PAPER rule compares against */
 } qcqp_options;
 
 typedef struct {
@@ -144,6 +153,7 @@ typedef struct {
     double last_gap;           /* last G_xi value (NaN if none) */
     int64_t pass_bytes;        /* algorithmic HBM bytes of one Q pass: (m+has_q0) n^2 sizeof(storage) */
     int64_t timed_passes;      /* Q passes covered by pass_seconds */
+    double stop_value;         /* the stop rule's value at the returned iterate */
 } qcqp_info;
 
 /* Fill *o with the defaults listed above.  Never fails. */

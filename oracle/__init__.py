@@ -40,7 +40,8 @@ class _Options(C.Structure):
                 ("eta", C.c_double), ("tau_bar", C.c_double), ("gamma0", C.c_double),
                 ("mu", C.c_double), ("c_alpha", C.c_double), ("c_beta", C.c_double),
                 ("delta", C.c_double), ("xi", C.c_double), ("q_restart", C.c_double),
-                ("tol", C.c_double), ("inner_tol", C.c_double)]
+                ("tol", C.c_double), ("inner_tol", C.c_double),
+                ("stop_rule", C.c_int32), ("pad0", C.c_int32), ("f_star", C.c_double)]
 
 
 class _Info(C.Structure):
@@ -48,7 +49,7 @@ class _Info(C.Structure):
                 ("gap_evals", C.c_int64), ("status", C.c_int64),
                 ("rel_kkt", C.c_double), ("rel_dual", C.c_double), ("rel_pri", C.c_double),
                 ("rel_comp", C.c_double), ("f", C.c_double), ("max_violation", C.c_double),
-                ("last_gap", C.c_double)]
+                ("last_gap", C.c_double), ("stop_value", C.c_double)]
 
 
 def lib():
@@ -97,6 +98,8 @@ class Options:
     q_restart: float = 0.5
     tol: float = 1e-6
     inner_tol: float = 1e-12
+    stop_rule: str = "kkt"          # "kkt" | "paper" (needs f_star)
+    f_star: float = 0.0
 
     @staticmethod
     def xy(**kw) -> "Options":
@@ -113,7 +116,8 @@ class Options:
                         int(self.max_inner), float(self.eta), float(self.tau_bar),
                         float(self.gamma0), float(self.mu), float(self.c_alpha),
                         float(self.c_beta), float(self.delta), float(self.xi),
-                        float(self.q_restart), float(self.tol), float(self.inner_tol))
+                        float(self.q_restart), float(self.tol), float(self.inner_tol),
+                        {"kkt": 0, "paper": 1}[self.stop_rule], 0, float(self.f_star))
 
 
 _DT = {"float64": 0, "float32": 1, "bfloat16": 2, "float16": 3}

@@ -52,6 +52,10 @@
  *        the ball (exact for a cone and a ball centred at 0); with a simplex, only a ball on v.
  *   (R9) with lambda on the simplex, the lambda-part of the KKT residual is the natural residual
  *        || lambda - Pi_simplex(lambda + g(x)) || and g is no constraint (rel_pri covers Ax - b).
+ *  (R10) the experiments' criterion of §5.1, for a known optimal value f*:
+ *        max{ |f(x) - f*| / (1 + |f*|), (sum_i max(g_i(x), 0) + sum_l |(Ax - b)_l|) / (m + p) },
+ *        which is the printed mean violation when p = 0 (with lambda on a simplex only the
+ *        equalities count as constraints).
  */
 #include <math.h>
 #include <stdint.h>
@@ -93,11 +97,15 @@ typedef struct {
     double c_alpha, c_beta, delta;
     double xi, q_restart;
     double tol, inner_tol;
+    int32_t stop_rule;            /* 0: relative KKT (R7); 1: the criterion of §5.1 (R10) */
+    int32_t pad0;
+    double f_star;                /* the optimal value that criterion compares against */
 } orc_options;
 
 typedef struct {
     int64_t iters, trials, restarts, gap_evals, status;
     double rel_kkt, rel_dual, rel_pri, rel_comp, f, max_violation, last_gap;
+    double stop_value;            /* the stop rule's value at the returned point */
 } orc_info;
 
 enum { ORC_CONVERGED = 0, ORC_INVALID = 1, ORC_NOT_CONVERGED = 4, ORC_NUMERICAL = 5 };
@@ -318,6 +326,24 @@ static void kkt_eval(const orc_problem *P, const double *x, const double *y, con
     if (isnan(rel_dual) || isnan(rel_pri) || isnan(rel_comp)) r = NAN;
     out[0] = r; out[1] = rel_dual; out[2] = rel_pri; out[3] = rel_comp;
     out[4] = fval; out[5] = maxv;
+}
+
+/* (R10) the termination criterion of the experiments of §5.1 for a known optimal value f_star:
+ * the larger of the relative suboptimality and the mean constraint violation */
+static double paper_criterion(const orc_problem *P, const double *Gy, double fval, double f_star)
+{
+    const int64_t m = P->m, p = P->p;
+    double viol = 0.0;
+    int64_t cnt = p;
+    for (int64_t l = 0; l < p; ++l) viol += fabs(Gy[l]);
+    if (P->lambda_set != 1) {
+        for (int64_t i = 0; i < m; ++i)
+            if (Gy[p + i] > 0.0) viol += Gy[p + i];
+        cnt += m;
+    }
+    double sub = fabs(fval - f_star) / (1.0 + fabs(f_star));
+    double mv = cnt > 0 ? viol / (double)cnt : 0.0;
+    return sub > mv ? sub : mv;
 }
 
 /* ------------------------------------------------------------------------------------------ */
@@ -729,10 +755,12 @@ int orc_solve(const orc_problem *P, const orc_options *o, const double *x0, cons
     int status = ORC_NOT_CONVERGED;
     orc_epoch ep;
     epoch_init(&S, &ep);
+    double crit = NAN;
     for (;;) {
         kkt_eval(P, S.x, S.y, S.U, S.Gy, S.f, kk);
-        if (isnan(kk[0])) { status = ORC_NUMERICAL; break; }
-        if (kk[0] <= o->tol) { status = ORC_CONVERGED; break; }
+        crit = (o->stop_rule == 1) ? paper_criterion(P, S.Gy, S.f, o->f_star) : kk[0];
+        if (isnan(kk[0]) || isnan(crit)) { status = ORC_NUMERICAL; break; }
+        if (crit <= o->tol) { status = ORC_CONVERGED; break; }
         if (k >= o->max_iter) { status = ORC_NOT_CONVERGED; break; }
         int do_restart = 0;
         if (o->restart == 1 && ep.ke >= o->restart_every) do_restart = 1;
@@ -777,6 +805,7 @@ int orc_solve(const orc_problem *P, const orc_options *o, const double *x0, cons
     info->status = status;
     info->rel_kkt = kk[0]; info->rel_dual = kk[1]; info->rel_pri = kk[2]; info->rel_comp = kk[3];
     info->f = kk[4]; info->max_violation = kk[5]; info->last_gap = last_gap;
+    info->stop_value = crit;
     free_state(&S);
     return status;
 }

@@ -49,7 +49,8 @@ class Options(C.Structure):
                 ("ada_every", C.c_int64), ("max_iter", C.c_int64), ("tol", C.c_double),
                 ("storage", C.c_int), ("pass_mode", C.c_int), ("spec_trials", C.c_int),
                 ("poll_every", C.c_int64), ("timing", C.c_int), ("inner_tol", C.c_double),
-                ("max_inner", C.c_int64), ("use_graphs", C.c_int), ("stream", C.c_void_p)]
+                ("max_inner", C.c_int64), ("use_graphs", C.c_int), ("stream", C.c_void_p),
+                ("stop_rule", C.c_int), ("f_star", C.c_double)]
 
 
 class Info(C.Structure):
@@ -58,7 +59,7 @@ class Info(C.Structure):
                 ("rel_kkt", C.c_double), ("rel_dual", C.c_double), ("rel_pri", C.c_double),
                 ("rel_comp", C.c_double), ("f", C.c_double), ("max_violation", C.c_double),
                 ("seconds", C.c_double), ("pass_seconds", C.c_double), ("last_gap", C.c_double),
-                ("pass_bytes", C.c_int64), ("timed_passes", C.c_int64)]
+                ("pass_bytes", C.c_int64), ("timed_passes", C.c_int64), ("stop_value", C.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -137,6 +138,8 @@ def default_options(**kw) -> Options:
             v = DTYPES.get(v, v)
         elif k == "pass_mode":
             v = PASS_MODES.get(v, v)
+        elif k == "stop_rule":
+            v = {"kkt": 0, "paper": 1}.get(v, v)
         if not hasattr(o, k):
             raise KeyError(k)
         setattr(o, k, v)

@@ -720,7 +720,7 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
         __syncthreads();
         simplex_block(wsm, m);
     }
-    constexpr int NR = NPART + 2 + 3 * B;
+    constexpr int NR = NPART + 3 + 3 * B;   // ..., per-candidate triples, summed violation
     double r[NR];
 #pragma unroll
     for (int f = 0; f < NR; ++f) r[f] = 0.0;
@@ -737,6 +737,7 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
             const double gl = G[l];
             if (l < p) {
                 r[NPART + 1] += gl * gl;
+                r[NR - 1] += fabs(gl);
                 mx = fmax(mx, fabs(gl));
             } else if (simplex) {
                 const double d = y[l] - wsm[l - p];
@@ -747,6 +748,7 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
                 r[NPART] += mn * mn;
                 if (gl > 0.0) {
                     r[NPART + 1] += gl * gl;
+                    r[NR - 1] += gl;
                     mx = fmax(mx, gl);
                 }
             }
@@ -807,12 +809,24 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
         S->kkt[2] = rel_pri;
         S->kkt[3] = rel_comp;
         S->maxviol = kv[2];
+        // stop rule: the relative KKT residual, or the criterion of the experiments of §5.1
+        // (relative suboptimality against f_star and the mean constraint violation)
+        double crit = rk;
+        if (S->stop_rule == 1) {
+            const int cnt = p + (simplex ? 0 : m);
+            const double fs = S->f_star;
+            const double sub = fabs(S->G[ny] - fs) / (1.0 + fabs(fs));
+            const double mv = cnt > 0 ? r[NR - 1] / (double)cnt : 0.0;
+            crit = sub > mv ? sub : mv;
+            if (isnan(sub) || isnan(mv)) crit = NAN;
+        }
+        S->crit = crit;
         int dec = -1;
         S->passes += 1;                 // this group's pass was streamed, whatever follows
-        if (isnan(rk)) {
+        if (isnan(rk) || isnan(crit)) {
             S->status = ST_NUMERICAL;
             dec = -2;
-        } else if (rk <= S->tol) {
+        } else if (crit <= S->tol) {
             if (S->fresh) {
                 S->status = ST_CONVERGED;
             } else {

@@ -58,12 +58,14 @@ struct Slot {
     int32_t ld, dtype;            // row stride (elements) and storage type of Q
     int32_t c_nm, restart, restart_from_avg, incremental;
     int32_t B, nblk_step, nw, variant;   // nw = n rounded up to the pass vector width
-    int32_t lambda_set, pad1;     // dual domain of lambda: R^m_+ or the unit simplex
+    int32_t lambda_set;           // dual domain of lambda: R^m_+ or the unit simplex
+    int32_t stop_rule;            // 0: relative KKT <= tol; 1: the §5.1 criterion against f_star
     double q0_shift;              // rho: the objective's Hessian is Q_0 + rho I
     double ball, ball_v, ball_l;  // dual ball radii (0 = none): ||y||, ||v||, ||lambda||
     int64_t restart_every, ada_first, ada_every, max_iter;
     double eta, tau_bar, gamma0, mu, c_alpha, c_beta, delta, tol, q_restart;
     double cnorm, bnorm;          // ||c_{1..m}||, ||b||  (KKT scales)
+    double f_star;                // optimal value for stop rule 1
     const void *Q;
     const double *q, *c, *A, *b, *lb, *ub;
     // ---- buffers (pointers swapped by k_ctrl on acceptance) ----
@@ -81,6 +83,7 @@ struct Slot {
     // ---- mutable scalars ----
     double tau, tau_prev, sig_prev, gam, sig0, alpha_k, beta_k, T;
     double kkt[4];                // rel_kkt, rel_dual, rel_pri, rel_comp of the iterate
+    double crit;                  // the stop rule's value at the iterate
     double f, maxviol;
     double Gref, last_gap;
     int64_t k, ke, trials, passes, restarts, gap_evals, iter_trials;

@@ -226,6 +226,8 @@ void qcqp_options_default(qcqp_options *o)
     o->max_inner = 100000;
     o->use_graphs = 1;
     o->stream = nullptr;
+    o->stop_rule = QCQP_STOP_KKT;
+    o->f_star = 0.0;
 }
 
 static qcqp_status validate_options(const qcqp_options *o)
@@ -255,6 +257,10 @@ static qcqp_status validate_options(const qcqp_options *o)
     if (o->max_iter < 0) return fail(QCQP_E_INVALID, "max_iter must be >= 0");
     if (!(o->tol >= 0.0)) return fail(QCQP_E_INVALID, "tol must be >= 0");
     if (o->storage < QCQP_F64 || o->storage > QCQP_F16) return fail(QCQP_E_INVALID, "unknown storage type");
+    if (o->stop_rule != QCQP_STOP_KKT && o->stop_rule != QCQP_STOP_PAPER)
+        return fail(QCQP_E_INVALID, "unknown stop rule");
+    if (o->stop_rule == QCQP_STOP_PAPER && !std::isfinite(o->f_star))
+        return fail(QCQP_E_INVALID, "the PAPER stop rule needs a finite f_star");
     if (o->spec_trials < 1 || o->spec_trials > MAXB)
         return fail(QCQP_E_INVALID, "spec_trials must be in 1..%d", MAXB);
     if (o->pass_mode < QCQP_PASS_AUTO || o->pass_mode > QCQP_PASS_INCREMENTAL)
@@ -555,6 +561,8 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
     S.eta = o.eta; S.gamma0 = o.gamma0; S.mu = o.mu; S.c_alpha = o.c_alpha; S.c_beta = o.c_beta;
     S.delta = o.delta;
     S.tol = o.tol; S.q_restart = o.q_restart;
+    S.stop_rule = o.stop_rule == QCQP_STOP_PAPER ? 1 : 0;
+    S.f_star = o.f_star;
     double cn = 0.0, bn = 0.0;
     for (int64_t i = 1; i <= m; ++i) cn += hc[i] * hc[i];
     for (int64_t l = 0; l < p; ++l) bn += hb[l] * hb[l];
@@ -611,6 +619,7 @@ static void reset_run_scalars(Slot &S)
     S.beta_k = S.gamma0 * S.c_beta / S.sig_prev;
     S.T = 0.0;
     for (double &v : S.kkt) v = NAN;
+    S.crit = NAN;
     S.f = NAN;
     S.maxviol = NAN;
     S.Gref = NAN;
@@ -655,6 +664,7 @@ static void fill_info(const qcqp_handle *h, const Slot &S, qcqp_info *info, doub
     info->pass_seconds = pass_secs;
     info->timed_passes = timed;
     info->last_gap = S.last_gap;
+    info->stop_value = S.crit;
     info->pass_bytes = (int64_t)h->nq * h->n * h->n * elem_size(h->dtype);
     switch (S.status) {
     case ST_CONVERGED: info->status = QCQP_OK; break;

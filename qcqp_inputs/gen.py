@@ -104,6 +104,26 @@ def random_qcqp_torch(n: int, m: int, seed: int, shift: float = 0.0, box: float 
     return Instance(n, m, 0, Q, q, c, lb, ub, None, None, True, f"randT_n{n}_m{m}_s{seed}")
 
 
+def paper_random_qcqp(n: int = 1000, m: int = 10, seed: int = 0) -> Instance:
+    """The random QCQPs of the paper's first experiment (§5.1), drawn afresh (its instances and
+    seeds are not published): Q_i = L_i' S_i L_i for i = 0..m with L_i the orthonormal factor of
+    the QR decomposition of an n x n standard Gaussian matrix and S_i diagonal with entries
+    U[0, 100], the smallest set to 0 (so mu = 0); q_i ~ N(0, I); c_0 = 0 and c_i = r_i with
+    -r_i ~ U[0, 1]; X = [-10, 10]^n.  Host numpy PCG64, float64."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Q = np.empty((m + 1, n, n))
+    for i in range(m + 1):
+        L, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        d = rng.uniform(0.0, 100.0, n)
+        d[np.argmin(d)] = 0.0
+        Qi = (L.T * d) @ L
+        Q[i] = 0.5 * (Qi + Qi.T)
+    q = rng.standard_normal((m + 1, n))
+    c = np.concatenate([[0.0], -rng.uniform(0.0, 1.0, m)])
+    lb, ub = _box(n)
+    return Instance(n, m, 0, Q, q, c, lb, ub, None, None, True, f"paper_rand_n{n}_m{m}_s{seed}")
+
+
 def round_instance(inst: Instance, dtype: str) -> Instance:
     """Round Q once (RNE) to 'float32' | 'bfloat16' | 'float16' (torch tensors on Q's device)."""
     import torch

@@ -295,3 +295,4 @@ def test_dual_domain_validation(orc):
     bad_lb = lb.copy()
     bad_lb[0] = np.inf
     assert orc.solve(_problem(orc, Q, q, c, bad_lb, np.full(n, np.inf)), o)["info"]["status"] == "invalid"
+
