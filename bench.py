@@ -501,6 +501,82 @@ def workload_kml_minmax(args):
     }
 
 
+PAPER_ROWS = {
+    "mono rAPDB-xy": dict(variant="xy", c_nm=0, restart="fixed", restart_every=2000),
+    "mono rAPDB-yx": dict(variant="yx", c_nm=0, restart="fixed", restart_every=800),
+    "mono rAPDB-xy-ada": dict(variant="xy", c_nm=0, restart="adaptive", ada_first=100, ada_every=500),
+    "mono rAPDB-yx-ada": dict(variant="yx", c_nm=0, restart="adaptive", ada_first=50, ada_every=200),
+    "mono APDB-xy": dict(variant="xy", c_nm=0, restart="none"),
+    "mono APDB-yx": dict(variant="yx", c_nm=0, restart="none"),
+    "non-mono rAPDB-xy": dict(variant="xy", c_nm=1, restart="fixed", restart_every=1000),
+    "non-mono rAPDB-yx": dict(variant="yx", c_nm=1, restart="fixed", restart_every=400),
+    "non-mono rAPDB-xy-ada": dict(variant="xy", c_nm=1, restart="adaptive", ada_first=100, ada_every=500),
+    "non-mono rAPDB-yx-ada": dict(variant="yx", c_nm=1, restart="adaptive", ada_first=50, ada_every=500),
+    "non-mono APDB-xy": dict(variant="xy", c_nm=1, restart="none"),
+    "non-mono APDB-yx": dict(variant="yx", c_nm=1, restart="none"),
+}
+# the paper's reported iteration counts and A100 GPU seconds for these rows (context only:
+# its instances, f* and step parameters are not available)
+PAPER_TABLE = {
+    "mono rAPDB-xy": (20686, 58), "mono rAPDB-yx": (4609, 18), "mono rAPDB-xy-ada": (28404, 113),
+    "mono rAPDB-yx-ada": (10319, 52), "mono APDB-xy": (50000, 136), "mono APDB-yx": (34947, 133),
+    "non-mono rAPDB-xy": (3008, 18), "non-mono rAPDB-yx": (873, 6), "non-mono rAPDB-xy-ada": (3040, 22),
+    "non-mono rAPDB-yx-ada": (877, 10), "non-mono APDB-xy": (3026, 18), "non-mono APDB-yx": (871, 6),
+}
+
+
+def workload_paper_random(args):
+    """The random-QCQP experiment of §5.1 with its twelve method rows: n = 1000, m = 10, four
+    fresh instances of the paper's generator, FP64, the criterion of §5.1 at 1e-7 with f* from a
+    tight GPU solve (relative KKT <= 1e-11), at most 50000 iterations; eta, c_alpha, c_beta,
+    delta, restart frequencies and adaptive schedules as §5.1 gives them; gamma_0 and tau_bar
+    (unstated in the paper) from the command line and 1 / ||Q_0||."""
+    import torch
+    import qcqp_inputs as qi
+    from paper_2605_29291_amd import Solver
+    n, m = 1000, 10
+    insts = []
+    for k in range(4):
+        log(f"paper random QCQP instance {k}")
+        inst = qi.paper_random_qcqp(n, m, seed=qi.config_seed(6, k))
+        L = float(np.linalg.norm(inst.Q[0], 2))
+        s = Solver(inst, tau_bar=1.0 / L, gamma0=args.gamma0, tol=1e-11, max_iter=400000)
+        x, y, info = s.solve()
+        s.close()
+        log(f"  f* = {info['f']:.12g} ({info['status']}, {info['iters']} iterations, rel-KKT {info['rel_kkt']:.2e})")
+        insts.append((inst, 1.0 / L, info["f"]))
+    rows = {}
+    for name, row in PAPER_ROWS.items():
+        kw = dict(row)
+        if kw["variant"] == "xy":
+            kw.update(c_alpha=0.25, c_beta=0.3, delta=0.4)
+        its, secs, ok = [], [], 0
+        for inst, tb, fs in insts:
+            s = Solver(inst, tau_bar=tb, gamma0=args.gamma0, tol=1e-7, stop_rule="paper", f_star=fs,
+                       max_iter=50000, **kw)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            x, y, info = s.solve()
+            secs.append(time.perf_counter() - t)
+            its.append(info["iters"])
+            ok += info["status"] == "ok"
+            s.close()
+        pi, pg = PAPER_TABLE[name]
+        rows[name] = dict(iters=float(np.mean(its)), iters_each=its, gpu_s=float(np.mean(secs)),
+                          converged=ok, paper_iters=pi, paper_a100_gpu_s=pg)
+        log(f"{name}: {rows[name]}")
+    best = rows["non-mono rAPDB-yx"]
+    return {
+        "metric": METRIC, "value": 1.0 / best["gpu_s"], "unit": "solves/s", "n_gpus": 1, "steps": 4,
+        "warmup": 0, "ms_per_step": best["gpu_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"the paper's random QCQPs (Q_i = L_i' S_i L_i): n=1000, m=10, 4 instances, "
+                               f"criterion of the experiments at 1e-7, non-mono rAPDB-yx restart 400, "
+                               f"gamma0={args.gamma0}"},
+        "roofline": None, "cpu_baseline": None, "rows": rows,
+    }
+
+
 def workload_traffic(args):
     """Dispatches for the HBM-traffic counters (run under rocprofv3 --pmc FETCH_SIZE, then
     WRITE_SIZE): a plain device copy of known size (the calibration), then the config-2 FP64
@@ -597,6 +673,7 @@ def main():
     ap.add_argument("--check", type=int, default=8, help="serving: requests checked by the oracle")
     ap.add_argument("--no-fifo", action="store_true", help="serving: skip the FP64 FIFO comparison")
     ap.add_argument("--kml-iters", type=int, default=20000, help="kml: iteration cap")
+    ap.add_argument("--gamma0", type=float, default=0.1, help="paper_random: gamma_0")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -614,6 +691,8 @@ def main():
         out = workload_precision(args)
     elif args.workload == "kml":
         out = workload_kml(args)
+    elif args.workload == "paper_random":
+        out = workload_paper_random(args)
     elif args.workload == "kml_minmax":
         out = workload_kml_minmax(args)
     elif args.workload == "traffic":

@@ -1,0 +1,74 @@
+"""The twelve method rows of the paper's random-QCQP experiment (§5.1, Table 2) on the GPU, against
+the oracle, on a small instance of the same generator (n = 100, m = 10).
+
+Every row -- (mono / non-mono) x (APDB / rAPDB / rAPDB-ada) x (xy / yx), with the restart
+frequencies and adaptive schedules §5.1 gives -- runs until the criterion of §5.1 (relative
+suboptimality against f* and mean violation) is <= 1e-7, with f* from a tight oracle solve.
+The GPU and the oracle take the same decisions, so they stop at the same iteration (rows with
+adaptive restarts: within 1 %, since G_xi's inner solve ends at a tolerance on both sides), and
+the GPU's stop value is the oracle's evaluation of the returned point.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_common import announce, oracle, qi, to_np
+
+pytestmark = pytest.mark.gpu
+
+XY = dict(c_alpha=0.25, c_beta=0.3, delta=0.4)
+ROWS = {
+    "mono-rAPDB-xy": dict(variant="xy", c_nm=0, restart="fixed", restart_every=2000),
+    "mono-rAPDB-yx": dict(variant="yx", c_nm=0, restart="fixed", restart_every=800),
+    "mono-rAPDB-xy-ada": dict(variant="xy", c_nm=0, restart="adaptive", ada_first=100, ada_every=500),
+    "mono-rAPDB-yx-ada": dict(variant="yx", c_nm=0, restart="adaptive", ada_first=50, ada_every=200),
+    "mono-APDB-xy": dict(variant="xy", c_nm=0, restart="none"),
+    "mono-APDB-yx": dict(variant="yx", c_nm=0, restart="none"),
+    "nonmono-rAPDB-xy": dict(variant="xy", c_nm=1, restart="fixed", restart_every=1000),
+    "nonmono-rAPDB-yx": dict(variant="yx", c_nm=1, restart="fixed", restart_every=400),
+    "nonmono-rAPDB-xy-ada": dict(variant="xy", c_nm=1, restart="adaptive", ada_first=100, ada_every=500),
+    "nonmono-rAPDB-yx-ada": dict(variant="yx", c_nm=1, restart="adaptive", ada_first=50, ada_every=500),
+    "nonmono-APDB-xy": dict(variant="xy", c_nm=1, restart="none"),
+    "nonmono-APDB-yx": dict(variant="yx", c_nm=1, restart="none"),
+}
+
+_CACHE = {}
+
+
+def _instance():
+    if "inst" not in _CACHE:
+        inst = qi.paper_random_qcqp(100, 10, seed=qi.config_seed(6))
+        P = oracle.Problem(inst)
+        L = np.linalg.norm(inst.Q[0], 2)
+        ref = oracle.solve(P, oracle.Options(tau_bar=1 / L, gamma0=1.0, tol=1e-11, max_iter=200000))
+        assert ref["info"]["status"] == "converged"
+        _CACHE["inst"] = (inst, P, 1 / L, ref["info"]["f"])
+    return _CACHE["inst"]
+
+
+@pytest.mark.parametrize("name", list(ROWS))
+def test_table2_row_stops_where_the_oracle_stops(name):
+    from paper_2605_29291_amd import Solver
+    inst, P, tb, f_star = _instance()
+    row = dict(ROWS[name])
+    variant = row.pop("variant")
+    common = dict(tau_bar=tb, gamma0=1.0, tol=1e-7, stop_rule="paper", f_star=f_star,
+                  max_iter=50000, **row)
+    mk = oracle.Options.xy if variant == "xy" else oracle.Options
+    ref = oracle.solve(P, mk(**common))
+    gkw = dict(common, variant=variant, **(XY if variant == "xy" else {}))
+    announce(f"table-2 row {name}: oracle stopped at {ref['info']['iters']}")
+    x, y, info = Solver(inst, **gkw).solve()
+    assert ref["info"]["status"] == "converged" and info["status"] == "ok", (info, ref["info"])
+    k_ref, k = ref["info"]["iters"], info["iters"]
+    if row.get("restart") == "adaptive":
+        assert abs(k - k_ref) <= max(2, 0.01 * k_ref), (k, k_ref)
+    else:
+        assert k == k_ref, (k, k_ref)
+    # the GPU's stop value is the criterion at the returned point, evaluated from the data
+    xs = to_np(x)
+    Q, q, c = inst.Q, inst.q, inst.c
+    f = 0.5 * xs @ Q[0] @ xs + q[0] @ xs
+    g = np.array([0.5 * xs @ Q[i] @ xs + q[i] @ xs + c[i] for i in range(1, inst.m + 1)])
+    crit = max(abs(f - f_star) / (1 + abs(f_star)), float(np.mean(np.maximum(g, 0.0))))
+    assert info["stop_value"] <= 1e-7
+    assert abs(crit - info["stop_value"]) <= 1e-12, (crit, info["stop_value"])
