@@ -29,7 +29,8 @@ class _Problem(C.Structure):
                 ("q", C.c_void_p), ("c", C.c_void_p), ("A", C.c_void_p), ("b", C.c_void_p),
                 ("lb", C.c_void_p), ("ub", C.c_void_p),
                 ("lambda_set", C.c_int32), ("pad0", C.c_int32), ("q0_shift", C.c_double),
-                ("ball", C.c_double), ("ball_v", C.c_double), ("ball_l", C.c_double)]
+                ("ball", C.c_double), ("ball_v", C.c_double), ("ball_l", C.c_double),
+                ("q_stored", C.c_void_p), ("n_soc", C.c_int64), ("soc_dims", C.c_void_p)]
 
 
 class _Options(C.Structure):
@@ -128,7 +129,7 @@ class Problem:
 
     def __init__(self, inst=None, *, Q=None, q=None, c=None, lb=None, ub=None, A=None, b=None,
                  has_q0=True, lambda_set=None, q0_shift=None, ball=0.0, ball_v=0.0,
-                 ball_l=0.0):
+                 ball_l=0.0, q_stored=None, soc_dims=None):
         if inst is not None:
             Q, q, c, lb, ub, A, b, has_q0 = (inst.Q, inst.q, inst.c, inst.lb, inst.ub, inst.A,
                                              inst.b, inst.has_q0)
@@ -136,6 +137,10 @@ class Problem:
                 lambda_set = getattr(inst, "lambda_set", None)
             if q0_shift is None:
                 q0_shift = getattr(inst, "q0_shift", None)
+            if q_stored is None:
+                q_stored = getattr(inst, "q_stored", None)
+            if soc_dims is None:
+                soc_dims = getattr(inst, "soc_dims", None)
         lambda_set = "nonneg" if lambda_set is None else lambda_set
         q0_shift = 0.0 if q0_shift is None else q0_shift
         self.lambda_set = lambda_set
@@ -157,15 +162,25 @@ class Problem:
         else:
             self.A = self.b = None
             self.p = 0
-        nq = self.m + (1 if self.has_q0 else 0)
+        if q_stored is not None:
+            self.q_stored = np.ascontiguousarray(q_stored, dtype=np.int32)
+            assert self.q_stored.shape == (self.m + 1,)
+            nq = int(self.q_stored.sum())
+        else:
+            self.q_stored = None
+            nq = self.m + (1 if self.has_q0 else 0)
+        self.soc_dims = None if soc_dims is None else np.ascontiguousarray(soc_dims, dtype=np.int64)
         assert self.Q.shape == (nq, self.n, self.n), (self.Q.shape, nq, self.n)
         self._c = _Problem(self.n, self.m, self.p, self.Q.ctypes.data, dt, int(self.has_q0),
                            self.q.ctypes.data, self.c.ctypes.data,
                            self.A.ctypes.data if self.A is not None else None,
                            self.b.ctypes.data if self.b is not None else None,
                            self.lb.ctypes.data, self.ub.ctypes.data,
-                           {"nonneg": 0, "simplex": 1}[self.lambda_set], 0, self.q0_shift,
-                           self.ball, self.ball_v, self.ball_l)
+                           {"nonneg": 0, "simplex": 1, "cones": 2}[self.lambda_set], 0,
+                           self.q0_shift, self.ball, self.ball_v, self.ball_l,
+                           _ptr(self.q_stored),
+                           0 if self.soc_dims is None else len(self.soc_dims),
+                           _ptr(self.soc_dims))
 
     @property
     def ny(self):

@@ -26,6 +26,10 @@
  *   - the restricted dual domain Y-hat = Y ∩ B of problem (R-min-max), §3.2: the ball of
  *     eq. (defcalB) or the separable balls of the Remark after it (off unless requested, as in
  *     the experiments of §5);
+ *   - conic constraints g(x) in -K with K = R^{m0}_+ x Q^{k_1} x ... x Q^{k_r}, second-order
+ *     cones (the cone setting of §2.1; K* = K); the closed-form value r* of the Remark after
+ *     Lemma "dual bound" shows the same cone;
+ *   - constraints without a stored matrix (Q_i = 0, affine g_i), listed by a 0/1 map;
  *   - a min-max problem whose lambda ranges over the unit simplex and whose objective carries
  *     rho ||x||^2 / 2 (the kernel-learning form (min-max-KML) of §5, rho = 2 lambda_KML), with
  *     its equality constraint b'x = 0 entering Phi through the multiplier v.
@@ -52,6 +56,10 @@
  *        the ball (exact for a cone and a ball centred at 0); with a simplex, only a ball on v.
  *   (R9) with lambda on the simplex, the lambda-part of the KKT residual is the natural residual
  *        || lambda - Pi_simplex(lambda + g(x)) || and g is no constraint (rel_pri covers Ax - b).
+ *  (R11) with cones, the lambda-part of the KKT residual is || lambda - Pi_K*(lambda + g(x)) ||
+ *        and the infeasibility is dist(g(x), -K) = || Pi_K*(g(x)) || (Moreau's decomposition);
+ *        both reduce to (R7)'s formulas for R^m_+.  The criterion of (R10) counts one violation
+ *        per scalar constraint of R^{m0}_+ and one, dist(g_c, -Q), per cone.
  *  (R10) the experiments' criterion of §5.1, for a known optimal value f*:
  *        max{ |f(x) - f*| / (1 + |f*|), (sum_i max(g_i(x), 0) + sum_l |(Ax - b)_l|) / (m + p) },
  *        which is the printed mean violation when p = 0 (with lambda on a simplex only the
@@ -82,6 +90,13 @@ typedef struct {
     double ball;             /* B > 0: ||y|| <= B, the set of eq. (defcalB); 0: none */
     double ball_v, ball_l;   /* > 0: ||v|| <= B_v, ||lambda|| <= B_lambda (the separable form of
                                 the Remark after eq. (defcalB)); 0: none */
+    const int32_t *q_stored; /* m+1 flags, 1 where Q_i is stored (Q holds those matrices in index
+                                order; the others are 0, e.g. affine constraints); NULL: Q_1..Q_m
+                                stored and Q_0 as has_q0 says */
+    int64_t n_soc;           /* lambda_set 2: lambda in R^{m0}_+ x Q^{k_1} x ... x Q^{k_r}, the
+                                second-order cones at the end of lambda (K* for g(x) in -K with K
+                                the same product, which is self-dual) */
+    const int64_t *soc_dims; /* k_1..k_r, each >= 1, sum <= m */
 } orc_problem;
 
 typedef struct {
@@ -129,14 +144,23 @@ static double bf16_to_double(uint16_t h)
     return (double)f;
 }
 
-/* element (r, j) of Q_i, i = 0..m; returns 0 for Q_0 when it is absent */
-static double qel(const orc_problem *P, int64_t i, int64_t r, int64_t j)
+/* position of Q_i (i = 0..m) among the stored matrices, or -1 when Q_i = 0 is not stored */
+static int64_t stored_index(const orc_problem *P, int64_t i)
 {
-    if (!P->has_q0) {
-        if (i == 0) return 0.0;
-        i -= 1;
+    if (P->q_stored) {
+        if (!P->q_stored[i]) return -1;
+        int64_t s = 0;
+        for (int64_t k = 0; k < i; ++k) s += P->q_stored[k] ? 1 : 0;
+        return s;
     }
-    int64_t idx = (i * P->n + r) * P->n + j;
+    if (!P->has_q0) return i == 0 ? -1 : i - 1;
+    return i;
+}
+
+/* element (r, j) of the stored matrix number s (see stored_index) */
+static double qel(const orc_problem *P, int64_t s, int64_t r, int64_t j)
+{
+    int64_t idx = (s * P->n + r) * P->n + j;
     switch (P->q_dtype) {
     case 0: return ((const double *)P->Q)[idx];
     case 1: return (double)((const float *)P->Q)[idx];
@@ -164,10 +188,11 @@ static void stack_matvec(const orc_problem *P, const double *x, double *U)
 {
     const int64_t n = P->n;
     for (int64_t i = 0; i <= P->m; ++i) {
+        const int64_t si = stored_index(P, i);
         for (int64_t r = 0; r < n; ++r) {
             double s = 0.0;
-            if (i > 0 || P->has_q0) {
-                for (int64_t j = 0; j < n; ++j) s += qel(P, i, r, j) * x[j];
+            if (si >= 0) {
+                for (int64_t j = 0; j < n; ++j) s += qel(P, si, r, j) * x[j];
             }
             if (i == 0) s += P->q0_shift * x[r];      /* (Q_0 + rho I) x */
             U[i * n + r] = s;
@@ -228,6 +253,46 @@ static void project_simplex(double *z, int64_t k)
     for (int64_t i = 0; i < k; ++i) z[i] = z[i] > theta ? z[i] - theta : 0.0;
 }
 
+/* Euclidean projection of z = (t, u) (k entries) onto the second-order cone
+ * Q^k = {(t, u): ||u|| <= t}: z itself inside, 0 inside the polar cone (||u|| <= -t), otherwise
+ * ((t + ||u||) / 2) (1, u / ||u||) (the closed form for the second-order cone, e.g. Fukushima,
+ * Luo and Tseng, 2002).  Q^1 is the half-line t >= 0. */
+static void project_soc(double *z, int64_t k)
+{
+    double t = z[0];
+    double un = k > 1 ? sqrt(nrm2sq(z + 1, k - 1)) : 0.0;
+    if (un <= t) return;
+    if (un <= -t) {
+        for (int64_t i = 0; i < k; ++i) z[i] = 0.0;
+        return;
+    }
+    double a = 0.5 * (t + un);
+    z[0] = a;
+    for (int64_t i = 1; i < k; ++i) z[i] *= a / un;
+}
+
+/* lambda (m entries) onto K*: R^m_+, the unit simplex, or R^{m0}_+ x Q^{k_1} x ... x Q^{k_r} */
+static void project_kstar(const orc_problem *P, double *lam)
+{
+    const int64_t m = P->m;
+    if (P->lambda_set == 1) {
+        project_simplex(lam, m);
+        return;
+    }
+    int64_t m0 = m;
+    if (P->lambda_set == 2)
+        for (int64_t c = 0; c < P->n_soc; ++c) m0 -= P->soc_dims[c];
+    for (int64_t i = 0; i < m0; ++i)
+        if (lam[i] < 0.0) lam[i] = 0.0;
+    if (P->lambda_set == 2) {
+        int64_t off = m0;
+        for (int64_t c = 0; c < P->n_soc; ++c) {
+            project_soc(lam + off, P->soc_dims[c]);
+            off += P->soc_dims[c];
+        }
+    }
+}
+
 /* scale w (k entries) back onto the ball of radius r when it lies outside */
 static void scale_to_ball(double *w, int64_t k, double r)
 {
@@ -239,23 +304,20 @@ static void scale_to_ball(double *w, int64_t k, double r)
 }
 
 /* Euclidean projection onto the dual domain Y-hat = Y ∩ B, y = (v, lambda):
- *   Y = R^p x K*, with K* = R^m_+ for the QCQP (§2.1), or R^p x (unit simplex) for a min-max
- *   problem whose lambda ranges over a simplex;
+ *   Y = R^p x K*, with K* = R^m_+ for the QCQP (§2.1), a product of R^{m0}_+ and second-order
+ *   cones for a conic constraint g(x) in -K (the cone setting of §2.1), or R^p x (unit simplex)
+ *   for a min-max problem whose lambda ranges over a simplex;
  *   B = {||y|| <= B} (eq. (defcalB)) or {||v|| <= B_v} x {||lambda|| <= B_lambda} (the Remark
  *   after it), or the whole space.
- * R^p x R^m_+ is a closed convex cone, and the projection onto the intersection of such a cone
+ * R^p x K* (not the simplex) is a closed convex cone, and the projection onto the intersection
+ * of such a cone
  * with a ball centred at 0 is the cone projection scaled back onto the ball; the separable ball
  * treats v and lambda the same way one block at a time. */
 static void project_y(const orc_problem *P, double *y)
 {
     const int64_t p = P->p, m = P->m;
     double *lam = y + p;
-    if (P->lambda_set == 1) {
-        project_simplex(lam, m);
-    } else {
-        for (int64_t i = 0; i < m; ++i)
-            if (lam[i] < 0.0) lam[i] = 0.0;
-    }
+    project_kstar(P, lam);
     if (P->ball > 0.0) scale_to_ball(y, p + m, P->ball);
     if (P->ball_v > 0.0) scale_to_ball(y, p, P->ball_v);
     if (P->ball_l > 0.0) scale_to_ball(lam, m, P->ball_l);
@@ -292,7 +354,35 @@ static void kkt_eval(const orc_problem *P, const double *x, const double *y, con
         s2 += a2 * a2;
     }
     double rl = 0, pri = 0, cn = 0, bn = 0, maxv = 0;
-    if (P->lambda_set == 1) {
+    if (P->lambda_set == 2) {
+        /* cones: r_l = ||lambda - Pi_K*(lambda + g)||, infeasibility dist(g, -K) = ||Pi_K*(g)||
+         * (Moreau), per block for the maximum */
+        double *w = malloc(sizeof(double) * (m > 0 ? m : 1));
+        double *gv = malloc(sizeof(double) * (m > 0 ? m : 1));
+        if (!w || !gv) { free(w); free(gv); for (int k = 0; k < 6; ++k) out[k] = NAN; return; }
+        for (int64_t i = 0; i < m; ++i) {
+            w[i] = y[p + i] + Gy[p + i];
+            gv[i] = Gy[p + i];
+            cn += P->c[i + 1] * P->c[i + 1];
+        }
+        project_kstar(P, w);
+        project_kstar(P, gv);
+        int64_t m0 = m;
+        for (int64_t c = 0; c < P->n_soc; ++c) m0 -= P->soc_dims[c];
+        for (int64_t i = 0; i < m; ++i) {
+            double d = y[p + i] - w[i];
+            rl += d * d;
+            pri += gv[i] * gv[i];
+            if (i < m0 && gv[i] > maxv) maxv = gv[i];
+        }
+        int64_t off = m0;
+        for (int64_t c = 0; c < P->n_soc; ++c) {
+            double b = sqrt(nrm2sq(gv + off, P->soc_dims[c]));
+            if (b > maxv) maxv = b;
+            off += P->soc_dims[c];
+        }
+        free(w); free(gv);
+    } else if (P->lambda_set == 1) {
         double *w = malloc(sizeof(double) * (m > 0 ? m : 1));
         if (!w) { for (int k = 0; k < 6; ++k) out[k] = NAN; return; }
         for (int64_t i = 0; i < m; ++i) w[i] = y[p + i] + Gy[p + i];
@@ -336,10 +426,26 @@ static double paper_criterion(const orc_problem *P, const double *Gy, double fva
     double viol = 0.0;
     int64_t cnt = p;
     for (int64_t l = 0; l < p; ++l) viol += fabs(Gy[l]);
-    if (P->lambda_set != 1) {
+    if (P->lambda_set == 0) {
         for (int64_t i = 0; i < m; ++i)
             if (Gy[p + i] > 0.0) viol += Gy[p + i];
         cnt += m;
+    } else if (P->lambda_set == 2) {
+        /* one violation per scalar constraint of R^{m0}_+ and one per cone, dist(g_c, -Q) */
+        double *gv = malloc(sizeof(double) * (m > 0 ? m : 1));
+        if (!gv) return NAN;
+        memcpy(gv, Gy + p, sizeof(double) * m);
+        project_kstar(P, gv);
+        int64_t m0 = m;
+        for (int64_t c = 0; c < P->n_soc; ++c) m0 -= P->soc_dims[c];
+        for (int64_t i = 0; i < m0; ++i) viol += gv[i];
+        int64_t off = m0;
+        for (int64_t c = 0; c < P->n_soc; ++c) {
+            viol += sqrt(nrm2sq(gv + off, P->soc_dims[c]));
+            off += P->soc_dims[c];
+        }
+        cnt += m0 + P->n_soc;
+        free(gv);
     }
     double sub = fabs(fval - f_star) / (1.0 + fabs(f_star));
     double mv = cnt > 0 ? viol / (double)cnt : 0.0;
@@ -390,12 +496,17 @@ static int gap_eval(const orc_problem *P, const double *x, const double *y, doub
     }
 
     /* x-part: H = Q(lambda) + 2 xi I, with Q(lambda) = Q_0 + rho I + sum lambda_i Q_i */
+    int64_t *sidx = malloc(sizeof(int64_t) * (m + 1));
+    if (!sidx) { free(U); free(Gy); free(gx); free(H); free(D); free(Dn); free(Z); free(gz); return -1; }
+    for (int64_t i = 0; i <= m; ++i) sidx[i] = stored_index(P, i);
     for (int64_t r = 0; r < n; ++r)
         for (int64_t j = 0; j < n; ++j) {
-            double h = qel(P, 0, r, j);
-            for (int64_t i = 1; i <= m; ++i) h += y[p + i - 1] * qel(P, i, r, j);
+            double h = sidx[0] >= 0 ? qel(P, sidx[0], r, j) : 0.0;
+            for (int64_t i = 1; i <= m; ++i)
+                if (sidx[i] >= 0) h += y[p + i - 1] * qel(P, sidx[i], r, j);
             H[r * n + j] = h + (r == j ? 2.0 * xi + P->q0_shift : 0.0);
         }
+    free(sidx);
     double L = 0.0;   /* Gershgorin bound on lambda_max(H) */
     for (int64_t r = 0; r < n; ++r) {
         double s = 0.0;
@@ -721,7 +832,21 @@ static int validate(const orc_problem *P, const orc_options *o)
     }
     for (int64_t j = 0; j < P->n; ++j)
         if (!(P->lb[j] <= P->ub[j]) || P->lb[j] == INFINITY || P->ub[j] == -INFINITY) return -1;
-    if (P->lambda_set != 0 && P->lambda_set != 1) return -1;
+    if (P->lambda_set < 0 || P->lambda_set > 2) return -1;
+    if (P->lambda_set == 2) {
+        if (P->n_soc < 1 || !P->soc_dims) return -1;
+        int64_t tot = 0;
+        for (int64_t c = 0; c < P->n_soc; ++c) {
+            if (P->soc_dims[c] < 1) return -1;
+            tot += P->soc_dims[c];
+        }
+        if (tot > P->m) return -1;
+    }
+    if (P->q_stored) {
+        if (P->q_stored[0] != (P->has_q0 ? 1 : 0)) return -1;
+        for (int64_t i = 0; i <= P->m; ++i)
+            if (P->q_stored[i] != 0 && P->q_stored[i] != 1) return -1;
+    }
     if (P->lambda_set == 1 && (P->m < 1 || P->ball > 0.0 || P->ball_l > 0.0)) return -1;
     if (!(P->q0_shift >= 0.0 && P->ball >= 0.0 && P->ball_v >= 0.0 && P->ball_l >= 0.0)) return -1;
     if (P->ball > 0.0 && (P->ball_v > 0.0 || P->ball_l > 0.0)) return -1;

@@ -154,7 +154,8 @@ struct qcqp_handle {
     int pass_grid = 1, nt = 0;
     double *d_ueval = nullptr, *d_geval = nullptr, *d_grad = nullptr, *d_kpart = nullptr,
            *d_out6 = nullptr, *d_xe = nullptr, *d_ye = nullptr;
-    Slot *h_poll = nullptr;   // pinned
+    Slot *h_poll = nullptr;   // pinned: two status snapshots (pipelined polls)
+    hipEvent_t ev_snap[2] = {nullptr, nullptr};   // recorded after each snapshot copy
     double *h_out = nullptr;  // pinned scratch (16 doubles)
     qcqp_batch *owner = nullptr;
     double *gap_mem = nullptr;  // G_xi scratch: H (n x ldh), 6 vectors, partials, control
@@ -280,6 +281,10 @@ static void free_handle_memory(qcqp_handle *h)
     if (h->dQ) (void)hipFree(h->dQ);
     if (h->arena) (void)hipFree(h->arena);
     if (h->h_poll) (void)hipHostFree(h->h_poll);
+    for (auto &x : h->ev_snap) {
+        if (x) (void)hipEventDestroy(x);
+        x = nullptr;
+    }
     if (h->h_out) (void)hipHostFree(h->h_out);
     if (h->gap_mem) (void)hipFree(h->gap_mem);
     h->gap_mem = nullptr;
@@ -537,7 +542,9 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
     if (e == hipSuccess) e = hipMemcpyAsync(dlb, hlb.data(), n * 8, k, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(dub, hub.data(), n * 8, k, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_poll, sizeof(Slot));
+    if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_poll, 2 * sizeof(Slot));
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_snap[0], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_snap[1], hipEventDisableTiming);
     if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_out, 16 * sizeof(double));
     if (e != hipSuccess) {
         free_handle_memory(h);
@@ -702,8 +709,9 @@ qcqp_status qcqp_solve(qcqp_handle *h, const double *x0, const double *y0, doubl
     HIPCHK(launch_start(h->stream, h->dslot));
     int64_t poll = h->opt.poll_every;
     if (poll <= 0) {
-        const double bytes = (double)h->q_bytes;
-        poll = bytes > 64e6 ? 4 : (bytes > 4e6 ? 16 : 64);
+        // about 1 ms of work per chunk, from the pass at ~5 TB/s plus ~40 us of small kernels
+        const double group_s = (double)h->q_bytes / 5e12 + 40e-6;
+        poll = std::max<int64_t>(4, (int64_t)std::ceil(1e-3 / group_s));
     }
     const bool timing = h->opt.timing != 0;
     std::vector<hipEvent_t> ev;
@@ -714,7 +722,7 @@ qcqp_status qcqp_solve(qcqp_handle *h, const double *x0, const double *y0, doubl
     double pass_secs = 0.0;
     int64_t timed = 0;
     const int ntiles = (int)h->tiles.size();
-    Slot &snap = *h->h_poll;
+    Slot snap = S0;           // the last status snapshot read on the host
     qcqp_status result = QCQP_OK;
     int64_t passes_before = 0;
     auto launch_chunk = [&](hipStream_t s, bool with_events) -> hipError_t {
@@ -735,13 +743,52 @@ qcqp_status qcqp_solve(qcqp_handle *h, const double *x0, const double *y0, doubl
         HIPCHK(capture_graph(h->stream, [&](hipStream_t s) { return launch_chunk(s, false); }, &h->gexec));
         h->gexec_groups = poll;
     }
-    for (;;) {
-        hipError_t el = graphs ? hipGraphLaunch(h->gexec, h->stream) : launch_chunk(h->stream, timing);
+    // Pipelined polls (eager launches without timing, and graphs): one chunk is always queued
+    // behind the one whose status snapshot the host reads, so the device does not idle for the
+    // host round trip.  Once the slot stops running every later group returns at once, so the
+    // extra chunk is a no-op; at a pending G_xi evaluation the queue is drained first.
+    if (!timing) {
+        auto enqueue = [&](int buf) -> hipError_t {
+            hipError_t e = graphs ? hipGraphLaunch(h->gexec, h->stream) : launch_chunk(h->stream, false);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(&h->h_poll[buf], h->dslot, sizeof(Slot), hipMemcpyDeviceToHost, h->stream);
+            if (e == hipSuccess) e = hipEventRecord(h->ev_snap[buf], h->stream);
+            return e;
+        };
+        int pending = 0;
+        hipError_t e = enqueue(0);
+        while (e == hipSuccess) {
+            e = enqueue(1 - pending);
+            if (e == hipSuccess) e = hipEventSynchronize(h->ev_snap[pending]);
+            if (e != hipSuccess) break;
+            const Slot &sn = h->h_poll[pending];
+            if (sn.status == ST_GAP_PENDING) {
+                e = hipStreamSynchronize(h->stream);   // the queued chunk saw the same pending state
+                if (e != hipSuccess) break;
+                double gval = 0.0, kk[6];
+                snap = sn;
+                if ((result = run_gap_for(h, h->dslot, snap, &gval, kk))) break;
+                pending = 0;
+                e = enqueue(0);
+                continue;
+            }
+            if (sn.status != ST_RUNNING) {
+                e = hipStreamSynchronize(h->stream);
+                snap = sn;
+                break;
+            }
+            pending = 1 - pending;
+        }
+        if (e != hipSuccess && !result) result = fail(QCQP_E_DEVICE, "launch/poll: %s", hipGetErrorString(e));
+    }
+    for (; timing && !result;) {
+        hipError_t el = launch_chunk(h->stream, true);
         if (el != hipSuccess) { result = fail(QCQP_E_DEVICE, "launch: %s", hipGetErrorString(el)); break; }
-        hipError_t e = hipMemcpyAsync(&snap, h->dslot, sizeof(Slot), hipMemcpyDeviceToHost, h->stream);
+        hipError_t e = hipMemcpyAsync(&h->h_poll[0], h->dslot, sizeof(Slot), hipMemcpyDeviceToHost, h->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
         if (e != hipSuccess) { result = fail(QCQP_E_DEVICE, "poll: %s", hipGetErrorString(e)); break; }
-        if (timing) {
+        snap = h->h_poll[0];
+        {
             // the groups that streamed a pass are the first (passes now - passes before) of the
             // chunk: once the slot stops running every later group is a no-op
             const int64_t worked = std::min<int64_t>(poll, snap.passes - passes_before);

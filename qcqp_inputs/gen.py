@@ -37,8 +37,11 @@ class Instance:
     b: np.ndarray | None = None   # (p,)
     has_q0: bool = True
     name: str = ""
-    lambda_set: str = "nonneg"   # "nonneg" (QCQP) or "simplex" (min-max over a simplex)
+    lambda_set: str = "nonneg"   # "nonneg" (QCQP), "simplex" (min-max over a simplex) or
+                                 # "cones" (R^{m0}_+ x second-order cones of sizes soc_dims)
     q0_shift: float = 0.0        # the objective's Hessian is Q_0 + q0_shift I
+    q_stored: object = None      # (m+1,) 0/1: which Q_i are stored in Q (None: all but Q_0 per has_q0)
+    soc_dims: object = None      # second-order cone sizes at the end of lambda ("cones")
 
     def q_as_float64_numpy(self) -> np.ndarray:
         Q = self.Q
