@@ -53,10 +53,17 @@ typedef enum { QCQP_RESTART_NONE = 0, QCQP_RESTART_FIXED = 1, QCQP_RESTART_ADAPT
  *                and the start re-anchor U with a direct pass accumulated in FP64.
  *   AUTO:        DIRECT for FP64 storage, INCREMENTAL otherwise. */
 typedef enum { QCQP_PASS_AUTO = 0, QCQP_PASS_DIRECT = 1, QCQP_PASS_INCREMENTAL = 2 } qcqp_pass_mode;
-/* Where lambda ranges: R^m_+ (K* of the QCQP's cone, §2.1), or the unit simplex, which turns the
- * problem into min_x max_{lambda in simplex} f(x) + sum_i lambda_i g_i(x) + <v, Ax - b> (the
- * kernel-learning form (min-max-KML) of §5). */
-typedef enum { QCQP_LAMBDA_NONNEG = 0, QCQP_LAMBDA_SIMPLEX = 1 } qcqp_lambda_set;
+/* Where lambda ranges:
+ *   NONNEG:  R^m_+, K* for the QCQP's constraints g(x) <= 0 (§2.1);
+ *   SIMPLEX: the unit simplex, which turns the problem into
+ *            min_x max_{lambda in simplex} f(x) + sum_i lambda_i g_i(x) + <v, Ax - b>
+ *            (the kernel-learning form (min-max-KML) of §5);
+ *   CONES:   R^{m0}_+ x Q^{k_1} x ... x Q^{k_r} for the conic constraint g(x) in -K with the
+ *            same (self-dual) product of second-order cones Q^k = {(t, u): ||u|| <= t} placed
+ *            at the end of lambda (the cone setting of §2.1; m0 = m - sum k_j).  Convexity of
+ *            lambda'g(x) over K* is the caller's: e.g. g_1 convex quadratic and the other
+ *            components of a cone affine. */
+typedef enum { QCQP_LAMBDA_NONNEG = 0, QCQP_LAMBDA_SIMPLEX = 1, QCQP_LAMBDA_CONES = 2 } qcqp_lambda_set;
 /* When a solve stops.
  *   KKT:   the relative KKT residual (built from r(x,v,lambda) of the Theorem in §4.3) <= tol.
  *   PAPER: the criterion of the experiments of §5.1 for a known optimal value f_star,
@@ -75,9 +82,10 @@ typedef struct qcqp_batch qcqp_batch;
  * plain QCQP. */
 typedef struct {
     int64_t n, m, p;           /* n > 0, m >= 0, 0 <= p < n (rank(A) = p is assumed, not checked) */
-    const void *Q;             /* (m + has_q0) matrices, each n rows of ldq elements, row-major,
-                                  element type Q_dtype; Q_0 first when has_q0.  Must be
-                                  symmetric: the library uses Q_i x = Q_i' x. */
+    const void *Q;             /* the stored matrices (m + has_q0 of them, or as q_stored lists),
+                                  each n rows of ldq elements, row-major, element type Q_dtype,
+                                  in index order (Q_0 first when has_q0).  Must be symmetric:
+                                  the library uses Q_i x = Q_i' x. */
     qcqp_dtype Q_dtype;        /* element type of the caller's Q */
     int64_t ldq;               /* leading dimension in elements (>= n; 0 means n) */
     int has_q0;                /* 0: Q_0 = 0 and is neither stored nor streamed */
@@ -97,6 +105,11 @@ typedef struct {
                                   form of the Remark after eq. (defcalB); 0: off.  Not combined
                                   with `ball`; with the simplex only ball_v is allowed.
                                   The experiments of §5 impose no ball. */
+    const int *q_stored;       /* NULL, or m+1 flags 0/1: which Q_i are stored in Q; the others
+                                  are 0 (affine constraints), stream no bytes and need no
+                                  memory.  q_stored[0] must equal has_q0.  Host memory. */
+    int64_t n_soc;             /* CONES: number of second-order cones r >= 1 */
+    const int64_t *soc_dims;   /* CONES: k_1..k_r >= 1, sum <= m; host memory */
 } qcqp_problem;
 
 /* Method parameters (Algorithm 1, the APDB-yx rules of §3.2, Algorithm 2, eq. (ada_restart)).

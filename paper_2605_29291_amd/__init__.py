@@ -51,7 +51,7 @@ class Solver:
 
     def __init__(self, inst=None, *, Q=None, q=None, c=None, lb=None, ub=None, A=None, b=None,
                  has_q0=True, lambda_set=None, q0_shift=None, ball=0.0, ball_v=0.0,
-                 ball_lambda=0.0, device=None, **options):
+                 ball_lambda=0.0, q_stored=None, soc_dims=None, device=None, **options):
         if inst is not None:
             Q, q, c, lb, ub, A, b, has_q0 = (inst.Q, inst.q, inst.c, inst.lb, inst.ub, inst.A,
                                              inst.b, inst.has_q0)
@@ -59,6 +59,10 @@ class Solver:
                 lambda_set = getattr(inst, "lambda_set", None)
             if q0_shift is None:
                 q0_shift = getattr(inst, "q0_shift", None)
+            if q_stored is None:
+                q_stored = getattr(inst, "q_stored", None)
+            if soc_dims is None:
+                soc_dims = getattr(inst, "soc_dims", None)
         lambda_set = "nonneg" if lambda_set is None else lambda_set
         q0_shift = 0.0 if q0_shift is None else q0_shift
         L = load()
@@ -104,11 +108,16 @@ class Solver:
                 qcode = _q_dtype_code(Qa)
                 self._keep.append(Qa)
                 qptr = Qa.ctypes.data
+        qs = None if q_stored is None else np.ascontiguousarray(q_stored, dtype=np.int32)
+        sd = None if soc_dims is None else np.ascontiguousarray(soc_dims, dtype=np.int64)
+        self._keep += [a for a in (qs, sd) if a is not None]
         prob = abi.Problem(self.n, self.m, self.p, qptr, qcode, 0, 1 if has_q0 else 0,
                            vec(q), vec(c), vec(A) if self.p else None, vec(b) if self.p else None,
                            vec(lb), vec(ub), 1 if self.on_device else 0,
-                           {"nonneg": 0, "simplex": 1}[lambda_set], float(q0_shift), float(ball),
-                           float(ball_v), float(ball_lambda))
+                           {"nonneg": 0, "simplex": 1, "cones": 2}[lambda_set], float(q0_shift),
+                           float(ball), float(ball_v), float(ball_lambda),
+                           None if qs is None else qs.ctypes.data,
+                           0 if sd is None else len(sd), None if sd is None else sd.ctypes.data)
         if "stream" not in options:
             options["stream"] = _current_stream()
         self.options = abi.default_options(**options)

@@ -36,7 +36,8 @@ class Problem(C.Structure):
                 ("q", C.c_void_p), ("c", C.c_void_p), ("A", C.c_void_p), ("b", C.c_void_p),
                 ("lb", C.c_void_p), ("ub", C.c_void_p), ("on_device", C.c_int),
                 ("lambda_set", C.c_int), ("q0_shift", C.c_double), ("ball", C.c_double),
-                ("ball_v", C.c_double), ("ball_lambda", C.c_double)]
+                ("ball_v", C.c_double), ("ball_lambda", C.c_double), ("q_stored", C.c_void_p),
+                ("n_soc", C.c_int64), ("soc_dims", C.c_void_p)]
 
 
 class Options(C.Structure):

@@ -101,20 +101,85 @@ __device__ void simplex_block(double *w, int k)
     __syncthreads();
 }
 
-// y = (v, lambda) (ny entries) onto Y-hat = Y ∩ B (problem (R-min-max), §3.2): lambda onto
-// R^m_+ or the simplex, then the ball ||y|| <= B (eq. (defcalB)) or ||v|| <= B_v,
-// ||lambda|| <= B_lambda (the separable form): scaled back when outside, which is the exact
-// projection for the cone R^p x R^m_+ intersected with a ball centred at 0.
+// z = (t, u) (k entries) onto the second-order cone Q^k = {||u|| <= t} by one thread: z inside,
+// 0 inside the polar cone (||u|| <= -t), otherwise ((t + ||u||) / 2) (1, u / ||u||)
+__device__ __forceinline__ void soc_serial(double *z, int k)
+{
+    const double t = z[0];
+    double s = 0.0;
+    for (int i = 1; i < k; ++i) s = fma(z[i], z[i], s);
+    const double un = sqrt(s);
+    if (un <= t) return;
+    if (un <= -t) {
+        for (int i = 0; i < k; ++i) z[i] = 0.0;
+        return;
+    }
+    const double a = 0.5 * (t + un);
+    z[0] = a;
+    for (int i = 1; i < k; ++i) z[i] *= a / un;
+}
+
+// lambda (m entries, LDS or global) onto K*: R^m_+, the unit simplex, or
+// R^{m0}_+ x Q^{k_1} x ... x Q^{k_r} (cones smaller than SOC_BLOCK_DIM one per thread, larger
+// ones by the whole block with a fixed-order reduction)
+__device__ void project_kstar_block(const Slot *S, double *lam)
+{
+    const int m = S->m, tid = threadIdx.x;
+    if (S->lambda_set == LAMBDA_SIMPLEX) {
+        simplex_block(lam, m);
+        return;
+    }
+    const int m0 = S->lambda_set == LAMBDA_CONES ? S->m0 : m;
+    for (int l = tid; l < m0; l += STEP_BS)
+        if (lam[l] < 0.0) lam[l] = 0.0;
+    if (S->lambda_set == LAMBDA_CONES) {
+        const int nc = S->n_soc;
+        const int32_t *off = S->soc_off, *dim = S->soc_off + nc;
+        for (int c = tid; c < nc; c += STEP_BS)
+            if (dim[c] < SOC_BLOCK_DIM) soc_serial(lam + off[c], dim[c]);
+        __shared__ double s_soc[2];
+        for (int bi = 0; bi < S->n_soc_big; ++bi) {
+            const int c = S->soc_big[bi];
+            double *z = lam + off[c];
+            const int k = dim[c];
+            double v[1] = {0.0};
+            for (int i = 1 + tid; i < k; i += STEP_BS) v[0] = fma(z[i], z[i], v[0]);
+            block_sum<1>(v);
+            if (tid == 0) {
+                const double t = z[0], un = sqrt(v[0]);
+                double a = t, f = 1.0;
+                if (!(un <= t)) {
+                    if (un <= -t) {
+                        a = 0.0;
+                        f = 0.0;
+                    } else {
+                        a = 0.5 * (t + un);
+                        f = a / un;
+                    }
+                }
+                s_soc[0] = a;
+                s_soc[1] = f;
+            }
+            __syncthreads();
+            const double a = s_soc[0], f = s_soc[1];
+            if (f != 1.0)
+                for (int i = 1 + tid; i < k; i += STEP_BS) z[i] *= f;
+            if (tid == 0) z[0] = a;
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+}
+
+// y = (v, lambda) (ny entries) onto Y-hat = Y ∩ B (problem (R-min-max), §3.2): lambda onto K*
+// (R^m_+, a product with second-order cones, or the simplex), then the ball ||y|| <= B
+// (eq. (defcalB)) or ||v|| <= B_v, ||lambda|| <= B_lambda (the separable form): scaled back
+// when outside, which is the exact projection for a closed convex cone intersected with a ball
+// centred at 0.
 __device__ void project_dual_block(const Slot *S, double *w)
 {
-    const int p = S->p, m = S->m, ny = S->ny, tid = threadIdx.x;
-    if (S->lambda_set == LAMBDA_SIMPLEX) {
-        simplex_block(w + p, m);
-    } else {
-        for (int l = p + tid; l < ny; l += STEP_BS)
-            if (w[l] < 0.0) w[l] = 0.0;
-        __syncthreads();
-    }
+    const int p = S->p, ny = S->ny, tid = threadIdx.x;
+    project_kstar_block(S, w + p);
     const double B = S->ball, Bv = S->ball_v, Bl = S->ball_l;
     if (B > 0.0 || Bv > 0.0 || Bl > 0.0) {
         __shared__ double s_f[2];
@@ -149,7 +214,7 @@ __device__ void project_dual_block(const Slot *S, double *w)
 // ---------------------------------------------------------------------------------------
 // step kernel: dual step then primal step for B candidate step sizes (eq. (apdb-yx-y)):
 //   sigma = gamma tau, theta = sigma_{k-1}/sigma, s = (1+theta) G^k - theta G^{k-1},
-//   y+ = Pi_{Y-hat}(y + sigma s)   (lambda in R^m_+ or the simplex, v free, optional ball),
+//   y+ = Pi_{Y-hat}(y + sigma s)   (lambda in K* or the simplex, v free, optional ball),
 //   x+ = Pi_X(x - tau grad_x Phi(x^k, y+)),  grad from the cached U^k = [Q_i x^k].
 // Also the KKT partials of the iterate (x^k, y^k).
 
@@ -711,14 +776,20 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
     // ---- 1+2. one fixed-order block reduction of everything the decision needs:
     //   step partials (KKT pieces of the iterate, ||d_b||^2), ||min(lambda,-g)||^2,
     //   ||([g]+, Ax-b)||^2, and per candidate 1/2 d'Q(lambda+)d terms, ||dG||^2, ||dy||^2 ----
-    // lambda on the simplex: the lambda-part of the KKT residual is the natural residual
-    // lambda - Pi_simplex(lambda + g(x)); the projected point is staged in LDS
+    // lambda on the simplex or on cones: the lambda-part of the KKT residual is the natural
+    // residual lambda - Pi_K*(lambda + g(x)), and with cones the infeasibility is
+    // dist(g, -K) = ||Pi_K*(g)||; the projected points are staged in LDS (wsm, wsm + m)
     extern __shared__ double wsm[];
     const bool simplex = S->lambda_set == LAMBDA_SIMPLEX;
-    if (simplex) {
-        for (int l = tid; l < m; l += STEP_BS) wsm[l] = S->y[p + l] + S->G[p + l];
+    const bool cones = S->lambda_set == LAMBDA_CONES;
+    if (simplex || cones) {
+        for (int l = tid; l < m; l += STEP_BS) {
+            wsm[l] = S->y[p + l] + S->G[p + l];
+            if (cones) wsm[m + l] = S->G[p + l];
+        }
         __syncthreads();
-        simplex_block(wsm, m);
+        project_kstar_block(S, wsm);
+        if (cones) project_kstar_block(S, wsm + m);
     }
     constexpr int NR = NPART + 3 + 3 * B;   // ..., per-candidate triples, summed violation
     double r[NR];
@@ -742,6 +813,15 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
             } else if (simplex) {
                 const double d = y[l] - wsm[l - p];
                 r[NPART] += d * d;
+            } else if (cones) {
+                const double d = y[l] - wsm[l - p];
+                const double gp = wsm[m + l - p];
+                r[NPART] += d * d;
+                r[NPART + 1] += gp * gp;
+                if (l - p < S->m0) {
+                    r[NR - 1] += gp;
+                    mx = fmax(mx, gp);
+                }
             } else {
                 const double lam = y[l];
                 const double mn = lam < -gl ? lam : -gl;
@@ -751,6 +831,19 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
                     r[NR - 1] += gl;
                     mx = fmax(mx, gl);
                 }
+            }
+        }
+        if (cones) {
+            // one violation dist(g_c, -Q) = ||Pi_Q(g_c)|| per cone
+            const int nc = S->n_soc;
+            const int32_t *off = S->soc_off, *dim = S->soc_off + nc;
+            for (int c = tid; c < nc; c += STEP_BS) {
+                double sq = 0.0;
+                const double *z = wsm + m + off[c];
+                for (int i = 0; i < dim[c]; ++i) sq = fma(z[i], z[i], sq);
+                const double v = sqrt(sq);
+                r[NR - 1] += v;
+                mx = fmax(mx, v);
             }
         }
         const bool xy = S->variant == VAR_XY;
@@ -813,7 +906,7 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
         // (relative suboptimality against f_star and the mean constraint violation)
         double crit = rk;
         if (S->stop_rule == 1) {
-            const int cnt = p + (simplex ? 0 : m);
+            const int cnt = p + (simplex ? 0 : (cones ? S->m0 + S->n_soc : m));
             const double fs = S->f_star;
             const double sub = fabs(S->G[ny] - fs) / (1.0 + fabs(fs));
             const double mv = cnt > 0 ? r[NR - 1] / (double)cnt : 0.0;
@@ -1062,13 +1155,28 @@ __global__ void __launch_bounds__(STEP_BS) k_kkt_fin(const Slot *__restrict__ S,
     block_sum<4>(tot);
     extern __shared__ double wsm[];
     const bool simplex = S->lambda_set == LAMBDA_SIMPLEX;
-    if (simplex) {
-        for (int l = tid; l < m; l += STEP_BS) wsm[l] = y[p + l] + G[p + l];
+    const bool cones = S->lambda_set == LAMBDA_CONES;
+    if (simplex || cones) {
+        for (int l = tid; l < m; l += STEP_BS) {
+            wsm[l] = y[p + l] + G[p + l];
+            if (cones) wsm[m + l] = G[p + l];
+        }
         __syncthreads();
-        simplex_block(wsm, m);
+        project_kstar_block(S, wsm);
+        if (cones) project_kstar_block(S, wsm + m);
     }
     double kv[2] = {0.0, 0.0};
     double mx = 0.0;
+    if (cones) {
+        const int nc = S->n_soc;
+        const int32_t *off = S->soc_off, *dim = S->soc_off + nc;
+        for (int c = tid; c < nc; c += STEP_BS) {
+            double sq = 0.0;
+            const double *z = wsm + m + off[c];
+            for (int i = 0; i < dim[c]; ++i) sq = fma(z[i], z[i], sq);
+            mx = fmax(mx, sqrt(sq));
+        }
+    }
     for (int l = tid; l < ny; l += STEP_BS) {
         const double gl = G[l];
         if (l < p) {
@@ -1077,6 +1185,12 @@ __global__ void __launch_bounds__(STEP_BS) k_kkt_fin(const Slot *__restrict__ S,
         } else if (simplex) {
             const double d = y[l] - wsm[l - p];
             kv[0] += d * d;
+        } else if (cones) {
+            const double d = y[l] - wsm[l - p];
+            const double gp = wsm[m + l - p];
+            kv[0] += d * d;
+            kv[1] += gp * gp;
+            if (l - p < S->m0) mx = fmax(mx, gp);
         } else {
             const double lam = y[l];
             const double mn = lam < -gl ? lam : -gl;
@@ -1215,17 +1329,17 @@ __global__ void __launch_bounds__(STEP_BS) k_form_h(const Slot *__restrict__ S,
     const int n = S->n, m = S->m, p = S->p, r = blockIdx.x;
     const size_t ld = (size_t)S->ld;
     const int dt = S->dtype;
-    const int has_q0 = S->has_q0;
+    const int32_t *qmap = S->qmap;
     double v[1] = {0.0};
     for (int j = n + threadIdx.x; j < ldh; j += STEP_BS) H[(size_t)r * ldh + j] = 0.0;   // padding
     for (int j = threadIdx.x; j < n; j += STEP_BS) {
         double h = 0.0;
-        if (has_q0) h = load_any(S->Q, dt, (size_t)r * ld + j);
+        if (qmap[0] >= 0) h = load_any(S->Q, dt, ((size_t)qmap[0] * n + r) * ld + j);
         for (int i = 1; i <= m; ++i) {
             const double w = y[p + i - 1];
-            if (w == 0.0) continue;
-            const size_t mat = (size_t)(i - 1 + has_q0);
-            h += w * load_any(S->Q, dt, (mat * n + r) * ld + j);
+            const int si = qmap[i];
+            if (w == 0.0 || si < 0) continue;
+            h += w * load_any(S->Q, dt, ((size_t)si * n + r) * ld + j);
         }
         if (j == r) h += 2.0 * xi + S->q0_shift;
         H[(size_t)r * ldh + j] = h;
@@ -1401,7 +1515,7 @@ static hipError_t group_b(hipStream_t s, Slot *slots, const int *live, int nslot
     if (ev1) (void)hipEventRecord(ev1, s);
     k_epi<B><<<dim3(max_epi, nslots), STEP_BS, 0, s>>>(slots, live);
     if (variants & HAS_XY) k_post_xy<B><<<vgrid, STEP_BS, step_lds, s>>>(slots, live);
-    k_ctrl<B><<<nslots, STEP_BS, (size_t)(max_ny > 0 ? max_ny : 1) * sizeof(double), s>>>(slots, live);
+    k_ctrl<B><<<nslots, STEP_BS, (size_t)(max_ny > 0 ? 2 * max_ny : 1) * sizeof(double), s>>>(slots, live);
     return hipGetLastError();
 }
 
@@ -1438,7 +1552,7 @@ hipError_t launch_kkt(hipStream_t s, const Slot *slot, int n, int ny, const doub
 {
     const int nblk = (n + STEP_BS - 1) / STEP_BS;
     k_kkt_part<<<nblk, STEP_BS, 0, s>>>(slot, x, y, U, part);
-    k_kkt_fin<<<1, STEP_BS, (size_t)(ny > 0 ? ny : 1) * sizeof(double), s>>>(slot, nblk, y, G, part, out6);
+    k_kkt_fin<<<1, STEP_BS, (size_t)(ny > 0 ? 2 * ny : 1) * sizeof(double), s>>>(slot, nblk, y, G, part, out6);
     return hipGetLastError();
 }
 

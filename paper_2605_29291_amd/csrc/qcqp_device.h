@@ -46,7 +46,11 @@ enum StoreType : int32_t { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2, DT_F16 = 3 };
 
 enum Variant : int32_t { VAR_YX = 0, VAR_XY = 1 };
 
-enum LambdaSet : int32_t { LAMBDA_NONNEG = 0, LAMBDA_SIMPLEX = 1 };
+enum LambdaSet : int32_t { LAMBDA_NONNEG = 0, LAMBDA_SIMPLEX = 1, LAMBDA_CONES = 2 };
+
+// second-order cones of at least this dimension are projected by a whole block, smaller ones by
+// one thread each
+constexpr int SOC_BLOCK_DIM = 128;
 
 // bit mask of the variants present among the slots of a launch
 constexpr int HAS_YX = 1, HAS_XY = 2;
@@ -62,6 +66,11 @@ struct Slot {
     int32_t stop_rule;            // 0: relative KKT <= tol; 1: the §5.1 criterion against f_star
     double q0_shift;              // rho: the objective's Hessian is Q_0 + rho I
     double ball, ball_v, ball_l;  // dual ball radii (0 = none): ||y||, ||v||, ||lambda||
+    int32_t n_soc, m0;            // cones: count, and the R_+ entries of lambda before them
+    int32_t n_soc_big, pad2;      // cones of dimension >= SOC_BLOCK_DIM
+    const int32_t *soc_off;       // n_soc start offsets within lambda, then n_soc dimensions
+    const int32_t *soc_big;       // indices of the large cones
+    const int32_t *qmap;          // m+1: position of Q_i among the stored matrices, -1 if absent
     int64_t restart_every, ada_first, ada_every, max_iter;
     double eta, tau_bar, gamma0, mu, c_alpha, c_beta, delta, tol, q_restart;
     double cnorm, bnorm;          // ||c_{1..m}||, ||b||  (KKT scales)
@@ -94,9 +103,10 @@ struct Slot {
 
 struct Tile {
     int32_t slot;
-    int32_t row0;    // first stored row (0 .. nq*n)
+    int32_t row0;    // first stored row (0 .. nq*n); a tile lies within one stored matrix
     int32_t nrows;
     int32_t lpr;     // lanes per row: 16, 32 or 64
+    int32_t uoff;    // output row of stored row r is uoff + r: (i - s) n for Q_i stored s-th
 };
 
 // ---- launch wrappers (kernels.hip) ----

@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(PASS_BS) k_pass(Slot *__restrict__ slots,
     const int t1 = (int)(((int64_t)(blockIdx.x + 1) * ntiles) / G);
     int cur = -1;
     bool active = false, anchor = false, inc = false;
-    int n = 0, nw = 0, uoff = 0;
+    int n = 0, nw = 0;
     size_t ld = 0;
     const void *Q = nullptr;
     double *outs[B];
@@ -218,7 +218,6 @@ __global__ void __launch_bounds__(PASS_BS) k_pass(Slot *__restrict__ slots,
                 inc = S->incremental != 0;
                 n = S->n;
                 nw = S->nw;
-                uoff = S->has_q0 ? 0 : n;
                 ld = (size_t)S->ld;
                 Q = S->Q;
                 const double *x = S->x;
@@ -247,11 +246,11 @@ __global__ void __launch_bounds__(PASS_BS) k_pass(Slot *__restrict__ slots,
             // direct pass at the iterate, accumulated in FP64 whatever the storage type
             double *const o1[1] = {outs[0]};
             pass_rows_lpr<DT, double, 1, NT>(t.lpr, Q, n, ld, t.row0, t.nrows,
-                                             reinterpret_cast<const double *>(smem), nw, o1, uoff);
+                                             reinterpret_cast<const double *>(smem), nw, o1, t.uoff);
         } else {
             double *const (&co)[B] = outs;
             pass_rows_lpr<DT, AT, B, NT, PassShape<DT>::R, PassShape<DT>::UNR>(
-                t.lpr, Q, n, ld, t.row0, t.nrows, reinterpret_cast<const AT *>(smem), nw, co, uoff);
+                t.lpr, Q, n, ld, t.row0, t.nrows, reinterpret_cast<const AT *>(smem), nw, co, t.uoff);
         }
     }
 }

@@ -335,9 +335,28 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
     if (ldq < n) return fail(QCQP_E_INVALID, "ldq < n");
     if (!P->q || !P->c || !P->lb || !P->ub) return fail(QCQP_E_INVALID, "q, c, lb, ub are required");
     if (p > 0 && (!P->A || !P->b)) return fail(QCQP_E_INVALID, "A and b are required when p > 0");
-    if ((P->has_q0 || m > 0) && !P->Q) return fail(QCQP_E_INVALID, "Q is required");
+    if (P->q_stored) {
+        if ((P->q_stored[0] != 0) != (P->has_q0 != 0))
+            return fail(QCQP_E_INVALID, "q_stored[0] must equal has_q0");
+        for (int64_t i = 0; i <= m; ++i)
+            if (P->q_stored[i] != 0 && P->q_stored[i] != 1) return fail(QCQP_E_INVALID, "q_stored flags must be 0 or 1");
+    }
+    int64_t nstored = 0;
+    for (int64_t i = 0; i <= m; ++i)
+        nstored += P->q_stored ? P->q_stored[i] : (i == 0 ? (P->has_q0 ? 1 : 0) : 1);
+    if (nstored > 0 && !P->Q) return fail(QCQP_E_INVALID, "Q is required");
+    if (P->lambda_set == QCQP_LAMBDA_CONES) {
+        if (P->n_soc < 1 || !P->soc_dims) return fail(QCQP_E_INVALID, "CONES needs n_soc >= 1 and soc_dims");
+        int64_t tot = 0;
+        for (int64_t c = 0; c < P->n_soc; ++c) {
+            if (P->soc_dims[c] < 1) return fail(QCQP_E_INVALID, "cone dimensions must be >= 1");
+            tot += P->soc_dims[c];
+        }
+        if (tot > m) return fail(QCQP_E_INVALID, "cone dimensions sum to %lld > m", (long long)tot);
+    }
     if (P->Q_dtype < QCQP_F64 || P->Q_dtype > QCQP_F16) return fail(QCQP_E_INVALID, "unknown Q_dtype");
-    if (P->lambda_set != QCQP_LAMBDA_NONNEG && P->lambda_set != QCQP_LAMBDA_SIMPLEX)
+    if (P->lambda_set != QCQP_LAMBDA_NONNEG && P->lambda_set != QCQP_LAMBDA_SIMPLEX &&
+        P->lambda_set != QCQP_LAMBDA_CONES)
         return fail(QCQP_E_INVALID, "unknown lambda_set");
     if (P->lambda_set == QCQP_LAMBDA_SIMPLEX && m < 1) return fail(QCQP_E_INVALID, "the simplex needs m >= 1");
     if (!(P->q0_shift >= 0.0) || !std::isfinite(P->q0_shift)) return fail(QCQP_E_INVALID, "q0_shift must be finite and >= 0");
@@ -350,7 +369,28 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
     if (P->lambda_set == QCQP_LAMBDA_SIMPLEX && (P->ball > 0.0 || P->ball_lambda > 0.0))
         return fail(QCQP_E_INVALID, "with the simplex only the ball on v is supported");
     const int has_q0 = P->has_q0 ? 1 : 0;
-    const int64_t nq = m + has_q0;
+    const int64_t nq = nstored;
+    // position of Q_i among the stored matrices (-1: Q_i = 0, not stored)
+    std::vector<int32_t> qmap(m + 1, -1);
+    {
+        int32_t sidx = 0;
+        for (int64_t i = 0; i <= m; ++i)
+            if (P->q_stored ? P->q_stored[i] != 0 : (i > 0 || has_q0)) qmap[i] = sidx++;
+    }
+    // cone tables: start offsets within lambda, dimensions, and the large cones
+    std::vector<int32_t> soc_tab, soc_big;
+    int64_t m0 = m;
+    if (P->lambda_set == QCQP_LAMBDA_CONES) {
+        for (int64_t c = 0; c < P->n_soc; ++c) m0 -= P->soc_dims[c];
+        soc_tab.resize(2 * P->n_soc);
+        int64_t off = m0;
+        for (int64_t c = 0; c < P->n_soc; ++c) {
+            soc_tab[c] = (int32_t)off;
+            soc_tab[P->n_soc + c] = (int32_t)P->soc_dims[c];
+            if (P->soc_dims[c] >= SOC_BLOCK_DIM) soc_big.push_back((int32_t)c);
+            off += P->soc_dims[c];
+        }
+    }
 
     qcqp_handle *h = new (std::nothrow) qcqp_handle();
     if (!h) return fail(QCQP_E_NOMEM, "host allocation");
@@ -496,6 +536,11 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
     plan.push_back({&h->d_out6, 8});
     plan.push_back({&h->d_xe, n});
     plan.push_back({&h->d_ye, ny + 1});
+    // int32 tables, each in whole doubles: the stored-matrix map and the cone tables
+    double *d_qmap = nullptr, *d_soc = nullptr, *d_socbig = nullptr;
+    plan.push_back({&d_qmap, (m + 2) / 2});
+    if (!soc_tab.empty()) plan.push_back({&d_soc, ((int64_t)soc_tab.size() + 1) / 2});
+    if (!soc_big.empty()) plan.push_back({&d_socbig, ((int64_t)soc_big.size() + 1) / 2});
     size_t total = 0;
     for (auto &pr : plan) total += (size_t)round_up(pr.second * 8, 256);
     const size_t slot_off = total;
@@ -506,8 +551,16 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
     int lpr = 16, rpt = 16;
     tile_shape(n, h->dtype, nq * n, &lpr, &rpt);
     const int64_t rows = nq * n;
-    for (int64_t r0 = 0; r0 < rows; r0 += rpt)
-        h->tiles.push_back(Tile{0, (int32_t)r0, (int32_t)std::min<int64_t>(rpt, rows - r0), lpr});
+    (void)rows;
+    // tiles lie within one stored matrix; each carries the offset from its stored rows to the
+    // rows of U it produces (Q_i stored s-th writes U_i)
+    for (int64_t i = 0; i <= m; ++i) {
+        if (qmap[i] < 0) continue;
+        const int64_t sbase = (int64_t)qmap[i] * n;
+        for (int64_t r0 = 0; r0 < n; r0 += rpt)
+            h->tiles.push_back(Tile{0, (int32_t)(sbase + r0), (int32_t)std::min<int64_t>(rpt, n - r0), lpr,
+                                    (int32_t)((i - qmap[i]) * n)});
+    }
     const size_t tile_off = total;
     total += round_up((int64_t)std::max<size_t>(h->tiles.size(), 1) * sizeof(Tile), 256);
     h->pass_grid = pass_grid_for(B, h->dtype, (int)h->nw);
@@ -539,6 +592,11 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
     if (e == hipSuccess) e = hipMemcpyAsync(dc, hc.data(), (m + 1) * 8, k, h->stream);
     if (e == hipSuccess && p) e = hipMemcpyAsync(dA, hA.data(), p * n * 8, k, h->stream);
     if (e == hipSuccess && p) e = hipMemcpyAsync(db, hb.data(), p * 8, k, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_qmap, qmap.data(), (m + 1) * sizeof(int32_t), k, h->stream);
+    if (e == hipSuccess && d_soc)
+        e = hipMemcpyAsync(d_soc, soc_tab.data(), soc_tab.size() * sizeof(int32_t), k, h->stream);
+    if (e == hipSuccess && d_socbig)
+        e = hipMemcpyAsync(d_socbig, soc_big.data(), soc_big.size() * sizeof(int32_t), k, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(dlb, hlb.data(), n * 8, k, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(dub, hub.data(), n * 8, k, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -558,8 +616,15 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
     S.c_nm = o.c_nm; S.restart = (int32_t)o.restart; S.restart_from_avg = o.restart_from_average ? 1 : 0;
     S.incremental = h->incremental; S.B = B; S.nblk_step = h->nblk_step; S.nw = (int32_t)h->nw;
     S.variant = o.variant == QCQP_XY ? VAR_XY : VAR_YX;
-    S.lambda_set = P->lambda_set == QCQP_LAMBDA_SIMPLEX ? LAMBDA_SIMPLEX : LAMBDA_NONNEG;
     S.q0_shift = P->q0_shift;
+    S.n_soc = (int32_t)(P->lambda_set == QCQP_LAMBDA_CONES ? P->n_soc : 0);
+    S.m0 = (int32_t)m0;
+    S.n_soc_big = (int32_t)soc_big.size();
+    S.soc_off = reinterpret_cast<const int32_t *>(d_soc);
+    S.soc_big = reinterpret_cast<const int32_t *>(d_socbig);
+    S.qmap = reinterpret_cast<const int32_t *>(d_qmap);
+    S.lambda_set = P->lambda_set == QCQP_LAMBDA_SIMPLEX ? LAMBDA_SIMPLEX
+                   : (P->lambda_set == QCQP_LAMBDA_CONES ? LAMBDA_CONES : LAMBDA_NONNEG);
     S.ball = P->ball;
     S.ball_v = P->ball_v;
     S.ball_l = P->ball_lambda;

@@ -127,6 +127,46 @@ def paper_random_qcqp(n: int = 1000, m: int = 10, seed: int = 0) -> Instance:
     return Instance(n, m, 0, Q, q, c, lb, ub, None, None, True, f"paper_rand_n{n}_m{m}_s{seed}")
 
 
+def random_conic_qcqp(n: int, m_lin: int, soc_dims, seed: int, p: int = 0,
+                      box: float = 10.0) -> Instance:
+    """Convex problem with the constraint g(x) in -K, K = R^{m_lin}_+ x Q^{k_1} x ... (second-order
+    cones at the end).  Objective and the m_lin scalar constraints: Q_i = A_iA_i'/n (+0.1 I for Q_0),
+    q_i ~ N(0, I), c_i ~ U(-1, -0.1).  Each cone: a convex quadratic leading component of the same
+    kind and affine tail components q ~ N(0, I/n) with no stored matrix, constants chosen so that
+    x = 0 lies strictly inside (-c_lead > ||c_tail||): a Slater point.  Host numpy PCG64."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dims = [int(k) for k in soc_dims]
+    m = m_lin + sum(dims)
+    stored = np.zeros(m + 1, dtype=np.int32)
+    stored[0] = 1
+    stored[1:m_lin + 1] = 1
+    off = m_lin + 1
+    for k in dims:
+        stored[off] = 1                        # the cone's leading component is quadratic
+        off += k
+    mats = []
+    for i in range(m + 1):
+        if stored[i]:
+            A = rng.standard_normal((n, n))
+            Qi = A @ A.T / n + (0.1 * np.eye(n) if i == 0 else 0.0)
+            mats.append(0.5 * (Qi + Qi.T))
+    Q = np.stack(mats)
+    q = rng.standard_normal((m + 1, n))
+    c = np.concatenate([[0.0], rng.uniform(-1.0, -0.1, m)])
+    off = m_lin + 1
+    for k in dims:
+        q[off + 1:off + k] /= np.sqrt(n)
+        tail = rng.uniform(-0.3, 0.3, k - 1)
+        c[off + 1:off + k] = tail
+        c[off] = -(0.5 + np.linalg.norm(tail))
+        off += k
+    lb, ub = _box(n, -box, box)
+    A = rng.standard_normal((p, n)) if p else None
+    b = (A @ rng.uniform(-0.1, 0.1, n)) if p else None
+    return Instance(n, m, p, Q, q, c, lb, ub, A, b, True, f"conic_n{n}_m{m_lin}_k{dims}_s{seed}",
+                    lambda_set="cones", q_stored=stored, soc_dims=dims)
+
+
 def round_instance(inst: Instance, dtype: str) -> Instance:
     """Round Q once (RNE) to 'float32' | 'bfloat16' | 'float16' (torch tensors on Q's device)."""
     import torch
