@@ -580,6 +580,56 @@ def workload_paper_random(args):
     }
 
 
+def workload_batch_pass(args):
+    """Pass bandwidth of a full continuous batch at steady state: requests of the serving trace
+    (n ~ U[200, 3000], m ~ U[5, 200], BF16 storage) are admitted up to a byte budget, two
+    groups run untimed (start anchors), then 8 groups are timed with HIP events around each
+    pass launch; bytes are the live slots' stacks.  Live sets of 1, 8, 32, 128 and all that fit
+    in 64 GB."""
+    import torch
+    import qcqp_inputs as qi
+    from paper_2605_29291_amd import Batch, Solver
+    storage = "bfloat16"
+    trace = qi.serving_trace(512, qi.config_seed(5))
+    out = {}
+    for k in (1, 8, 32, 128, 512):
+        b = Batch(max_slots=k, hbm_budget_bytes=int(64e9), storage=storage, spec_trials=2, timing=1)
+        admitted, held = 0, []
+        for r in trace[:k]:
+            inst = _gen_request(r, storage)
+            s = Solver(inst, device=True, storage=storage, tau_bar=0.0, gamma0=0.1, spec_trials=2)
+            del inst
+            if b.admit(s) is None:
+                s.close()
+                break
+            held.append(s)
+            admitted += 1
+        torch.cuda.synchronize()
+        b.step(2)
+        st0 = b.pass_stats()
+        b.step(8)
+        st1 = b.pass_stats()
+        s0, by0, s1, by1 = st0["pass_seconds"], st0["pass_bytes"], st1["pass_seconds"], st1["pass_bytes"]
+        gbs = (by1 - by0) / max(s1 - s0, 1e-12) / 1e9
+        out[f"slots{admitted}"] = dict(slots=admitted, pass_GBs=gbs, frac=gbs / HBM_PEAK_GBS,
+                                       bytes_per_group=(by1 - by0) / 8, us_per_group_pass=(s1 - s0) / 8 * 1e6)
+        log(f"batch pass: {out[f'slots{admitted}']}")
+        b.close()
+        for s in held:
+            s.close()
+        torch.cuda.empty_cache()
+        if admitted < k:
+            break
+    last = list(out.values())[-1]
+    return {"metric": METRIC, "value": last["pass_GBs"], "unit": "GB/s", "n_gpus": 1, "steps": 8,
+            "warmup": 2, "ms_per_step": last["us_per_group_pass"] / 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "bf16-storage", "data": "synthetic",
+            "config": {"workload": "continuous batch of serving-trace requests, BF16, steady-state pass"},
+            "roofline": {"bound": "hbm", "achieved": last["pass_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": last["frac"], "traffic": None, "kernel": "k_pass<DT_BF16,2>"},
+            "cpu_baseline": None, "per_batch": out}
+
+
 def workload_traffic(args):
     """Dispatches for the HBM-traffic counters (run under rocprofv3 --pmc FETCH_SIZE, then
     WRITE_SIZE): a plain device copy of known size (the calibration), then the config-2 FP64
@@ -695,6 +745,8 @@ def main():
         out = workload_precision(args)
     elif args.workload == "kml":
         out = workload_kml(args)
+    elif args.workload == "batch_pass":
+        out = workload_batch_pass(args)
     elif args.workload == "paper_random":
         out = workload_paper_random(args)
     elif args.workload == "kml_minmax":

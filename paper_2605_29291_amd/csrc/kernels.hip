@@ -1503,6 +1503,7 @@ hipError_t launch_gap_finish(hipStream_t s, int n, const double *grad, const dou
 
 template <int B>
 static hipError_t group_b(hipStream_t s, Slot *slots, const int *live, int nslots, const Tile *tiles, int ntiles,
+                          const int *starts,
                           int dtype, int variants, int max_nblk_step, int max_ny, int max_nw, int max_epi,
                           int pass_grid, int nt, hipEvent_t ev0, hipEvent_t ev1)
 {
@@ -1511,7 +1512,7 @@ static hipError_t group_b(hipStream_t s, Slot *slots, const int *live, int nslot
     if (variants & HAS_YX) k_step<B><<<vgrid, STEP_BS, step_lds, s>>>(slots, live);
     if (variants & HAS_XY) k_step_xy<B><<<vgrid, STEP_BS, step_lds, s>>>(slots, live);
     if (ev0) (void)hipEventRecord(ev0, s);
-    (void)launch_pass_only(s, slots, tiles, ntiles, B, dtype, max_nw, pass_grid, nt);
+    (void)launch_pass_only(s, slots, tiles, ntiles, starts, B, dtype, max_nw, pass_grid, nt);
     if (ev1) (void)hipEventRecord(ev1, s);
     k_epi<B><<<dim3(max_epi, nslots), STEP_BS, 0, s>>>(slots, live);
     if (variants & HAS_XY) k_post_xy<B><<<vgrid, STEP_BS, step_lds, s>>>(slots, live);
@@ -1520,15 +1521,15 @@ static hipError_t group_b(hipStream_t s, Slot *slots, const int *live, int nslot
 }
 
 hipError_t launch_group(hipStream_t s, Slot *slots, const int *live, int nslots, const Tile *tiles,
-                        int ntiles, int B, int dtype, int variants, int max_nblk_step, int max_ny,
-                        int max_nw, int max_epi, int pass_grid, int nt, hipEvent_t ev0,
-                        hipEvent_t ev1)
+                        int ntiles, const int *starts, int B, int dtype, int variants,
+                        int max_nblk_step, int max_ny, int max_nw, int max_epi, int pass_grid,
+                        int nt, hipEvent_t ev0, hipEvent_t ev1)
 {
     switch (B) {
-    case 1: return group_b<1>(s, slots, live, nslots, tiles, ntiles, dtype, variants, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
-    case 2: return group_b<2>(s, slots, live, nslots, tiles, ntiles, dtype, variants, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
-    case 3: return group_b<3>(s, slots, live, nslots, tiles, ntiles, dtype, variants, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
-    default: return group_b<4>(s, slots, live, nslots, tiles, ntiles, dtype, variants, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
+    case 1: return group_b<1>(s, slots, live, nslots, tiles, ntiles, starts, dtype, variants, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
+    case 2: return group_b<2>(s, slots, live, nslots, tiles, ntiles, starts, dtype, variants, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
+    case 3: return group_b<3>(s, slots, live, nslots, tiles, ntiles, starts, dtype, variants, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
+    default: return group_b<4>(s, slots, live, nslots, tiles, ntiles, starts, dtype, variants, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1);
     }
 }
 

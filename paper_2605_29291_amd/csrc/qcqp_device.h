@@ -111,12 +111,14 @@ struct Tile {
 
 // ---- launch wrappers (kernels.hip) ----
 // one trial group for the slots listed in live[0..nslots); variants = HAS_YX | HAS_XY mask
+// tiles[starts[b] .. starts[b+1]) go to pass block b (starts: min(pass_grid, ntiles) + 1 entries,
+// or NULL for equal tile counts per block)
 hipError_t launch_group(hipStream_t s, Slot *slots, const int *live, int nslots, const Tile *tiles,
-                        int ntiles, int B, int dtype, int variants, int max_nblk_step, int max_ny,
-                        int max_nw, int max_epi, int pass_grid, int nt, hipEvent_t ev0,
-                        hipEvent_t ev1);
-hipError_t launch_pass_only(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles, int B,
-                            int dtype, int max_nw, int pass_grid, int nt);
+                        int ntiles, const int *starts, int B, int dtype, int variants,
+                        int max_nblk_step, int max_ny, int max_nw, int max_epi, int pass_grid,
+                        int nt, hipEvent_t ev0, hipEvent_t ev1);
+hipError_t launch_pass_only(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles,
+                            const int *starts, int B, int dtype, int max_nw, int pass_grid, int nt);
 // persistent pass grid: resident blocks per CU of k_pass for this configuration
 int pass_blocks_per_cu(int B, int dtype, int max_nw);
 size_t pass_lds_bytes(int B, int dtype, int max_nw);

@@ -182,7 +182,8 @@ __device__ __forceinline__ void pass_rows_lpr(int lpr, const void *Q, int n, siz
 {
     if (lpr == 64) pass_rows<DT, AT, B, 64, NT, R, UNR>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
     else if (lpr == 32) pass_rows<DT, AT, B, 32, NT, R, UNR>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
-    else pass_rows<DT, AT, B, 16, NT, R, UNR>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
+    else if (lpr == 16) pass_rows<DT, AT, B, 16, NT, R, UNR>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
+    else pass_rows<DT, AT, B, 8, NT, R, UNR>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
 }
 
 // The pass kernel runs a persistent grid: block b streams the contiguous tile range
@@ -191,13 +192,16 @@ __device__ __forceinline__ void pass_rows_lpr(int lpr, const void *Q, int n, siz
 // grouped by slot).
 template <int DT, int B, bool NT>
 __global__ void __launch_bounds__(PASS_BS) k_pass(Slot *__restrict__ slots,
-                                                  const Tile *__restrict__ tiles, int ntiles)
+                                                  const Tile *__restrict__ tiles, int ntiles,
+                                                  const int *__restrict__ starts)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     using AT = typename Store<DT>::acc_t;
     const int G = gridDim.x;
-    const int t0 = (int)(((int64_t)blockIdx.x * ntiles) / G);
-    const int t1 = (int)(((int64_t)(blockIdx.x + 1) * ntiles) / G);
+    // block b streams tiles [starts[b], starts[b+1]): ranges of nearly equal bytes (or of equal
+    // tile counts when no table is given)
+    const int t0 = starts ? starts[blockIdx.x] : (int)(((int64_t)blockIdx.x * ntiles) / G);
+    const int t1 = starts ? starts[blockIdx.x + 1] : (int)(((int64_t)(blockIdx.x + 1) * ntiles) / G);
     int cur = -1;
     bool active = false, anchor = false, inc = false;
     int n = 0, nw = 0;
@@ -206,8 +210,11 @@ __global__ void __launch_bounds__(PASS_BS) k_pass(Slot *__restrict__ slots,
     double *outs[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) outs[b] = nullptr;
+    // the next tile's descriptor is loaded while the current tile streams
+    Tile tn = t0 < t1 ? tiles[t0] : Tile{};
     for (int ti = t0; ti < t1; ++ti) {
-        const Tile t = tiles[ti];
+        const Tile t = tn;
+        if (ti + 1 < t1) tn = tiles[ti + 1];
         if (t.slot != cur) {
             __syncthreads();   // every wave is done with the previous slot's w
             cur = t.slot;
@@ -245,8 +252,8 @@ __global__ void __launch_bounds__(PASS_BS) k_pass(Slot *__restrict__ slots,
         if (anchor) {
             // direct pass at the iterate, accumulated in FP64 whatever the storage type
             double *const o1[1] = {outs[0]};
-            pass_rows_lpr<DT, double, 1, NT>(t.lpr, Q, n, ld, t.row0, t.nrows,
-                                             reinterpret_cast<const double *>(smem), nw, o1, t.uoff);
+            pass_rows_lpr<DT, double, 1, NT, PassShape<DT>::R, PassShape<DT>::UNR>(
+                t.lpr, Q, n, ld, t.row0, t.nrows, reinterpret_cast<const double *>(smem), nw, o1, t.uoff);
         } else {
             double *const (&co)[B] = outs;
             pass_rows_lpr<DT, AT, B, NT, PassShape<DT>::R, PassShape<DT>::UNR>(
@@ -307,25 +314,25 @@ size_t pass_lds_bytes(int B, int dtype, int max_nw)
 }
 
 template <int DT, int B>
-static void launch_pass_dt(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles, size_t lds,
-                           int grid, int nt)
+static void launch_pass_dt(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles,
+                           const int *starts, size_t lds, int grid, int nt)
 {
-    if (nt) k_pass<DT, B, true><<<grid, PASS_BS, lds, s>>>(slots, tiles, ntiles);
-    else k_pass<DT, B, false><<<grid, PASS_BS, lds, s>>>(slots, tiles, ntiles);
+    if (nt) k_pass<DT, B, true><<<grid, PASS_BS, lds, s>>>(slots, tiles, ntiles, starts);
+    else k_pass<DT, B, false><<<grid, PASS_BS, lds, s>>>(slots, tiles, ntiles, starts);
 }
 
 template <int B>
-static void launch_pass_b(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles, int dtype,
-                          int max_nw, int grid, int nt)
+static void launch_pass_b(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles,
+                          const int *starts, int dtype, int max_nw, int grid, int nt)
 {
     const size_t lds = pass_lds_bytes(B, dtype, max_nw);
     if (grid > ntiles) grid = ntiles;
     if (grid < 1) grid = 1;
     switch (dtype) {
-    case DT_F64: launch_pass_dt<DT_F64, B>(s, slots, tiles, ntiles, lds, grid, nt); break;
-    case DT_F32: launch_pass_dt<DT_F32, B>(s, slots, tiles, ntiles, lds, grid, nt); break;
-    case DT_BF16: launch_pass_dt<DT_BF16, B>(s, slots, tiles, ntiles, lds, grid, nt); break;
-    default: launch_pass_dt<DT_F16, B>(s, slots, tiles, ntiles, lds, grid, nt); break;
+    case DT_F64: launch_pass_dt<DT_F64, B>(s, slots, tiles, ntiles, starts, lds, grid, nt); break;
+    case DT_F32: launch_pass_dt<DT_F32, B>(s, slots, tiles, ntiles, starts, lds, grid, nt); break;
+    case DT_BF16: launch_pass_dt<DT_BF16, B>(s, slots, tiles, ntiles, starts, lds, grid, nt); break;
+    default: launch_pass_dt<DT_F16, B>(s, slots, tiles, ntiles, starts, lds, grid, nt); break;
     }
 }
 
@@ -362,14 +369,14 @@ int pass_blocks_per_cu(int B, int dtype, int max_nw)
     return o < 1 ? 1 : o;
 }
 
-hipError_t launch_pass_only(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles, int B,
-                            int dtype, int max_nw, int pass_grid, int nt)
+hipError_t launch_pass_only(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles,
+                            const int *starts, int B, int dtype, int max_nw, int pass_grid, int nt)
 {
     switch (B) {
-    case 1: launch_pass_b<1>(s, slots, tiles, ntiles, dtype, max_nw, pass_grid, nt); break;
-    case 2: launch_pass_b<2>(s, slots, tiles, ntiles, dtype, max_nw, pass_grid, nt); break;
-    case 3: launch_pass_b<3>(s, slots, tiles, ntiles, dtype, max_nw, pass_grid, nt); break;
-    default: launch_pass_b<4>(s, slots, tiles, ntiles, dtype, max_nw, pass_grid, nt); break;
+    case 1: launch_pass_b<1>(s, slots, tiles, ntiles, starts, dtype, max_nw, pass_grid, nt); break;
+    case 2: launch_pass_b<2>(s, slots, tiles, ntiles, starts, dtype, max_nw, pass_grid, nt); break;
+    case 3: launch_pass_b<3>(s, slots, tiles, ntiles, starts, dtype, max_nw, pass_grid, nt); break;
+    default: launch_pass_b<4>(s, slots, tiles, ntiles, starts, dtype, max_nw, pass_grid, nt); break;
     }
     return hipGetLastError();
 }

@@ -110,9 +110,18 @@ constexpr double CACHE_RESIDENT_BYTES = 256e6;   // Infinity Cache (MALL) of one
 void tile_shape(int64_t n, int dt, int64_t rows, int *lpr, int *rows_per_tile)
 {
     const int64_t vpr = (n + vec_width(dt) - 1) / vec_width(dt);   // 16-byte vectors per row
-    int l = 16;
-    if (vpr >= 8 * 64) l = 64;
-    else if (vpr >= 8 * 32) l = 32;
+    // lanes per row: the widest group in which each lane still streams `loads` vectors of a row
+    // (tuning overrides: QCQP_PASS_LOADS, QCQP_PASS_MIN_LPR)
+    int loads = 8, min_lpr = 8;
+    if (const char *ev = std::getenv("QCQP_PASS_LOADS")) loads = std::max(1, std::atoi(ev));
+    if (const char *ev = std::getenv("QCQP_PASS_MIN_LPR")) min_lpr = std::min(64, std::max(8, std::atoi(ev)));
+    while (min_lpr & (min_lpr - 1)) min_lpr &= min_lpr - 1;   // a power of two in [8, 64]
+    int l = min_lpr;
+    for (int c = 64; c > min_lpr; c /= 2)
+        if (vpr >= (int64_t)loads * c) {
+            l = c;
+            break;
+        }
     const int step = (PASS_BS / l) * pass_rows_per_step(dt);   // rows one block covers at once
     const int64_t row_bytes = n * elem_size(dt);
     int64_t r = std::max<int64_t>(1, (128 * 1024) / std::max<int64_t>(row_bytes, 1));
@@ -125,6 +134,27 @@ void tile_shape(int64_t n, int dt, int64_t rows, int *lpr, int *rows_per_tile)
 int pass_grid_for(int B, int dtype, int max_nw)
 {
     return std::max(1, num_cus) * pass_blocks_per_cu(B, dtype, max_nw);
+}
+
+// First tile of each of the `grid` pass blocks so that every block streams nearly the same
+// number of bytes: block b starts at the first tile whose preceding bytes reach b/grid of the
+// total.  Tiles of different requests carry different bytes (row lengths, storage), so equal
+// tile counts would leave blocks unequal.
+std::vector<int> balanced_starts(const std::vector<int64_t> &tile_bytes, int grid)
+{
+    const int nt = (int)tile_bytes.size();
+    std::vector<int> st(grid + 1, nt);
+    double total = 0.0;
+    for (int64_t b : tile_bytes) total += (double)b;
+    double acc = 0.0;
+    int t = 0;
+    for (int b = 0; b < grid; ++b) {
+        const double target = total * (double)b / (double)grid;
+        while (t < nt && acc + 0.5 * (double)tile_bytes[t] < target) acc += (double)tile_bytes[t++];
+        st[b] = t;
+    }
+    st[grid] = nt;
+    return st;
 }
 
 }  // namespace
@@ -149,6 +179,7 @@ struct qcqp_handle {
     Slot *dslot_eval = nullptr;   // device slot of point evaluations (never the running one)
     int *dlive0 = nullptr;        // device live list {0}: the single slot of a standalone run
     Tile *dtiles = nullptr;
+    int *dstarts = nullptr;   // balanced first tile per pass block (pass grid + 1 entries)
     std::vector<Tile> tiles;  // slot field 0
     int nblk_step = 1;
     int pass_grid = 1, nt = 0;
@@ -178,6 +209,9 @@ struct qcqp_batch {
     Slot *h_poll = nullptr;               // pinned copy of all slots
     Tile *dtiles = nullptr;
     size_t tiles_cap = 0;
+    int *dstarts = nullptr;               // balanced first tile per pass block
+    size_t starts_cap = 0;
+    std::vector<int> starts_host;         // kept alive until the copy above has run
     int *dlive = nullptr;                 // device list of live slot ids (max_slots entries)
     int nlive = 0;
     int ntiles = 0, max_nblk = 1, max_ny = 1, max_nw = 2, max_epi = 1;
@@ -552,17 +586,26 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
     tile_shape(n, h->dtype, nq * n, &lpr, &rpt);
     const int64_t rows = nq * n;
     (void)rows;
-    // tiles lie within one stored matrix; each carries the offset from its stored rows to the
-    // rows of U it produces (Q_i stored s-th writes U_i)
-    for (int64_t i = 0; i <= m; ++i) {
-        if (qmap[i] < 0) continue;
-        const int64_t sbase = (int64_t)qmap[i] * n;
-        for (int64_t r0 = 0; r0 < n; r0 += rpt)
-            h->tiles.push_back(Tile{0, (int32_t)(sbase + r0), (int32_t)std::min<int64_t>(rpt, n - r0), lpr,
-                                    (int32_t)((i - qmap[i]) * n)});
+    // Tiles cover runs of consecutive stored matrices whose rows of U are consecutive too (the
+    // whole stack for a plain QCQP); each carries the offset from its stored rows to the rows
+    // of U it produces (Q_i stored s-th writes U_i).
+    for (int64_t i = 0; i <= m;) {
+        if (qmap[i] < 0) {
+            ++i;
+            continue;
+        }
+        int64_t j = i;
+        while (j + 1 <= m && qmap[j + 1] == qmap[j] + 1) ++j;
+        const int64_t sbase = (int64_t)qmap[i] * n, run = (j - i + 1) * n;
+        const int32_t uoff = (int32_t)((i - qmap[i]) * n);
+        for (int64_t r0 = 0; r0 < run; r0 += rpt)
+            h->tiles.push_back(Tile{0, (int32_t)(sbase + r0), (int32_t)std::min<int64_t>(rpt, run - r0), lpr, uoff});
+        i = j + 1;
     }
     const size_t tile_off = total;
     total += round_up((int64_t)std::max<size_t>(h->tiles.size(), 1) * sizeof(Tile), 256);
+    const size_t starts_off = total;
+    total += round_up((int64_t)(h->tiles.size() + 2) * sizeof(int), 256);
     h->pass_grid = pass_grid_for(B, h->dtype, (int)h->nw);
     h->nt = (double)h->q_bytes > CACHE_RESIDENT_BYTES ? 1 : 0;
     if (const char *ev = std::getenv("QCQP_PASS_NT")) h->nt = std::atoi(ev) ? 1 : 0;   // tuning override
@@ -583,10 +626,21 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
     h->dslot_eval = reinterpret_cast<Slot *>(h->arena + slot_off + round_up(sizeof(Slot), 256));
     h->dlive0 = reinterpret_cast<int *>(h->arena + live_off);
     h->dtiles = reinterpret_cast<Tile *>(h->arena + tile_off);
+    h->dstarts = reinterpret_cast<int *>(h->arena + starts_off);
     hipError_t e = hipMemsetAsync(h->arena, 0, total, h->stream);
     if (e == hipSuccess && !h->tiles.empty())
         e = hipMemcpyAsync(h->dtiles, h->tiles.data(), h->tiles.size() * sizeof(Tile),
                            hipMemcpyHostToDevice, h->stream);
+    // the pass launch clips its grid to max(1, min(pass_grid, tiles)); the table matches it
+    std::vector<int> hstarts;
+    {
+        std::vector<int64_t> tb;
+        for (const Tile &t : h->tiles) tb.push_back((int64_t)t.nrows * n * es);
+        hstarts = balanced_starts(tb, std::max(1, std::min<int>(h->pass_grid, (int)h->tiles.size())));
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->dstarts, hstarts.data(), hstarts.size() * sizeof(int), hipMemcpyHostToDevice,
+                               h->stream);
+    }
     const hipMemcpyKind k = hipMemcpyHostToDevice;
     if (e == hipSuccess) e = hipMemcpyAsync(dq, hq.data(), U1 * 8, k, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(dc, hc.data(), (m + 1) * 8, k, h->stream);
@@ -792,7 +846,7 @@ qcqp_status qcqp_solve(qcqp_handle *h, const double *x0, const double *y0, doubl
     int64_t passes_before = 0;
     auto launch_chunk = [&](hipStream_t s, bool with_events) -> hipError_t {
         for (int64_t g = 0; g < poll; ++g) {
-            hipError_t e = launch_group(s, h->dslot, h->dlive0, 1, h->dtiles, ntiles, h->B, h->dtype,
+            hipError_t e = launch_group(s, h->dslot, h->dlive0, 1, h->dtiles, ntiles, h->dstarts, h->B, h->dtype,
                                         h->hslot.variant == VAR_XY ? HAS_XY : HAS_YX, h->nblk_step, (int)std::max<int64_t>(h->ny, 1), (int)h->nw,
                                         (int)(h->m + 1 + h->p), h->pass_grid, h->nt,
                                         with_events ? ev[2 * g] : nullptr,
@@ -897,7 +951,7 @@ static qcqp_status eval_loaded_point(qcqp_handle *h)
     S.Gc[0] = h->d_geval;
     HIPCHK(hipMemsetAsync(h->d_ueval, 0, (h->m + 1) * h->n * 8, h->stream));
     HIPCHK(hipMemcpyAsync(h->dslot_eval, &S, sizeof(Slot), hipMemcpyHostToDevice, h->stream));
-    HIPCHK(launch_pass_only(h->stream, h->dslot_eval, h->dtiles, (int)h->tiles.size(), h->B, h->dtype, (int)h->nw, h->pass_grid, h->nt));
+    HIPCHK(launch_pass_only(h->stream, h->dslot_eval, h->dtiles, (int)h->tiles.size(), h->dstarts, h->B, h->dtype, (int)h->nw, h->pass_grid, h->nt));
     HIPCHK(launch_epi_anchor(h->stream, h->dslot_eval, h->dlive0, 1, (int)(h->m + 1 + h->p)));
     return QCQP_OK;
 }
@@ -1041,10 +1095,10 @@ qcqp_status qcqp_time_pass(qcqp_handle *h, int64_t reps, double *avg_seconds)
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    HIPCHK(launch_pass_only(h->stream, h->dslot, h->dtiles, (int)h->tiles.size(), h->B, h->dtype, (int)h->nw, h->pass_grid, h->nt));
+    HIPCHK(launch_pass_only(h->stream, h->dslot, h->dtiles, (int)h->tiles.size(), h->dstarts, h->B, h->dtype, (int)h->nw, h->pass_grid, h->nt));
     HIPCHK(hipEventRecord(e0, h->stream));
     for (int64_t r = 0; r < reps; ++r)
-        HIPCHK(launch_pass_only(h->stream, h->dslot, h->dtiles, (int)h->tiles.size(), h->B, h->dtype, (int)h->nw, h->pass_grid, h->nt));
+        HIPCHK(launch_pass_only(h->stream, h->dslot, h->dtiles, (int)h->tiles.size(), h->dstarts, h->B, h->dtype, (int)h->nw, h->pass_grid, h->nt));
     HIPCHK(hipEventRecord(e1, h->stream));
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -1200,6 +1254,25 @@ static qcqp_status rebuild_tiles(qcqp_batch *bt)
     if (!mixed.empty())
         HIPCHK(hipMemcpyAsync(bt->dtiles, mixed.data(), mixed.size() * sizeof(Tile),
                               hipMemcpyHostToDevice, bt->stream));
+    // byte-balanced ranges of the persistent pass grid over the requests' tiles
+    bt->pass_grid = pass_grid_for(bt->opt.spec_trials, (int)bt->opt.storage, bt->max_nw);
+    {
+        std::vector<int64_t> tb;
+        tb.reserve(mixed.size());
+        const int es = elem_size((int)bt->opt.storage);
+        for (const Tile &t : mixed) tb.push_back((int64_t)t.nrows * bt->handles[t.slot]->n * es);
+        const int grid = std::max(1, std::min<int>(bt->pass_grid, (int)mixed.size()));
+        bt->starts_host = balanced_starts(tb, grid);
+        if (bt->starts_host.size() > bt->starts_cap) {
+            if (bt->dstarts) (void)hipFree(bt->dstarts);
+            bt->dstarts = nullptr;
+            const size_t cap = std::max<size_t>(bt->starts_host.size() * 2, 4096);
+            HIPCHK(hipMalloc(&bt->dstarts, cap * sizeof(int)));
+            bt->starts_cap = cap;
+        }
+        HIPCHK(hipMemcpyAsync(bt->dstarts, bt->starts_host.data(), bt->starts_host.size() * sizeof(int),
+                              hipMemcpyHostToDevice, bt->stream));
+    }
     if (!live.empty())
         HIPCHK(hipMemcpyAsync(bt->dlive, live.data(), live.size() * sizeof(int), hipMemcpyHostToDevice,
                               bt->stream));
@@ -1207,7 +1280,6 @@ static qcqp_status rebuild_tiles(qcqp_batch *bt)
     bt->ntiles = (int)mixed.size();
     if (bt->gexec) (void)hipGraphExecDestroy(bt->gexec);   // launch shapes changed
     bt->gexec = nullptr;
-    bt->pass_grid = pass_grid_for(bt->opt.spec_trials, (int)bt->opt.storage, bt->max_nw);
     bt->dirty = false;
     return QCQP_OK;
 }
@@ -1229,7 +1301,7 @@ qcqp_status qcqp_batch_step(qcqp_batch *bt, int64_t groups)
     if (bt->nlive > 0) {
         auto launch_chunk = [&](hipStream_t s, bool with_events) -> hipError_t {
             for (int64_t g = 0; g < groups; ++g) {
-                hipError_t e = launch_group(s, bt->dslots, bt->dlive, bt->nlive, bt->dtiles, bt->ntiles,
+                hipError_t e = launch_group(s, bt->dslots, bt->dlive, bt->nlive, bt->dtiles, bt->ntiles, bt->dstarts,
                                             bt->opt.spec_trials, (int)bt->opt.storage, bt->variants,
                                             bt->max_nblk,
                                             bt->max_ny, bt->max_nw, bt->max_epi, bt->pass_grid, bt->nt,
@@ -1362,6 +1434,7 @@ qcqp_status qcqp_batch_destroy(qcqp_batch *bt)
     if (bt->dslots) (void)hipFree(bt->dslots);
     if (bt->h_poll) (void)hipHostFree(bt->h_poll);
     if (bt->dtiles) (void)hipFree(bt->dtiles);
+    if (bt->dstarts) (void)hipFree(bt->dstarts);
     if (bt->dlive) (void)hipFree(bt->dlive);
     for (auto &e : bt->ev) (void)hipEventDestroy(e);
     if (bt->gexec) (void)hipGraphExecDestroy(bt->gexec);
