@@ -111,6 +111,31 @@ def cpu_baseline(inst_host, tau_bar, gamma0, trials_per_solve, budget_s=30.0):
                        f"solve, the GPU solve's count)")
 
 
+def stream_ceilings(Q):
+    """Context for the pass's roofline fraction: what plain library streams reach on the same
+    device -- a device-to-device copy of 2 GiB (read + write bytes) and torch's sum over the
+    resident FP64 stack (read only), best of 5 each, timed with events."""
+    import torch
+    out = {}
+    src = torch.empty(2 ** 30 // 4, dtype=torch.float64, device="cuda")   # 2 GiB
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    for name, fn, nbytes in (("d2d_copy_read_plus_write_GBs", lambda: dst.copy_(src), 2 * src.numel() * 8),
+                             ("torch_sum_read_GBs", lambda: Q.sum(), Q.numel() * Q.element_size())):
+        best = 1e9
+        for _ in range(6):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            best = min(best, a.elapsed_time(b) * 1e-3)
+        out[name] = nbytes / best / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def workload_config2(args):
     import torch
     import qcqp_inputs as qi
@@ -138,6 +163,7 @@ def workload_config2(args):
             f"pass {avg_pass * 1e6:.1f} us = {pb / avg_pass / 1e9:.0f} GB/s")
         s.close()
     r64 = res["float64"]
+    ceilings = stream_ceilings(inst.Q)
     Qhost = inst.Q.cpu().numpy()
     inst_h = qi.Instance(n, m, 0, Qhost, inst.q, inst.c, inst.lb, inst.ub)
     del inst
@@ -180,6 +206,7 @@ def workload_config2(args):
         "solve": {"iters": r64["infos"][0]["iters"], "trials": r64["infos"][0]["trials"],
                   "q_passes": r64["infos"][0]["q_passes"], "rel_kkt": r64["infos"][0]["rel_kkt"],
                   "rel_kkt_oracle_eval": kk["rel_kkt"], "f": kk["f"], "all_converged": r64["ok"]},
+        "stream_ceilings": ceilings,
         "fp32_storage": {"solves_per_s": args.steps / r32["wall"],
                          "q_pass_GBs": r32["pass_bytes"] / r32["avg_pass"] / 1e9,
                          "q_pass_frac": r32["pass_bytes"] / r32["avg_pass"] / 1e9 / HBM_PEAK_GBS,

@@ -269,9 +269,24 @@ __global__ void __launch_bounds__(STEP_BS) k_step(Slot *__restrict__ slots,
 #pragma unroll
     for (int b = 0; b < B; ++b) acc[b] = 0.0;
     if (j < n) {
-        // 4 matrices per step so 8 independent loads are in flight; the multiply-adds keep the
-        // ascending order of i
+        // 8 (then 4) matrices per step so 16 (8) independent loads are in flight; the
+        // multiply-adds keep the ascending order of i
         int i = 1 + wave;
+        for (; i + 7 * STEP_WAVES <= m; i += 8 * STEP_WAVES) {
+            double t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const size_t o = (size_t)(i + u * STEP_WAVES) * n + j;
+                t[u] = U[o] + q[o];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int ii = i + u * STEP_WAVES;
+#pragma unroll
+                for (int b = 0; b < B; ++b) acc[b] = fma(ynew[b * ny + p + ii - 1], t[u], acc[b]);
+                kk = fma(ycur[p + ii - 1], t[u], kk);
+            }
+        }
         for (; i + 3 * STEP_WAVES <= m; i += 4 * STEP_WAVES) {
             double t[4];
 #pragma unroll
@@ -384,6 +399,16 @@ __global__ void __launch_bounds__(STEP_BS) k_step_xy(Slot *__restrict__ slots,
     double kk = 0.0;
     if (j < n) {
         int i = 1 + wave;
+        for (; i + 7 * STEP_WAVES <= m; i += 8 * STEP_WAVES) {
+            double t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const size_t o = (size_t)(i + u * STEP_WAVES) * n + j;
+                t[u] = U[o] + q[o];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) kk = fma(ycur[p + i + u * STEP_WAVES - 1], t[u], kk);
+        }
         for (; i + 3 * STEP_WAVES <= m; i += 4 * STEP_WAVES) {
             double t[4];
 #pragma unroll
@@ -463,10 +488,33 @@ __global__ void __launch_bounds__(STEP_BS) k_epi(Slot *__restrict__ slots,
         const double *q = S->q + (size_t)row * n;
         const double ci = S->c[row];
         const size_t off = (size_t)row * n;
+        // The column loops below issue the loads of EU strided iterations before using them
+        // (each thread still sums its columns in ascending order), with the candidate
+        // pointers held in registers: loads no longer wait on stores through other pointers.
+        constexpr int EU = 4;
         if (anchor) {
             double *u = S->Uc[0] + off;
             double v[2] = {0.0, 0.0};
-            for (int j = tid; j < n; j += STEP_BS) {
+            int j = tid;
+            for (; j + (EU - 1) * STEP_BS < n; j += EU * STEP_BS) {
+                double xj[EU], uj[EU], qj[EU];
+#pragma unroll
+                for (int k = 0; k < EU; ++k) {
+                    xj[k] = x[j + k * STEP_BS];
+                    uj[k] = u[j + k * STEP_BS];
+                    qj[k] = q[j + k * STEP_BS];
+                }
+#pragma unroll
+                for (int k = 0; k < EU; ++k) {
+                    if (rho != 0.0) {
+                        uj[k] = fma(rho, xj[k], keep0 * uj[k]);
+                        u[j + k * STEP_BS] = uj[k];
+                    }
+                    v[0] = fma(xj[k], uj[k], v[0]);
+                    v[1] = fma(qj[k], xj[k], v[1]);
+                }
+            }
+            for (; j < n; j += STEP_BS) {
                 const double xj = x[j];
                 double uj = u[j];
                 if (rho != 0.0) {
@@ -480,24 +528,58 @@ __global__ void __launch_bounds__(STEP_BS) k_epi(Slot *__restrict__ slots,
             if (tid == 0) S->Gc[0][gi] = 0.5 * v[0] + v[1] + ci;
         } else if (inc) {
             const double *u = S->U + off;
+            const double *xcb[B];
+            double *wb[B], *ucb[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                xcb[b] = S->xc[b];
+                wb[b] = S->W[b] + off;
+                ucb[b] = S->Uc[b] + off;
+            }
             double v[3 * B];
 #pragma unroll
             for (int k = 0; k < 3 * B; ++k) v[k] = 0.0;
-            for (int j = tid; j < n; j += STEP_BS) {
-                const double xj = x[j], uj = u[j], qj = q[j];
+            auto col = [&](int jj, double xj, double uj, double qj, const double (&xn)[B], const double (&wl)[B]) {
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
-                    const double d = S->xc[b][j] - xj;
-                    double wv = S->W[b][off + j];
+                    const double d = xn[b] - xj;
+                    double wv = wl[b];
                     if (rho != 0.0) {
                         wv = fma(rho, d, keep0 * wv);
-                        S->W[b][off + j] = wv;
+                        wb[b][jj] = wv;
                     }
                     v[3 * b + 0] = fma(d, wv, v[3 * b + 0]);
                     v[3 * b + 1] = fma(d, uj, v[3 * b + 1]);
                     v[3 * b + 2] = fma(qj, d, v[3 * b + 2]);
-                    S->Uc[b][off + j] = uj + wv;
+                    ucb[b][jj] = uj + wv;
                 }
+            };
+            int j = tid;
+            for (; j + (EU - 1) * STEP_BS < n; j += EU * STEP_BS) {
+                double xj[EU], uj[EU], qj[EU], xn[EU][B], wl[EU][B];
+#pragma unroll
+                for (int k = 0; k < EU; ++k) {
+                    const int jj = j + k * STEP_BS;
+                    xj[k] = x[jj];
+                    uj[k] = u[jj];
+                    qj[k] = q[jj];
+#pragma unroll
+                    for (int b = 0; b < B; ++b) {
+                        xn[k][b] = xcb[b][jj];
+                        wl[k][b] = wb[b][jj];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < EU; ++k) col(j + k * STEP_BS, xj[k], uj[k], qj[k], xn[k], wl[k]);
+            }
+            for (; j < n; j += STEP_BS) {
+                double xn[B], wl[B];
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    xn[b] = xcb[b][j];
+                    wl[b] = wb[b][j];
+                }
+                col(j, x[j], u[j], q[j], xn, wl);
             }
             block_sum<3 * B>(v);
             if (tid == 0) {
@@ -512,23 +594,55 @@ __global__ void __launch_bounds__(STEP_BS) k_epi(Slot *__restrict__ slots,
             }
         } else {
             const double *u = S->U + off;
+            const double *xcb[B];
+            double *ucb[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                xcb[b] = S->xc[b];
+                ucb[b] = S->Uc[b] + off;
+            }
             double v[3 * B];
 #pragma unroll
             for (int k = 0; k < 3 * B; ++k) v[k] = 0.0;
-            for (int j = tid; j < n; j += STEP_BS) {
-                const double xj = x[j], uj = u[j], qj = q[j];
+            auto col = [&](int jj, double xj, double uj, double qj, const double (&xn)[B], const double (&ul)[B]) {
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
-                    const double xn = S->xc[b][j];
-                    double un = S->Uc[b][off + j];
+                    double un = ul[b];
                     if (rho != 0.0) {
-                        un = fma(rho, xn, keep0 * un);
-                        S->Uc[b][off + j] = un;
+                        un = fma(rho, xn[b], keep0 * un);
+                        ucb[b][jj] = un;
                     }
-                    v[3 * b + 0] = fma(xn - xj, un - uj, v[3 * b + 0]);
-                    v[3 * b + 1] = fma(xn, un, v[3 * b + 1]);
-                    v[3 * b + 2] = fma(qj, xn, v[3 * b + 2]);
+                    v[3 * b + 0] = fma(xn[b] - xj, un - uj, v[3 * b + 0]);
+                    v[3 * b + 1] = fma(xn[b], un, v[3 * b + 1]);
+                    v[3 * b + 2] = fma(qj, xn[b], v[3 * b + 2]);
                 }
+            };
+            int j = tid;
+            for (; j + (EU - 1) * STEP_BS < n; j += EU * STEP_BS) {
+                double xj[EU], uj[EU], qj[EU], xn[EU][B], ul[EU][B];
+#pragma unroll
+                for (int k = 0; k < EU; ++k) {
+                    const int jj = j + k * STEP_BS;
+                    xj[k] = x[jj];
+                    uj[k] = u[jj];
+                    qj[k] = q[jj];
+#pragma unroll
+                    for (int b = 0; b < B; ++b) {
+                        xn[k][b] = xcb[b][jj];
+                        ul[k][b] = ucb[b][jj];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < EU; ++k) col(j + k * STEP_BS, xj[k], uj[k], qj[k], xn[k], ul[k]);
+            }
+            for (; j < n; j += STEP_BS) {
+                double xn[B], ul[B];
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    xn[b] = xcb[b][j];
+                    ul[b] = ucb[b][j];
+                }
+                col(j, x[j], u[j], q[j], xn, ul);
             }
             block_sum<3 * B>(v);
             if (tid == 0) {
@@ -632,17 +746,48 @@ __global__ void __launch_bounds__(STEP_BS) k_post_xy(Slot *__restrict__ slots,
 #pragma unroll
     for (int b = 0; b < B; ++b) a[b] = c[b] = 0.0;
     if (j < n) {
-        for (int i = 1 + wave; i <= m; i += STEP_WAVES) {
-            const size_t o = (size_t)i * n + j;
-            const double u = U[o], qv = q[o];
+        const double *ucb[B], *wb[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            ucb[b] = S->Uc[b];
+            wb[b] = inc ? S->W[b] : S->Uc[b];
+        }
+        auto mat = [&](int i, double u, double qv, const double (&un)[B], const double (&wv)[B]) {
             const double lam = ycur[p + i - 1];
 #pragma unroll
             for (int b = 0; b < B; ++b) {
-                const double un = S->Uc[b][o];
-                const double du = inc ? S->W[b][o] : un - u;
-                a[b] = fma(ynew[b * ny + p + i - 1] - lam, un + qv, a[b]);
+                const double du = inc ? wv[b] : un[b] - u;
+                a[b] = fma(ynew[b * ny + p + i - 1] - lam, un[b] + qv, a[b]);
                 c[b] = fma(lam, du, c[b]);
             }
+        };
+        int i = 1 + wave;
+        // 4 matrices per step, loads first; the sums keep the ascending order of i
+        for (; i + 3 * STEP_WAVES <= m; i += 4 * STEP_WAVES) {
+            double u[4], qv[4], un[4][B], wv[4][B];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const size_t o = (size_t)(i + k * STEP_WAVES) * n + j;
+                u[k] = U[o];
+                qv[k] = q[o];
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    un[k][b] = ucb[b][o];
+                    wv[k][b] = wb[b][o];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) mat(i + k * STEP_WAVES, u[k], qv[k], un[k], wv[k]);
+        }
+        for (; i <= m; i += STEP_WAVES) {
+            const size_t o = (size_t)i * n + j;
+            double un[B], wv[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                un[b] = ucb[b][o];
+                wv[b] = wb[b][o];
+            }
+            mat(i, U[o], q[o], un, wv);
         }
     }
     if (wave > 0) {
