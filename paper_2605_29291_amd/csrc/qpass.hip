@@ -187,9 +187,8 @@ __device__ __forceinline__ void pass_rows_lpr(int lpr, const void *Q, int n, siz
 }
 
 // The pass kernel runs a persistent grid: block b streams the contiguous tile range
-// [b T / G, (b+1) T / G), so every block gets the same number of equal-byte tiles and the
-// grid finishes together; w is staged into LDS only when the tile's slot changes (tiles are
-// grouped by slot).
+// [starts[b], starts[b+1]), ranges of nearly equal bytes; w is staged into LDS only when the
+// tile's slot changes (tiles are grouped by slot).
 template <int DT, int B, bool NT>
 __global__ void __launch_bounds__(PASS_BS) k_pass(Slot *__restrict__ slots,
                                                   const Tile *__restrict__ tiles, int ntiles,
@@ -228,21 +227,50 @@ __global__ void __launch_bounds__(PASS_BS) k_pass(Slot *__restrict__ slots,
                 ld = (size_t)S->ld;
                 Q = S->Q;
                 const double *x = S->x;
+                // staging loads are batched (SU per thread and vector in flight): every block
+                // stages at once when the grid starts, and for large n the one-load-per-round-trip
+                // loop held the stream back by up to 14 us
+                constexpr int SU = 4;
                 if (anchor) {
                     double *w = reinterpret_cast<double *>(smem);
-                    for (int j = threadIdx.x; j < nw; j += PASS_BS) w[j] = j < n ? x[j] : 0.0;
+                    for (int j0 = threadIdx.x; j0 < nw; j0 += SU * PASS_BS) {
+                        double xv[SU];
+#pragma unroll
+                        for (int u = 0; u < SU; ++u) {
+                            const int j = j0 + u * PASS_BS;
+                            xv[u] = j < n ? x[j] : 0.0;
+                        }
+#pragma unroll
+                        for (int u = 0; u < SU; ++u)
+                            if (j0 + u * PASS_BS < nw) w[j0 + u * PASS_BS] = xv[u];
+                    }
                     outs[0] = S->Uc[0];
                 } else {
                     AT *w = reinterpret_cast<AT *>(smem);
+                    const double *xcs[B];
 #pragma unroll
                     for (int b = 0; b < B; ++b) {
-                        const double *xc = S->xc[b];
-                        for (int j = threadIdx.x; j < nw; j += PASS_BS) {
-                            double v = 0.0;
-                            if (j < n) v = inc ? xc[j] - x[j] : xc[j];
-                            w[b * nw + j] = (AT)v;
-                        }
+                        xcs[b] = S->xc[b];
                         outs[b] = inc ? S->W[b] : S->Uc[b];
+                    }
+                    for (int j0 = threadIdx.x; j0 < nw; j0 += SU * PASS_BS) {
+                        double xv[SU], cv[B][SU];
+#pragma unroll
+                        for (int u = 0; u < SU; ++u) {
+                            const int j = j0 + u * PASS_BS;
+                            xv[u] = (inc && j < n) ? x[j] : 0.0;
+#pragma unroll
+                            for (int b = 0; b < B; ++b) cv[b][u] = j < n ? xcs[b][j] : 0.0;
+                        }
+#pragma unroll
+                        for (int u = 0; u < SU; ++u) {
+                            const int j = j0 + u * PASS_BS;
+                            if (j < nw) {
+#pragma unroll
+                                for (int b = 0; b < B; ++b)
+                                    w[b * nw + j] = (AT)(inc ? cv[b][u] - xv[u] : cv[b][u]);
+                            }
+                        }
                     }
                 }
             }
