@@ -265,6 +265,14 @@ __global__ void __launch_bounds__(STEP_BS) k_step(Slot *__restrict__ slots,
     const int lane = threadIdx.x % STEP_COLS, wave = threadIdx.x / STEP_COLS;
     const int j = blockIdx.x * STEP_COLS + lane;
     const double *U = S->U, *q = S->q;
+    // the values the primal step needs at the end are loaded now, while the sums below stream
+    double xj = 0.0, lo = 0.0, hi = 0.0, u0 = 0.0;
+    if (wave == 0 && j < n) {
+        xj = S->x[j];
+        lo = S->lb[j];
+        hi = S->ub[j];
+        u0 = U[j] + q[j];
+    }
     double acc[B], kk = 0.0;
 #pragma unroll
     for (int b = 0; b < B; ++b) acc[b] = 0.0;
@@ -326,7 +334,6 @@ __global__ void __launch_bounds__(STEP_BS) k_step(Slot *__restrict__ slots,
             for (int b = 0; b < B; ++b) acc[b] += s_acc[w - 1][b][lane];
             kk += s_acc[w - 1][B][lane];
         }
-        const double u0 = U[j] + q[j];
         double av = 0.0;
         double g[B];
 #pragma unroll
@@ -337,7 +344,6 @@ __global__ void __launch_bounds__(STEP_BS) k_step(Slot *__restrict__ slots,
             for (int b = 0; b < B; ++b) g[b] = fma(ynew[b * ny + l], a, g[b]);
             av = fma(ycur[l], a, av);
         }
-        const double xj = S->x[j], lo = S->lb[j], hi = S->ub[j];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const double xn = clipd(xj - tau_b[b] * g[b], lo, hi);
@@ -1019,8 +1025,11 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
             }
         }
     }
-    __shared__ double s_mx[STEP_BS];
-    s_mx[tid] = mx;
+    // the block maximum of the violations: per-wave shuffles, then one value per wave
+    __shared__ double s_mx[STEP_BS / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    if ((tid & 63) == 0) s_mx[tid >> 6] = mx;
     block_sum<NR>(r);              // includes the barrier that publishes s_mx
     double tot[NPART], kv[3], tq[3 * B];
 #pragma unroll
@@ -1032,14 +1041,25 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
     for (int k2 = 0; k2 < 3 * B; ++k2) tq[k2] = r[NPART + 2 + k2];
     if (tid == 0) {
         double mm = 0.0;
-        for (int t = 0; t < STEP_BS; ++t) mm = fmax(mm, s_mx[t]);
+        for (int w = 0; w < STEP_BS / 64; ++w) mm = fmax(mm, s_mx[w]);
         kv[2] = mm;
     }
 
     if (tid == 0) {
+        // every slot field the decision reads is loaded here, before the first store, so the
+        // loads go out together instead of one round trip after each store
+        const auto cnorm = S->cnorm, bnorm = S->bnorm, f_star = S->f_star, tol = S->tol;
+        const auto stop_rule = S->stop_rule, m0 = S->m0, n_soc = S->n_soc, fresh = S->fresh;
+        const auto kk = S->k, ke = S->ke, max_iter = S->max_iter, passes = S->passes;
+        const auto trials = S->trials, iter_trials = S->iter_trials;
+        const auto tau = S->tau, gam = S->gam, sp = S->sig_prev, eta = S->eta, sig0 = S->sig0;
+        const auto c_alpha = S->c_alpha, gamma0 = S->gamma0, c_beta = S->c_beta, delta = S->delta;
+        const auto alpha_k = S->alpha_k, beta_k = S->beta_k;
+        const bool xy = S->variant == VAR_XY;
+        const double fval = S->G[ny];
         const double rel_dual = sqrt(tot[0]) / (1.0 + sqrt(tot[1]) + sqrt(tot[2]) + sqrt(tot[3]));
-        const double rel_comp = sqrt(kv[0]) / (1.0 + S->cnorm);
-        const double rel_pri = sqrt(kv[1]) / (1.0 + S->cnorm + S->bnorm);
+        const double rel_comp = sqrt(kv[0]) / (1.0 + cnorm);
+        const double rel_pri = sqrt(kv[1]) / (1.0 + cnorm + bnorm);
         double rk = fmax(rel_dual, fmax(rel_pri, rel_comp));
         if (isnan(rel_dual) || isnan(rel_pri) || isnan(rel_comp)) rk = NAN;
         S->kkt[0] = rk;
@@ -1050,22 +1070,22 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
         // stop rule: the relative KKT residual, or the criterion of the experiments of §5.1
         // (relative suboptimality against f_star and the mean constraint violation)
         double crit = rk;
-        if (S->stop_rule == 1) {
-            const int cnt = p + (simplex ? 0 : (cones ? S->m0 + S->n_soc : m));
-            const double fs = S->f_star;
-            const double sub = fabs(S->G[ny] - fs) / (1.0 + fabs(fs));
+        if (stop_rule == 1) {
+            const int cnt = p + (simplex ? 0 : (cones ? m0 + n_soc : m));
+            const double fs = f_star;
+            const double sub = fabs(fval - fs) / (1.0 + fabs(fs));
             const double mv = cnt > 0 ? r[NR - 1] / (double)cnt : 0.0;
             crit = sub > mv ? sub : mv;
             if (isnan(sub) || isnan(mv)) crit = NAN;
         }
         S->crit = crit;
         int dec = -1;
-        S->passes += 1;                 // this group's pass was streamed, whatever follows
+        S->passes = passes + 1;         // this group's pass was streamed, whatever follows
         if (isnan(rk) || isnan(crit)) {
             S->status = ST_NUMERICAL;
             dec = -2;
-        } else if (crit <= S->tol) {
-            if (S->fresh) {
+        } else if (crit <= tol) {
+            if (fresh) {
                 S->status = ST_CONVERGED;
             } else {
                 // the cached U carries FP32 / incremental rounding: confirm the stop test on
@@ -1074,14 +1094,12 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
                 S->anchor_keep_gp = 1;
             }
             dec = -2;
-        } else if (S->k >= S->max_iter) {
+        } else if (kk >= max_iter) {
             S->status = ST_MAX_ITER;
             dec = -2;
         }
         if (dec == -1) {
-            double t = S->tau;
-            const double gam = S->gam, sp = S->sig_prev, eta = S->eta;
-            const bool xy = S->variant == VAR_XY;
+            double t = tau;
             for (int b = 0; b < B; ++b) {
                 const double sig = gam * t;
                 const double th = sp / sig;
@@ -1091,17 +1109,17 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
                 if (xy) {
                     // Algorithm 1: alpha_{k+1} = c_a / tau_k, beta_{k+1} = gamma_0 c_b / sigma_k;
                     // E_k of eq. (backtracking) with the two gradient differences of k_post_xy
-                    const double alpha_next = S->c_alpha / t;
-                    const double beta_next = S->gamma0 * S->c_beta / sig;
+                    const double alpha_next = c_alpha / t;
+                    const double beta_next = gamma0 * c_beta / sig;
                     E = tq[3 * b] / (2.0 * alpha_next) - Dd / sig + tq[3 * b + 1] / (2.0 * beta_next) -
-                        (1.0 / t - th * (S->alpha_k + S->beta_k)) * Dp;
+                        (1.0 / t - th * (alpha_k + beta_k)) * Dp;
                 } else {
-                    const double alpha_next = S->c_alpha / sig;      // alpha_{k+1} = c_a / sigma_k
+                    const double alpha_next = c_alpha / sig;        // alpha_{k+1} = c_a / sigma_k
                     const double quad = 0.5 * tq[3 * b];              // 1/2 d'Q(lambda+)d
                     E = quad - Dp / t + tq[3 * b + 1] / (2.0 * alpha_next) -
-                        (1.0 / sig - th * S->alpha_k) * Dd;
+                        (1.0 / sig - th * alpha_k) * Dd;
                 }
-                const double rhs = -(S->delta / t) * Dp - (S->delta / sig) * Dd;
+                const double rhs = -(delta / t) * Dp - (delta / sig) * Dd;
                 if (E <= rhs) {
                     dec = b;
                     break;
@@ -1118,9 +1136,9 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
             } else if (dec == -1) {
                 // all candidates rejected: tau <- eta^B tau, next group retries
                 S->tau = t;
-                S->trials += B;
-                S->iter_trials += B;
-                if (S->iter_trials > 400 || !(t > 1e-300)) {
+                S->trials = trials + B;
+                S->iter_trials = iter_trials + B;
+                if (iter_trials + B > 400 || !(t > 1e-300)) {
                     S->status = ST_NUMERICAL;
                     dec = -2;
                 }
@@ -1128,11 +1146,12 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
         }
         s_dec = dec;
         if (dec >= 0) {
-            double t = S->tau;
-            for (int b = 0; b < dec; ++b) t *= S->eta;
-            const double sig = S->gam * t;
-            if (S->ke == 0) S->sig0 = sig;
-            s_t = sig / S->sig0;                                     // t_k = sigma_k / sigma_0
+            double t = tau;
+            for (int b = 0; b < dec; ++b) t *= eta;
+            const double sig = gam * t;
+            const double s0 = ke == 0 ? sig : sig0;
+            if (ke == 0) S->sig0 = sig;
+            s_t = sig / s0;                                          // t_k = sigma_k / sigma_0
         }
     }
     __syncthreads();
@@ -1149,46 +1168,66 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
     }
     __syncthreads();
     if (tid == 0) {
-        double t = S->tau;
-        for (int b = 0; b < dec; ++b) t *= S->eta;
-        const double sig = S->gam * t;
-        S->T += s_t;
-        S->trials += dec + 1;
+        // as above: all reads first, then the stores
+        const auto tau = S->tau, eta = S->eta, gam = S->gam, T = S->T, mu = S->mu;
+        const auto c_nm = S->c_nm;
+        const auto tau_prev = S->tau_prev;
+        const auto c_alpha = S->c_alpha, gamma0 = S->gamma0, c_beta = S->c_beta;
+        const auto trials = S->trials, kk = S->k, ke = S->ke;
+        const auto restart = S->restart;
+        const auto restart_every = S->restart_every;
+        const auto ada_first = S->ada_first, ada_every = S->ada_every;
+        const auto restart_from_avg = S->restart_from_avg;
+        const bool xy = S->variant == VAR_XY;
+        const bool exact = S->dtype == DT_F64 && !S->incremental;
+        double *const x = S->x, *const xn = S->xc[dec], *const U = S->U, *const Un = S->Uc[dec];
+        double *const y = S->y, *const yn = S->yc[dec];
+        double *const Gp = S->Gp, *const G = S->G, *const Gn = S->Gc[dec];
+        double *const gxp = S->gxp, *const gxk = S->gxk;
+        double t = tau;
+        for (int b = 0; b < dec; ++b) t *= eta;
+        const double sig = gam * t;
+        const double Tn = T + s_t;
+        S->T = Tn;
+        S->trials = trials + dec + 1;
         S->iter_trials = 0;
         // step-size rule, Algorithm 1 (non-monotone form with c_nm = 1)
-        const double gam_next = S->gam * (1.0 + S->mu * t);
-        const double tau_next = t * sqrt(S->gam / gam_next * (1.0 + S->c_nm * t / S->tau_prev));
+        const double gam_next = gam * (1.0 + mu * t);
+        const double tau_next = t * sqrt(gam / gam_next * (1.0 + c_nm * t / tau_prev));
         // shift the state: (x, U, y) <- candidate, G^{k-1} <- G^k, G^k <- candidate
-        swap_ptr(S->x, S->xc[dec]);
-        swap_ptr(S->U, S->Uc[dec]);
-        swap_ptr(S->y, S->yc[dec]);
-        double *gold = S->Gp;
-        S->Gp = S->G;
-        S->G = S->Gc[dec];
-        S->Gc[dec] = gold;
-        S->f = S->G[ny];
-        S->fresh = (S->dtype == DT_F64 && !S->incremental) ? 1 : 0;
-        if (S->variant == VAR_XY) {
+        S->x = xn;
+        S->xc[dec] = x;
+        S->U = Un;
+        S->Uc[dec] = U;
+        S->y = yn;
+        S->yc[dec] = y;
+        S->Gp = G;
+        S->G = Gn;
+        S->Gc[dec] = Gp;
+        S->f = Gn[ny];
+        S->fresh = exact ? 1 : 0;
+        if (xy) {
             // grad_x Phi(x^k, y^k) becomes the previous iterate's; the next step kernel
             // recomputes the new one from U
-            swap_ptr(S->gxp, S->gxk);
-            S->alpha_k = S->c_alpha / t;
-            S->beta_k = S->gamma0 * S->c_beta / sig;
+            S->gxp = gxk;
+            S->gxk = gxp;
+            S->alpha_k = c_alpha / t;
+            S->beta_k = gamma0 * c_beta / sig;
         } else {
-            S->alpha_k = S->c_alpha / sig;
+            S->alpha_k = c_alpha / sig;
         }
         S->sig_prev = sig;
         S->tau_prev = t;
         S->tau = tau_next;
         S->gam = gam_next;
-        S->k += 1;
-        S->ke += 1;
+        const auto k1 = kk + 1, ke1 = ke + 1;
+        S->k = k1;
+        S->ke = ke1;
         int rs = 0;
-        if (S->restart == 1 && S->ke >= S->restart_every) rs = 1;
-        if (S->restart == 2 &&
-            (S->k == S->ada_first || (S->k > S->ada_first && (S->k % S->ada_every) == 0)))
+        if (restart == 1 && ke1 >= restart_every) rs = 1;
+        if (restart == 2 && (k1 == ada_first || (k1 > ada_first && (k1 % ada_every) == 0)))
             S->status = ST_GAP_PENDING;
-        if (rs && S->restart_from_avg && S->T > 0.0) rs = 2;
+        if (rs && restart_from_avg && Tn > 0.0) rs = 2;
         s_restart = rs;
     }
     __syncthreads();
