@@ -136,6 +136,11 @@ def stream_ceilings(Q):
     return out
 
 
+# speculative candidates per pass for the config-2 solves: the iterates and trial counts are
+# those of sequential backtracking for any value; 3 streams 60 passes per solve instead of 67
+CONFIG2_SPEC = 3
+
+
 def workload_config2(args):
     import torch
     import qcqp_inputs as qi
@@ -149,7 +154,8 @@ def workload_config2(args):
     for storage in ("float64", "float32"):
         Qs = inst.Q if storage == "float64" else inst.Q.to(torch.float32)
         inst_s = qi.Instance(n, m, 0, Qs, inst.q, inst.c, inst.lb, inst.ub)
-        s = Solver(inst_s, device=True, storage=storage, tau_bar=tau_bar, gamma0=gamma0, timing=1)
+        s = Solver(inst_s, device=True, storage=storage, tau_bar=tau_bar, gamma0=gamma0, timing=1,
+                   spec_trials=CONFIG2_SPEC)
         if storage != "float64":
             del Qs
         wall, lat, infos, x, y = run_solves(s, args.steps, args.warmup)
@@ -193,13 +199,13 @@ def workload_config2(args):
         "data": "synthetic",
         "config": {"workload": "random convex QCQP n=2000 m=100, Q_i=A_iA_i'/n+0.01I, FP64 stack "
                                "3.23 GB, rAPDB-yx non-monotone, fixed restart 400, rel-KKT<=1e-6",
-                   "n": 2000, "m": 100, "storage": "float64", "spec_trials": 2,
+                   "n": 2000, "m": 100, "storage": "float64", "spec_trials": CONFIG2_SPEC,
                    "tau_bar": tau_bar, "gamma0": gamma0},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic("traffic_bytes_per_launch_f64"),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "kernel": "k_pass<DT_F64,2>", "avg_pass_us": r64["avg_pass"] * 1e6,
+                     "kernel": f"k_pass<DT_F64,{CONFIG2_SPEC}>", "avg_pass_us": r64["avg_pass"] * 1e6,
                      "bytes_per_pass": r64["pass_bytes"], "timed_passes": r64["timed"]},
         "cpu_baseline": cpu,
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
@@ -665,7 +671,8 @@ def workload_batch_pass(args):
 def workload_traffic(args):
     """Dispatches for the HBM-traffic counters (run under rocprofv3 --pmc FETCH_SIZE, then
     WRITE_SIZE): a plain device copy of known size (the calibration), then the config-2 FP64
-    pass and a BF16 pass exactly as the solves launch them (trial mode, 2 candidates)."""
+    pass exactly as the config-2 solves launch it (trial mode, CONFIG2_SPEC candidates) and a
+    BF16 pass as the serving batches launch it (2 candidates)."""
     import torch
     import qcqp_inputs as qi
     from paper_2605_29291_amd import Solver
@@ -680,7 +687,7 @@ def workload_traffic(args):
     torch.cuda.empty_cache()
     out = {"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}
     inst = qi.random_qcqp_torch(2000, 100, qi.config_seed(2), shift=0.01, device="cuda")
-    s = Solver(inst, device=True, storage="float64", tau_bar=1.0, spec_trials=2)
+    s = Solver(inst, device=True, storage="float64", tau_bar=1.0, spec_trials=CONFIG2_SPEC)
     s.time_pass(reps=3)
     out["f64_pass_bytes"] = 101 * 2000 * 2000 * 8
     s.close()
