@@ -247,8 +247,8 @@ def serve_batched(trace, storage, args, budget, timing=1):
     events around every pass (eager launches); timing=0 replays captured graphs."""
     import torch
     from paper_2605_29291_amd import Batch, Solver
-    b = Batch(max_slots=args.max_slots, hbm_budget_bytes=budget, storage=storage, spec_trials=2,
-              timing=timing)
+    b = Batch(max_slots=args.max_slots, hbm_budget_bytes=budget, storage=storage,
+              spec_trials=args.spec, timing=timing)
     reqs = [dict(r) for r in trace]
     idx, done, gen = 0, 0, 0.0
     slot_req = {}
@@ -265,7 +265,8 @@ def serve_batched(trace, storage, args, budget, timing=1):
             if held is None:
                 tg = time.perf_counter()
                 inst = _gen_request(r, storage)
-                held = Solver(inst, device=True, storage=storage, tau_bar=0.0, gamma0=0.1, spec_trials=2)
+                held = Solver(inst, device=True, storage=storage, tau_bar=0.0, gamma0=0.1,
+                              spec_trials=args.spec)
                 del inst
                 torch.cuda.synchronize()
                 gen += time.perf_counter() - tg
@@ -318,7 +319,8 @@ def serve_fifo(trace, storage, args):
             time.sleep(r["arrival"] - now)
         tg = time.perf_counter()
         inst = _gen_request(r, storage)
-        s = Solver(inst, device=True, storage=storage, tau_bar=0.0, gamma0=0.1, spec_trials=2, timing=1)
+        s = Solver(inst, device=True, storage=storage, tau_bar=0.0, gamma0=0.1,
+                   spec_trials=args.spec, timing=1)
         del inst
         torch.cuda.synchronize()
         gen += time.perf_counter() - tg
@@ -383,10 +385,10 @@ def workload_serving(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16-storage/f32-acc/f64-checks", "data": "synthetic",
         "config": {"workload": f"serving: {len(trace)} random QCQP requests n~U[200,3000], m~U[5,200], BF16 "
                                "stack, continuous batching admitted by free HBM", "max_slots": args.max_slots,
-                   "groups_per_step": args.groups, "budget_bytes": budget},
+                   "groups_per_step": args.groups, "budget_bytes": budget, "spec_trials": args.spec},
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS if gbs else None, "traffic": None,
-                     "kernel": "k_pass<DT_BF16,2> over all resident requests"},
+                     "kernel": f"k_pass<DT_BF16,{args.spec}> over all resident requests"},
         "cpu_baseline": cpu,
         "latency_ms": {"p50": closed["p50_ms"], "p99": closed["p99_ms"]},
         "closed_loop": closed, "closed_loop_with_pass_events": timed,
@@ -631,11 +633,13 @@ def workload_batch_pass(args):
     trace = qi.serving_trace(512, qi.config_seed(5))
     out = {}
     for k in (1, 8, 32, 128, 512):
-        b = Batch(max_slots=k, hbm_budget_bytes=int(64e9), storage=storage, spec_trials=2, timing=1)
+        b = Batch(max_slots=k, hbm_budget_bytes=int(64e9), storage=storage, spec_trials=args.spec,
+                  timing=1)
         admitted, held = 0, []
         for r in trace[:k]:
             inst = _gen_request(r, storage)
-            s = Solver(inst, device=True, storage=storage, tau_bar=0.0, gamma0=0.1, spec_trials=2)
+            s = Solver(inst, device=True, storage=storage, tau_bar=0.0, gamma0=0.1,
+                       spec_trials=args.spec)
             del inst
             if b.admit(s) is None:
                 s.close()
@@ -662,9 +666,10 @@ def workload_batch_pass(args):
     return {"metric": METRIC, "value": last["pass_GBs"], "unit": "GB/s", "n_gpus": 1, "steps": 8,
             "warmup": 2, "ms_per_step": last["us_per_group_pass"] / 1e3, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "bf16-storage", "data": "synthetic",
-            "config": {"workload": "continuous batch of serving-trace requests, BF16, steady-state pass"},
+            "config": {"workload": "continuous batch of serving-trace requests, BF16, steady-state pass",
+                       "spec_trials": args.spec},
             "roofline": {"bound": "hbm", "achieved": last["pass_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": last["frac"], "traffic": None, "kernel": "k_pass<DT_BF16,2>"},
+                         "frac": last["frac"], "traffic": None, "kernel": f"k_pass<DT_BF16,{args.spec}>"},
             "cpu_baseline": None, "per_batch": out}
 
 
@@ -764,6 +769,8 @@ def main():
     ap.add_argument("--groups", type=int, default=4, help="serving: trial groups per batch step")
     ap.add_argument("--check", type=int, default=8, help="serving: requests checked by the oracle")
     ap.add_argument("--no-fifo", action="store_true", help="serving: skip the FP64 FIFO comparison")
+    ap.add_argument("--spec", type=int, default=2,
+                    help="serving, batch_pass: speculative candidates per pass")
     ap.add_argument("--kml-iters", type=int, default=20000, help="kml: iteration cap")
     ap.add_argument("--gamma0", type=float, default=0.1, help="paper_random: gamma_0")
     ap.add_argument("--rows", default="", help="paper_random: comma-separated method rows (default all)")
