@@ -119,7 +119,7 @@ hipError_t launch_group(hipStream_t s, Slot *slots, const int *live, int nslots,
                         int nt, hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_pass_only(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles,
                             const int *starts, int B, int dtype, int max_nw, int pass_grid, int nt);
-// persistent pass grid: resident blocks per CU of k_pass for this configuration
+// pass grid: resident blocks per CU of k_pass for this configuration
 int pass_blocks_per_cu(int B, int dtype, int max_nw);
 size_t pass_lds_bytes(int B, int dtype, int max_nw);
 // rows one lane group of the trial pass streams at a time for this storage type

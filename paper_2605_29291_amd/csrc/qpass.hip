@@ -186,8 +186,8 @@ __device__ __forceinline__ void pass_rows_lpr(int lpr, const void *Q, int n, siz
     else pass_rows<DT, AT, B, 8, NT, R, UNR>(Q, n, ld, row0, nrows, w, nw, outs, uoff);
 }
 
-// The pass kernel runs a persistent grid: block b streams the contiguous tile range
-// [starts[b], starts[b+1]), ranges of nearly equal bytes; w is staged into LDS only when the
+// Block b of the pass grid streams the contiguous tile range [starts[b], starts[b+1]), ranges
+// of nearly equal bytes; w is staged into LDS when the block starts and again only when the
 // tile's slot changes (tiles are grouped by slot).
 template <int DT, int B, bool NT>
 __global__ void __launch_bounds__(PASS_BS) k_pass(Slot *__restrict__ slots,

@@ -106,7 +106,7 @@ constexpr double CACHE_RESIDENT_BYTES = 256e6;   // Infinity Cache (MALL) of one
 // A lane should issue at least one full batch of 8 loads per row, so short rows share a wave
 // (32 or 16 lanes per row).  Tiles hold ~128 KB of the stack, rounded to whole block steps
 // (every lane group streams its R rows), and there are at least ~1024 of them when the stack
-// allows it, so that the persistent grid splits into nearly equal contiguous ranges.
+// allows it, so that the pass grid splits into nearly equal contiguous ranges.
 void tile_shape(int64_t n, int dt, int64_t rows, int *lpr, int *rows_per_tile)
 {
     const int64_t vpr = (n + vec_width(dt) - 1) / vec_width(dt);   // 16-byte vectors per row
@@ -131,9 +131,24 @@ void tile_shape(int64_t n, int dt, int64_t rows, int *lpr, int *rows_per_tile)
     *rows_per_tile = (int)r;
 }
 
-int pass_grid_for(int B, int dtype, int max_nw)
+// Pass grid.  One round is the resident block count (CUs x pass blocks per CU).  With one
+// byte-balanced range per resident block, blocks on slower CUs finished up to twice as late as
+// the fastest (config 2: 250 to 500 us), so when at least two blocks fit on a CU the grid takes
+// up to four rounds and the hardware hands the later ranges to whichever CUs free up first.
+// Every block stages w ((B + 1) n FP64 values from L2) when it starts: a round is added only
+// while each block still streams at least ten times those bytes.  With one block per CU a new
+// block's staging would leave its CU idle, so the grid stays at one round.
+constexpr int PASS_GRID_ROUNDS = 4;
+
+int pass_grid_for(int B, int dtype, int max_nw, double stack_bytes)
 {
-    return std::max(1, num_cus) * pass_blocks_per_cu(B, dtype, max_nw);
+    const int occ = pass_blocks_per_cu(B, dtype, max_nw);
+    const int base = std::max(1, num_cus) * occ;
+    if (occ < 2) return base;
+    const double stage = (double)(B + 1) * max_nw * 8.0;
+    for (int k = PASS_GRID_ROUNDS; k > 1; k /= 2)
+        if (stack_bytes / ((double)base * k) >= 10.0 * stage) return base * k;
+    return base;
 }
 
 // First tile of each of the `grid` pass blocks so that every block streams nearly the same
@@ -606,7 +621,7 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
     total += round_up((int64_t)std::max<size_t>(h->tiles.size(), 1) * sizeof(Tile), 256);
     const size_t starts_off = total;
     total += round_up((int64_t)(h->tiles.size() + 2) * sizeof(int), 256);
-    h->pass_grid = pass_grid_for(B, h->dtype, (int)h->nw);
+    h->pass_grid = pass_grid_for(B, h->dtype, (int)h->nw, (double)h->q_bytes);
     h->nt = (double)h->q_bytes > CACHE_RESIDENT_BYTES ? 1 : 0;
     if (const char *ev = std::getenv("QCQP_PASS_NT")) h->nt = std::atoi(ev) ? 1 : 0;   // tuning override
     if (hipMalloc(&h->arena, total) != hipSuccess) {
@@ -1236,7 +1251,7 @@ static qcqp_status rebuild_tiles(qcqp_batch *bt)
         bt->max_epi = std::max<int>(bt->max_epi, (int)(h->m + 1 + h->p));
         bt->variants |= h->hslot.variant == VAR_XY ? HAS_XY : HAS_YX;
     }
-    // tiles stay grouped by slot: the persistent pass grid gives each block a contiguous
+    // tiles stay grouped by slot: the pass grid gives each block a contiguous
     // range, so a block restages the iterate only at slot boundaries
     std::vector<Tile> &mixed = all;
     size_t resident = 0;
@@ -1254,8 +1269,8 @@ static qcqp_status rebuild_tiles(qcqp_batch *bt)
     if (!mixed.empty())
         HIPCHK(hipMemcpyAsync(bt->dtiles, mixed.data(), mixed.size() * sizeof(Tile),
                               hipMemcpyHostToDevice, bt->stream));
-    // byte-balanced ranges of the persistent pass grid over the requests' tiles
-    bt->pass_grid = pass_grid_for(bt->opt.spec_trials, (int)bt->opt.storage, bt->max_nw);
+    // byte-balanced ranges of the pass grid over the requests' tiles
+    bt->pass_grid = pass_grid_for(bt->opt.spec_trials, (int)bt->opt.storage, bt->max_nw, (double)resident);
     {
         std::vector<int64_t> tb;
         tb.reserve(mixed.size());
