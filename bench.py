@@ -142,6 +142,9 @@ CONFIG2_SPEC = 3
 
 
 def workload_config2(args):
+    """The default bench line.  Three solvers over the same FP64 instance: the packed symmetric
+    pass (options.sym_pass, the line's value), the row-major FP64 pass and FP32 storage (both
+    reported beside it)."""
     import torch
     import qcqp_inputs as qi
     from paper_2605_29291_amd import Solver
@@ -151,24 +154,24 @@ def workload_config2(args):
     L0 = spectral_norm_gpu(inst.Q[0])
     tau_bar, gamma0 = 1.0 / L0, 0.1
     res = {}
-    for storage in ("float64", "float32"):
+    for name, storage, sym in (("sym", "float64", 1), ("float64", "float64", 0), ("float32", "float32", 0)):
         Qs = inst.Q if storage == "float64" else inst.Q.to(torch.float32)
         inst_s = qi.Instance(n, m, 0, Qs, inst.q, inst.c, inst.lb, inst.ub)
         s = Solver(inst_s, device=True, storage=storage, tau_bar=tau_bar, gamma0=gamma0, timing=1,
-                   spec_trials=CONFIG2_SPEC)
+                   spec_trials=CONFIG2_SPEC, sym_pass=sym)
         if storage != "float64":
             del Qs
         wall, lat, infos, x, y = run_solves(s, args.steps, args.warmup)
         avg_pass, tp = pass_stats(infos)
         pb = infos[0]["pass_bytes"]
         ok = all(i["status"] == "ok" and i["rel_kkt"] <= 1e-6 for i in infos)
-        res[storage] = dict(wall=wall, lat=lat, infos=infos, avg_pass=avg_pass, timed=tp,
-                            pass_bytes=pb, ok=ok, x=x.cpu().numpy(), y=y.cpu().numpy())
-        log(f"{storage}: {args.steps} solves in {wall:.3f} s; iters={infos[0]['iters']} "
+        res[name] = dict(wall=wall, lat=lat, infos=infos, avg_pass=avg_pass, timed=tp,
+                         pass_bytes=pb, ok=ok, x=x.cpu().numpy(), y=y.cpu().numpy())
+        log(f"{name}: {args.steps} solves in {wall:.3f} s; iters={infos[0]['iters']} "
             f"trials={infos[0]['trials']} passes={infos[0]['q_passes']} rel_kkt={infos[0]['rel_kkt']:.2e} "
             f"pass {avg_pass * 1e6:.1f} us = {pb / avg_pass / 1e9:.0f} GB/s")
         s.close()
-    r64 = res["float64"]
+    r = res["sym"]
     ceilings = stream_ceilings(inst.Q)
     Qhost = inst.Q.cpu().numpy()
     inst_h = qi.Instance(n, m, 0, Qhost, inst.q, inst.c, inst.lb, inst.ub)
@@ -176,14 +179,21 @@ def workload_config2(args):
     torch.cuda.empty_cache()
     # result check by the oracle's own KKT evaluation (one host pass)
     import oracle
-    kk = oracle.kkt(oracle.Problem(inst_h), r64["x"], r64["y"])
+    kk = oracle.kkt(oracle.Problem(inst_h), r["x"], r["y"])
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(inst_h, tau_bar, gamma0, r64["infos"][0]["trials"])
-    solves_s = args.steps / r64["wall"]
-    lat_ms = np.array(r64["lat"]) * 1e3
-    achieved = r64["pass_bytes"] / r64["avg_pass"] / 1e9
-    r32 = res["float32"]
+        cpu = cpu_baseline(inst_h, tau_bar, gamma0, r["infos"][0]["trials"])
+    solves_s = args.steps / r["wall"]
+    lat_ms = np.array(r["lat"]) * 1e3
+    achieved = r["pass_bytes"] / r["avg_pass"] / 1e9
+
+    def side(rr):
+        gbs = rr["pass_bytes"] / rr["avg_pass"] / 1e9
+        return {"solves_per_s": args.steps / rr["wall"], "q_pass_us": rr["avg_pass"] * 1e6,
+                "q_pass_bytes": rr["pass_bytes"], "q_pass_GBs": gbs, "q_pass_frac": gbs / HBM_PEAK_GBS,
+                "iters": rr["infos"][0]["iters"], "q_passes": rr["infos"][0]["q_passes"],
+                "rel_kkt": rr["infos"][0]["rel_kkt"], "all_converged": rr["ok"]}
+
     out = {
         "metric": METRIC,
         "value": solves_s,
@@ -191,33 +201,35 @@ def workload_config2(args):
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r64["wall"] / args.steps * 1e3,
+        "ms_per_step": r["wall"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "random convex QCQP n=2000 m=100, Q_i=A_iA_i'/n+0.01I, FP64 stack "
-                               "3.23 GB, rAPDB-yx non-monotone, fixed restart 400, rel-KKT<=1e-6",
-                   "n": 2000, "m": 100, "storage": "float64", "spec_trials": CONFIG2_SPEC,
-                   "tau_bar": tau_bar, "gamma0": gamma0},
+        "config": {"workload": "random convex QCQP n=2000 m=100, Q_i=A_iA_i'/n+0.01I, FP64 (3.23 GB "
+                               "row-major, 1.62 GB upper triangles), rAPDB-yx non-monotone, fixed "
+                               "restart 400, rel-KKT<=1e-6",
+                   "n": 2000, "m": 100, "storage": "float64", "sym_pass": 1,
+                   "spec_trials": CONFIG2_SPEC, "tau_bar": tau_bar, "gamma0": gamma0},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("traffic_bytes_per_launch_f64"),
-                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "kernel": f"k_pass<DT_F64,{CONFIG2_SPEC}>", "avg_pass_us": r64["avg_pass"] * 1e6,
-                     "bytes_per_pass": r64["pass_bytes"], "timed_passes": r64["timed"]},
+                     "traffic": measured_traffic("traffic_bytes_per_launch_f64_sym"),
+                     "traffic_unit": "bytes per pass (rocprofv3 FETCH_SIZE + WRITE_SIZE of k_spass and "
+                                     "k_sred, copy-calibrated)",
+                     "kernel": f"k_spass<{CONFIG2_SPEC}> + k_sred<{CONFIG2_SPEC}> (packed upper-triangle "
+                               "tiles; algorithmic bytes (m+1) n(n+1)/2 x 8)",
+                     "avg_pass_us": r["avg_pass"] * 1e6, "bytes_per_pass": r["pass_bytes"],
+                     "timed_passes": r["timed"]},
         "cpu_baseline": cpu,
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
-        "solve": {"iters": r64["infos"][0]["iters"], "trials": r64["infos"][0]["trials"],
-                  "q_passes": r64["infos"][0]["q_passes"], "rel_kkt": r64["infos"][0]["rel_kkt"],
-                  "rel_kkt_oracle_eval": kk["rel_kkt"], "f": kk["f"], "all_converged": r64["ok"]},
+        "solve": {"iters": r["infos"][0]["iters"], "trials": r["infos"][0]["trials"],
+                  "q_passes": r["infos"][0]["q_passes"], "rel_kkt": r["infos"][0]["rel_kkt"],
+                  "rel_kkt_oracle_eval": kk["rel_kkt"], "f": kk["f"], "all_converged": r["ok"]},
         "stream_ceilings": ceilings,
-        "fp32_storage": {"solves_per_s": args.steps / r32["wall"],
-                         "q_pass_GBs": r32["pass_bytes"] / r32["avg_pass"] / 1e9,
-                         "q_pass_frac": r32["pass_bytes"] / r32["avg_pass"] / 1e9 / HBM_PEAK_GBS,
-                         "iters": r32["infos"][0]["iters"], "q_passes": r32["infos"][0]["q_passes"],
-                         "rel_kkt": r32["infos"][0]["rel_kkt"], "all_converged": r32["ok"]},
+        "row_major_fp64": dict(side(res["float64"]),
+                               traffic=measured_traffic("traffic_bytes_per_launch_f64")),
+        "fp32_storage": side(res["float32"]),
     }
     return out
 
@@ -676,8 +688,9 @@ def workload_batch_pass(args):
 def workload_traffic(args):
     """Dispatches for the HBM-traffic counters (run under rocprofv3 --pmc FETCH_SIZE, then
     WRITE_SIZE): a plain device copy of known size (the calibration), then the config-2 FP64
-    pass exactly as the config-2 solves launch it (trial mode, CONFIG2_SPEC candidates) and a
-    BF16 pass as the serving batches launch it (2 candidates)."""
+    row-major pass and the packed symmetric pass (k_spass + k_sred) exactly as the config-2
+    solves launch them (trial mode, CONFIG2_SPEC candidates), and a BF16 pass as the serving
+    batches launch it (2 candidates)."""
     import torch
     import qcqp_inputs as qi
     from paper_2605_29291_amd import Solver
@@ -695,6 +708,10 @@ def workload_traffic(args):
     s = Solver(inst, device=True, storage="float64", tau_bar=1.0, spec_trials=CONFIG2_SPEC)
     s.time_pass(reps=3)
     out["f64_pass_bytes"] = 101 * 2000 * 2000 * 8
+    s.close()
+    s = Solver(inst, device=True, storage="float64", tau_bar=1.0, spec_trials=CONFIG2_SPEC, sym_pass=1)
+    s.time_pass(reps=3)
+    out["f64_sym_pass_bytes"] = 101 * (2000 * 2001 // 2) * 8
     s.close()
     Qb = inst.Q.to(torch.bfloat16)
     ib = qi.Instance(2000, 100, 0, Qb, inst.q, inst.c, inst.lb, inst.ub)

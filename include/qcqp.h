@@ -149,6 +149,15 @@ typedef struct {
                                   stream of default priority, ordered after this one */
     qcqp_stop_rule stop_rule;  /* KKT (default) or PAPER */
     double f_star;             /* the optimal value the PAPER rule compares against */
+    int sym_pass;              /* 1: the Q pass streams a second copy of the stack that holds
+                                  only the upper-triangle 128 x 128 tiles of each Q_i (about
+                                  half the bytes): each off-diagonal tile serves both its rows
+                                  (Q_IJ w_J) and, transposed, its columns (Q_IJ' w_I), and a
+                                  second kernel sums the per-tile results in a fixed order.
+                                  Uses only the upper triangle, so Q_i must be symmetric (as
+                                  in the problem class).  F64 storage and single-instance
+                                  solves only (a batch refuses such a handle).  0: the
+                                  row-major pass (default). */
 } qcqp_options;
 
 typedef struct {
@@ -164,7 +173,8 @@ typedef struct {
     double seconds;            /* wall time of the call */
     double pass_seconds;       /* summed Q-pass kernel time (only with options.timing) */
     double last_gap;           /* last G_xi value (NaN if none) */
-    int64_t pass_bytes;        /* algorithmic HBM bytes of one Q pass: (m+has_q0) n^2 sizeof(storage) */
+    int64_t pass_bytes;        /* algorithmic HBM bytes of one Q pass: (m+has_q0) n^2 sizeof(storage);
+                                  with sym_pass the upper triangles, (m+has_q0) n(n+1)/2 x 8 */
     int64_t timed_passes;      /* Q passes covered by pass_seconds */
     double stop_value;         /* the stop rule's value at the returned iterate */
 } qcqp_info;

@@ -51,7 +51,7 @@ class Options(C.Structure):
                 ("storage", C.c_int), ("pass_mode", C.c_int), ("spec_trials", C.c_int),
                 ("poll_every", C.c_int64), ("timing", C.c_int), ("inner_tol", C.c_double),
                 ("max_inner", C.c_int64), ("use_graphs", C.c_int), ("stream", C.c_void_p),
-                ("stop_rule", C.c_int), ("f_star", C.c_double)]
+                ("stop_rule", C.c_int), ("f_star", C.c_double), ("sym_pass", C.c_int)]
 
 
 class Info(C.Structure):

@@ -113,12 +113,28 @@ struct Tile {
 // one trial group for the slots listed in live[0..nslots); variants = HAS_YX | HAS_XY mask
 // tiles[starts[b] .. starts[b+1]) go to pass block b (starts: min(pass_grid, ntiles) + 1 entries,
 // or NULL for equal tile counts per block)
+// Packed symmetric stack (options.sym_pass): for every stored matrix s, the tiles (I, J), I <= J,
+// of SYM_T x SYM_T FP64 values (row-major inside a tile, zero beyond n), row of tiles by row of
+// tiles.  One 64-lane block per tile yields the row products Q_IJ w_J and, for I < J, the
+// column products Q_IJ' w_I; a second kernel adds them per output row in a fixed order.
+constexpr int SYM_T = 128;
+struct SymPass {
+    const double *P;         // nq * ntt packed tiles
+    double *ws;              // per tile: row results [B][SYM_T], then column results [B][SYM_T]
+    const int32_t *ubase;    // output row of the first row of stored matrix s: (matrix index) n
+    int32_t n, NT, ntt, nq;  // NT = ceil(n / SYM_T) tiles per side, ntt = NT (NT + 1) / 2
+    int32_t B;               // candidate slots of the workspace
+};
+hipError_t launch_sym_pack(hipStream_t s, const double *Q, int64_t ld, const SymPass &sp, double *P);
+
+// one trial group; sym != NULL streams the packed symmetric stack instead of the tiles
 hipError_t launch_group(hipStream_t s, Slot *slots, const int *live, int nslots, const Tile *tiles,
                         int ntiles, const int *starts, int B, int dtype, int variants,
                         int max_nblk_step, int max_ny, int max_nw, int max_epi, int pass_grid,
-                        int nt, hipEvent_t ev0, hipEvent_t ev1);
+                        int nt, hipEvent_t ev0, hipEvent_t ev1, const SymPass *sym = nullptr);
 hipError_t launch_pass_only(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles,
-                            const int *starts, int B, int dtype, int max_nw, int pass_grid, int nt);
+                            const int *starts, int B, int dtype, int max_nw, int pass_grid, int nt,
+                            const SymPass *sym = nullptr);
 // pass grid: resident blocks per CU of k_pass for this configuration
 int pass_blocks_per_cu(int B, int dtype, int max_nw);
 size_t pass_lds_bytes(int B, int dtype, int max_nw);

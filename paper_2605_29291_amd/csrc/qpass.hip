@@ -397,9 +397,221 @@ int pass_blocks_per_cu(int B, int dtype, int max_nw)
     return o < 1 ? 1 : o;
 }
 
-hipError_t launch_pass_only(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles,
-                            const int *starts, int B, int dtype, int max_nw, int pass_grid, int nt)
+// ---------------------------------------------------------------------------------------
+// Packed symmetric pass.  Q_i = Q_i' (the problem class), so the tile Q_IJ of the upper
+// triangle also holds Q_JI = Q_IJ'.  Streaming only the tiles I <= J gives every product
+// (Q_i w)_r from the row dots of tile row I (J >= I) plus the column dots of tile column I
+// (K < I): about half the bytes of the row-major pass.
+
+// (I, J) of the k-th tile of a matrix, tiles ordered row of tiles by row of tiles, J >= I
+__device__ __forceinline__ void sym_tile_ij(int k, int NT, int &I, int &J)
 {
+    int i = 0, base = 0;
+    while (base + (NT - i) <= k) {
+        base += NT - i;
+        ++i;
+    }
+    I = i;
+    J = i + (k - base);
+}
+
+__device__ __forceinline__ int sym_tile_index(int s, int I, int J, int NT, int ntt)
+{
+    return s * ntt + I * NT - I * (I - 1) / 2 + (J - I);
+}
+
+__global__ void __launch_bounds__(256) k_sym_pack(const double *__restrict__ Q, int64_t ld, SymPass sp,
+                                                  double *__restrict__ P)
+{
+    const int t = blockIdx.x;
+    const int s = t / sp.ntt;
+    int I, J;
+    sym_tile_ij(t - s * sp.ntt, sp.NT, I, J);
+    double *dst = P + (size_t)t * SYM_T * SYM_T;
+    const double *src = Q + (size_t)s * sp.n * ld;
+    for (int e = threadIdx.x; e < SYM_T * SYM_T; e += 256) {
+        const int gr = I * SYM_T + e / SYM_T, gc = J * SYM_T + e % SYM_T;
+        dst[e] = (gr < sp.n && gc < sp.n) ? src[(size_t)gr * ld + gc] : 0.0;
+    }
+}
+
+hipError_t launch_sym_pack(hipStream_t s, const double *Q, int64_t ld, const SymPass &sp, double *P)
+{
+    const int ntiles = sp.nq * sp.ntt;
+    if (ntiles > 0) k_sym_pack<<<ntiles, 256, 0, s>>>(Q, ld, sp, P);
+    return hipGetLastError();
+}
+
+// One tile by one 64-lane wave: lane l holds columns 2l, 2l+1 of every row.  Row dots are
+// summed over the 64 lanes eight rows at a time by a transposing reduction (three exchange
+// steps that halve the rows each lane keeps, then three butterfly steps); the column dots
+// stay in the lane's registers over all rows.  Lane l also holds w_I at rows 2l, 2l+1, and
+// each row's value is broadcast from there with readlane.  The next eight rows' loads are in
+// flight while the current eight are reduced.
+
+// the value v of lane `src` (uniform) in every lane
+__device__ __forceinline__ double lane_bcast(double v, int src)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
+
+template <int NB>
+__device__ __forceinline__ void sym_tile(const double *__restrict__ q, int n, int I, int J,
+                                         const double *const (&w)[NB], double *__restrict__ rp,
+                                         double *__restrict__ cp, bool diag)
+{
+    using T = Store<DT_F64>;
+    const int lane = threadIdx.x & 63;
+    const int c = 2 * lane;
+    const int gc = J * SYM_T + c;
+    const int gi = I * SYM_T + c;
+    const bool cval = gc < n;
+    const int rmax = min(SYM_T, n - I * SYM_T);
+    auto load8 = [&](int r0, u32x4 (&v)[8]) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            v[i] = (r0 + i < rmax && cval) ? ld16<true>(q, ((size_t)(r0 + i) * SYM_T + c) * 8)
+                                           : u32x4{0u, 0u, 0u, 0u};
+    };
+    u32x4 v[8];
+    load8(0, v);
+    double xj0[NB], xj1[NB], xi0[NB], xi1[NB], ca0[NB], ca1[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        xj0[b] = cval ? w[b][gc] : 0.0;
+        xj1[b] = gc + 1 < n ? w[b][gc + 1] : 0.0;
+        xi0[b] = gi < n ? w[b][gi] : 0.0;
+        xi1[b] = gi + 1 < n ? w[b][gi + 1] : 0.0;
+        ca0[b] = 0.0;
+        ca1[b] = 0.0;
+    }
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+    for (int r0 = 0; r0 < rmax; r0 += 8) {
+        u32x4 vn[8];
+        if (r0 + 8 < rmax) load8(r0 + 8, vn);
+        double rp8[8][NB];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const double q0 = T::get(v[i], 0), q1 = T::get(v[i], 1);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                rp8[i][b] = fma(q1, xj1[b], q0 * xj0[b]);
+                if (!diag) {
+                    // rows r0 + i = 2 k + e live in lane k, element e (zero past n)
+                    const double xv = lane_bcast((i & 1) ? xi1[b] : xi0[b], (r0 + i) >> 1);
+                    ca0[b] = fma(q0, xv, ca0[b]);
+                    ca1[b] = fma(q1, xv, ca1[b]);
+                }
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            double v4[4], v2[2];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double send = b5 ? rp8[k][b] : rp8[4 + k][b];
+                const double keep = b5 ? rp8[4 + k][b] : rp8[k][b];
+                v4[k] = keep + __shfl_xor(send, 32, 64);
+            }
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const double send = b4 ? v4[k] : v4[2 + k];
+                const double keep = b4 ? v4[2 + k] : v4[k];
+                v2[k] = keep + __shfl_xor(send, 16, 64);
+            }
+            const double send = b3 ? v2[0] : v2[1];
+            const double keep = b3 ? v2[1] : v2[0];
+            double v1 = keep + __shfl_xor(send, 8, 64);
+            v1 += __shfl_xor(v1, 4, 64);
+            v1 += __shfl_xor(v1, 2, 64);
+            v1 += __shfl_xor(v1, 1, 64);
+            const int row = r0 + (b5 ? 4 : 0) + (b4 ? 2 : 0) + (b3 ? 1 : 0);
+            if ((lane & 7) == 0 && row < rmax) rp[b * SYM_T + row] = v1;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = vn[i];
+    }
+    if (!diag) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if (cval) cp[b * SYM_T + c] = ca0[b];
+            if (gc + 1 < n) cp[b * SYM_T + c + 1] = ca1[b];
+        }
+    }
+}
+
+template <int B>
+__global__ void __launch_bounds__(64, 4) k_spass(Slot *__restrict__ slots, SymPass sp)
+{
+    Slot *S = slots;
+    if (S->status != ST_RUNNING) return;
+    const int t = blockIdx.x;
+    const int s = t / sp.ntt;
+    int I, J;
+    sym_tile_ij(t - s * sp.ntt, sp.NT, I, J);
+    const double *q = sp.P + (size_t)t * SYM_T * SYM_T;
+    double *rp = sp.ws + (size_t)t * 2 * sp.B * SYM_T;
+    double *cp = rp + (size_t)sp.B * SYM_T;
+    if (S->mode == MODE_ANCHOR) {
+        const double *const w1[1] = {S->x};
+        sym_tile<1>(q, sp.n, I, J, w1, rp, cp, I == J);
+    } else {
+        const double *wb[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) wb[b] = S->xc[b];
+        sym_tile<B>(q, sp.n, I, J, wb, rp, cp, I == J);
+    }
+}
+
+// (Q_s w)_r for the rows of tile row I: the row results of tiles (I, J >= I), then the column
+// results of tiles (K < I, I), in that order
+template <int B>
+__global__ void __launch_bounds__(SYM_T) k_sred(Slot *__restrict__ slots, SymPass sp)
+{
+    Slot *S = slots;
+    if (S->status != ST_RUNNING) return;
+    const int s = blockIdx.x / sp.NT, I = blockIdx.x % sp.NT;
+    const int rr = threadIdx.x, gr = I * SYM_T + rr;
+    if (gr >= sp.n) return;
+    const bool anchor = S->mode == MODE_ANCHOR;
+    const int nb = anchor ? 1 : B;
+    const size_t stride = (size_t)2 * sp.B * SYM_T;
+    const size_t ob = (size_t)sp.ubase[s] + gr;
+    for (int b = 0; b < nb; ++b) {
+        double v = 0.0;
+        for (int J = I; J < sp.NT; ++J)
+            v += sp.ws[(size_t)sym_tile_index(s, I, J, sp.NT, sp.ntt) * stride + b * SYM_T + rr];
+        for (int K = 0; K < I; ++K)
+            v += sp.ws[(size_t)sym_tile_index(s, K, I, sp.NT, sp.ntt) * stride + (size_t)(sp.B + b) * SYM_T + rr];
+        double *out = anchor ? S->Uc[0] : S->Uc[b];
+        out[ob] = v;
+    }
+}
+
+template <int B>
+static void launch_sym_b(hipStream_t s, Slot *slots, const SymPass &sp)
+{
+    const int ntiles = sp.nq * sp.ntt;
+    if (ntiles <= 0) return;
+    k_spass<B><<<ntiles, 64, 0, s>>>(slots, sp);
+    k_sred<B><<<sp.nq * sp.NT, SYM_T, 0, s>>>(slots, sp);
+}
+
+hipError_t launch_pass_only(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles,
+                            const int *starts, int B, int dtype, int max_nw, int pass_grid, int nt,
+                            const SymPass *sym)
+{
+    if (sym) {
+        switch (B) {
+        case 1: launch_sym_b<1>(s, slots, *sym); break;
+        case 2: launch_sym_b<2>(s, slots, *sym); break;
+        case 3: launch_sym_b<3>(s, slots, *sym); break;
+        default: launch_sym_b<4>(s, slots, *sym); break;
+        }
+        return hipGetLastError();
+    }
     switch (B) {
     case 1: launch_pass_b<1>(s, slots, tiles, ntiles, starts, dtype, max_nw, pass_grid, nt); break;
     case 2: launch_pass_b<2>(s, slots, tiles, ntiles, starts, dtype, max_nw, pass_grid, nt); break;

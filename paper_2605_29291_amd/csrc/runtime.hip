@@ -206,6 +206,13 @@ struct qcqp_handle {
     qcqp_batch *owner = nullptr;
     double *gap_mem = nullptr;  // G_xi scratch: H (n x ldh), 6 vectors, partials, control
     size_t gap_bytes = 0;
+    // options.sym_pass: the packed upper-triangle copy of the stack, its per-tile results and
+    // the output row base of each stored matrix
+    bool use_sym = false;
+    SymPass sym{};
+    double *dP = nullptr, *dws = nullptr;
+    int32_t *dubase = nullptr;
+    size_t sym_bytes = 0;
 };
 
 struct qcqp_batch {
@@ -278,6 +285,7 @@ void qcqp_options_default(qcqp_options *o)
     o->stream = nullptr;
     o->stop_rule = QCQP_STOP_KKT;
     o->f_star = 0.0;
+    o->sym_pass = 0;
 }
 
 static qcqp_status validate_options(const qcqp_options *o)
@@ -315,6 +323,9 @@ static qcqp_status validate_options(const qcqp_options *o)
         return fail(QCQP_E_INVALID, "spec_trials must be in 1..%d", MAXB);
     if (o->pass_mode < QCQP_PASS_AUTO || o->pass_mode > QCQP_PASS_INCREMENTAL)
         return fail(QCQP_E_INVALID, "unknown pass mode");
+    if (o->sym_pass != 0 && o->sym_pass != 1) return fail(QCQP_E_INVALID, "sym_pass must be 0 or 1");
+    if (o->sym_pass && (o->storage != QCQP_F64 || o->pass_mode == QCQP_PASS_INCREMENTAL))
+        return fail(QCQP_E_INVALID, "sym_pass needs F64 storage and direct passes");
     return QCQP_OK;
 }
 
@@ -337,6 +348,11 @@ static void free_handle_memory(qcqp_handle *h)
     if (h->h_out) (void)hipHostFree(h->h_out);
     if (h->gap_mem) (void)hipFree(h->gap_mem);
     h->gap_mem = nullptr;
+    if (h->dP) (void)hipFree(h->dP);
+    if (h->dws) (void)hipFree(h->dws);
+    if (h->dubase) (void)hipFree(h->dubase);
+    h->dP = h->dws = nullptr;
+    h->dubase = nullptr;
     h->dQ = nullptr;
     h->arena = nullptr;
     h->h_poll = nullptr;
@@ -544,6 +560,35 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
         if (stage) (void)hipFree(stage);
     }
 
+    // ---- options.sym_pass: the packed upper-triangle copy of the stack ----
+    if (o.sym_pass && nq > 0) {
+        const int32_t NT = (int32_t)((n + SYM_T - 1) / SYM_T);
+        const int64_t ntt = (int64_t)NT * (NT + 1) / 2;
+        const size_t pbytes = (size_t)nq * ntt * SYM_T * SYM_T * sizeof(double);
+        const size_t wbytes = (size_t)nq * ntt * 2 * h->B * SYM_T * sizeof(double);
+        std::vector<int32_t> ub;
+        for (int64_t i = 0; i <= m; ++i)
+            if (qmap[i] >= 0) ub.push_back((int32_t)(i * n));
+        if (hipMalloc(&h->dP, pbytes) != hipSuccess || hipMalloc(&h->dws, wbytes) != hipSuccess ||
+            hipMalloc(&h->dubase, ub.size() * sizeof(int32_t)) != hipSuccess) {
+            free_handle_memory(h);
+            delete h;
+            return fail(QCQP_E_NOMEM, "packed symmetric stack (%zu bytes)", pbytes + wbytes);
+        }
+        h->sym = SymPass{h->dP, h->dws, h->dubase, (int32_t)n, NT, (int32_t)ntt, (int32_t)nq, (int32_t)h->B};
+        hipError_t e = hipMemcpyAsync(h->dubase, ub.data(), ub.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                      h->stream);
+        if (e == hipSuccess) e = launch_sym_pack(h->stream, (const double *)h->dQ, h->ld, h->sym, h->dP);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);   // ub is read by the copy
+        if (e != hipSuccess) {
+            free_handle_memory(h);
+            delete h;
+            return fail(QCQP_E_DEVICE, "packing the symmetric stack: %s", hipGetErrorString(e));
+        }
+        h->use_sym = true;
+        h->sym_bytes = pbytes + wbytes + ub.size() * sizeof(int32_t);
+    }
+
     // ---- arena for vectors and state ----
     const int B = h->B;
     h->nblk_step = (int)((n + STEP_COLS - 1) / STEP_COLS);
@@ -734,7 +779,7 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
     return QCQP_OK;
 }
 
-size_t qcqp_handle_bytes(const qcqp_handle *h) { return h ? h->q_bytes + h->arena_bytes : 0; }
+size_t qcqp_handle_bytes(const qcqp_handle *h) { return h ? h->q_bytes + h->arena_bytes + h->sym_bytes : 0; }
 
 qcqp_status qcqp_destroy(qcqp_handle *h)
 {
@@ -806,7 +851,8 @@ static void fill_info(const qcqp_handle *h, const Slot &S, qcqp_info *info, doub
     info->timed_passes = timed;
     info->last_gap = S.last_gap;
     info->stop_value = S.crit;
-    info->pass_bytes = (int64_t)h->nq * h->n * h->n * elem_size(h->dtype);
+    info->pass_bytes = h->use_sym ? (int64_t)h->nq * (h->n * (h->n + 1) / 2) * 8
+                                  : (int64_t)h->nq * h->n * h->n * elem_size(h->dtype);
     switch (S.status) {
     case ST_CONVERGED: info->status = QCQP_OK; break;
     case ST_MAX_ITER: info->status = QCQP_E_NOT_CONVERGED; break;
@@ -865,7 +911,8 @@ qcqp_status qcqp_solve(qcqp_handle *h, const double *x0, const double *y0, doubl
                                         h->hslot.variant == VAR_XY ? HAS_XY : HAS_YX, h->nblk_step, (int)std::max<int64_t>(h->ny, 1), (int)h->nw,
                                         (int)(h->m + 1 + h->p), h->pass_grid, h->nt,
                                         with_events ? ev[2 * g] : nullptr,
-                                        with_events ? ev[2 * g + 1] : nullptr);
+                                        with_events ? ev[2 * g + 1] : nullptr,
+                                        h->use_sym ? &h->sym : nullptr);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -966,7 +1013,8 @@ static qcqp_status eval_loaded_point(qcqp_handle *h)
     S.Gc[0] = h->d_geval;
     HIPCHK(hipMemsetAsync(h->d_ueval, 0, (h->m + 1) * h->n * 8, h->stream));
     HIPCHK(hipMemcpyAsync(h->dslot_eval, &S, sizeof(Slot), hipMemcpyHostToDevice, h->stream));
-    HIPCHK(launch_pass_only(h->stream, h->dslot_eval, h->dtiles, (int)h->tiles.size(), h->dstarts, h->B, h->dtype, (int)h->nw, h->pass_grid, h->nt));
+    HIPCHK(launch_pass_only(h->stream, h->dslot_eval, h->dtiles, (int)h->tiles.size(), h->dstarts, h->B, h->dtype, (int)h->nw, h->pass_grid, h->nt,
+                            h->use_sym ? &h->sym : nullptr));
     HIPCHK(launch_epi_anchor(h->stream, h->dslot_eval, h->dlive0, 1, (int)(h->m + 1 + h->p)));
     return QCQP_OK;
 }
@@ -1110,10 +1158,12 @@ qcqp_status qcqp_time_pass(qcqp_handle *h, int64_t reps, double *avg_seconds)
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    HIPCHK(launch_pass_only(h->stream, h->dslot, h->dtiles, (int)h->tiles.size(), h->dstarts, h->B, h->dtype, (int)h->nw, h->pass_grid, h->nt));
+    HIPCHK(launch_pass_only(h->stream, h->dslot, h->dtiles, (int)h->tiles.size(), h->dstarts, h->B, h->dtype, (int)h->nw, h->pass_grid, h->nt,
+                            h->use_sym ? &h->sym : nullptr));
     HIPCHK(hipEventRecord(e0, h->stream));
     for (int64_t r = 0; r < reps; ++r)
-        HIPCHK(launch_pass_only(h->stream, h->dslot, h->dtiles, (int)h->tiles.size(), h->dstarts, h->B, h->dtype, (int)h->nw, h->pass_grid, h->nt));
+        HIPCHK(launch_pass_only(h->stream, h->dslot, h->dtiles, (int)h->tiles.size(), h->dstarts, h->B, h->dtype, (int)h->nw, h->pass_grid, h->nt,
+                            h->use_sym ? &h->sym : nullptr));
     HIPCHK(hipEventRecord(e1, h->stream));
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -1198,6 +1248,7 @@ qcqp_status qcqp_batch_admit(qcqp_batch *bt, qcqp_handle *h, const double *x0, c
     if (h->owner) return fail(QCQP_E_INVALID, "handle already admitted");
     if (h->dtype != (int)bt->opt.storage || h->B != bt->opt.spec_trials || h->dev != bt->dev)
         return fail(QCQP_E_INVALID, "handle storage/spec_trials/device differ from the batch's");
+    if (h->use_sym) return fail(QCQP_E_INVALID, "a handle created with sym_pass solves alone only");
     int64_t free_slot = -1;
     for (int64_t s = 0; s < bt->max_slots; ++s)
         if (!bt->handles[s]) { free_slot = s; break; }

@@ -1,0 +1,136 @@
+"""GPU parity of the packed symmetric pass (options.sym_pass = 1) against the FP64 oracle.
+
+The packed stack holds only the upper-triangle 128 x 128 tiles of every Q_i; the products
+(Q_i w)_r are the row dots of tile row I plus the column dots of tile column I.  Checked:
+
+* one pass (qcqp_eval_operator): U = [Q_i x], g, f, grad_x Phi to <= 1e-12 normwise, for n a
+  multiple of 128, one past it, ragged, a single tile, with an equality block, without Q_0 and
+  with affine constraints that store no matrix;
+* trajectories: the same iterates as the oracle's (rtol 1e-10) for K iterations with two and
+  three speculative candidates, and the row-major pass's iterates within the same bar;
+* final solutions: relative KKT <= 1e-6 evaluated by the oracle; two solves bitwise equal;
+* the random convex QCQP n = 2000, m = 100 (the config-2 workload): converged, KKT by the oracle
+  on sampled operator rows of the returned point;
+* refusals: 16-bit storage with sym_pass, and a batch admitting a sym_pass handle.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from tests.gpu_common import announce, oracle, qi, tau_bar_of, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(inst, **kw):
+    from paper_2605_29291_amd import Solver
+    return Solver(inst, **kw)
+
+
+def _operator_parity(inst, seed=0, tol=1e-12):
+    s = _solver(inst, tau_bar=1.0, sym_pass=1)
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-3, 3, inst.n)
+    y = np.concatenate([rng.standard_normal(inst.p), rng.uniform(0, 2, inst.m)])
+    out = s.eval_operator(x, y)
+    P = oracle.Problem(inst)
+    ref = oracle.operator(P, x, y)
+    U, g, f, gr = (to_np(out[k]) for k in ("U", "g", "f", "grad"))
+    scale_u = max(np.max(np.abs(ref["U"])), 1e-300)
+    assert np.max(np.abs(U - ref["U"])) <= tol * scale_u * 10
+    gs = np.abs(0.5 * (ref["U"] @ x)) + np.abs(inst.q @ x) + np.abs(inst.c)
+    np.testing.assert_array_less(np.abs(g - ref["G"][inst.p:]), tol * 10 * (gs[1:] + 1e-300) + 1e-300)
+    assert abs(f[0] - ref["f"]) <= tol * 10 * gs[0]
+    gsc = np.max(np.abs(ref["grad"])) + 1e-300
+    assert np.max(np.abs(gr - ref["grad"])) <= tol * 10 * gsc * max(1.0, np.sum(np.abs(y)))
+    s.close()
+
+
+@pytest.mark.parametrize("n,m,p", [(128, 3, 0), (129, 4, 1), (300, 6, 0), (40, 2, 0), (513, 3, 2)])
+def test_sym_operator_matches_oracle(n, m, p):
+    inst = qi.random_qcqp(n, m, seed=3000 + n, shift=0.01, p=p)
+    announce(f"sym operator n={n} m={m} p={p}")
+    _operator_parity(inst)
+
+
+def test_sym_operator_without_q0_and_with_unstored_matrices():
+    inst = qi.kml_qcqp(npts=300, seed=3)
+    announce("sym operator kernel-learning QCQP (no Q_0)")
+    _operator_parity(inst)
+    base = qi.random_qcqp(260, 5, seed=31, shift=0.01)
+    Q = np.array(base.Q)
+    stored = np.array([1, 0, 1, 1, 0, 1], dtype=np.int32)
+    sparse = qi.Instance(260, 5, 0, Q[stored == 1], base.q, base.c, base.lb, base.ub, q_stored=stored)
+    announce("sym operator with unstored matrices")
+    _operator_parity(sparse, seed=1)
+
+
+@pytest.mark.parametrize("spec", [2, 3])
+def test_sym_trajectory_matches_oracle_and_row_major(spec):
+    inst = qi.random_qcqp(300, 8, seed=41, shift=0.01)
+    tb = tau_bar_of(inst)
+    K = 60
+    kw = dict(tau_bar=tb, gamma0=0.1, max_iter=K, tol=0.0)
+    announce(f"sym trajectory spec={spec}")
+    ref = oracle.solve(oracle.Problem(inst), oracle.Options(**kw))
+    xs, ys, infs = _solver(inst, spec_trials=spec, sym_pass=1, **kw).solve()
+    xr, yr, infr = _solver(inst, spec_trials=spec, **kw).solve()
+    assert infs["iters"] == K and infs["trials"] == ref["info"]["trials"] == infr["trials"]
+    np.testing.assert_allclose(to_np(xs), ref["x"], rtol=1e-10, atol=1e-11)
+    np.testing.assert_allclose(to_np(ys), ref["y"], rtol=1e-10, atol=1e-11)
+    np.testing.assert_allclose(to_np(xs), to_np(xr), rtol=1e-10, atol=1e-11)
+
+
+def test_sym_final_solution_and_determinism():
+    inst = qi.random_qcqp(400, 12, seed=43, shift=0.01, p=2)
+    tb = tau_bar_of(inst)
+    announce("sym final solution")
+    s = _solver(inst, tau_bar=tb, gamma0=0.1, spec_trials=3, sym_pass=1)
+    x1, y1, i1 = s.solve()
+    x2, y2, i2 = s.solve()
+    assert i1["status"] == "ok", i1
+    kk = oracle.kkt(oracle.Problem(inst), to_np(x1), to_np(y1))
+    assert kk["rel_kkt"] <= 1e-6, kk
+    assert abs(i1["rel_kkt"] - kk["rel_kkt"]) <= 1e-9
+    np.testing.assert_array_equal(to_np(x1), to_np(x2))
+    np.testing.assert_array_equal(to_np(y1), to_np(y2))
+    n = inst.n
+    assert i1["pass_bytes"] == (inst.m + 1) * (n * (n + 1) // 2) * 8
+
+
+def test_sym_full_size_random_qcqp():
+    """The random convex QCQP n=2000, m=100 solved through the packed symmetric pass; the
+    returned point checked by the oracle's KKT evaluation (one host pass over the stack)."""
+    import torch
+    n, m = 2000, 100
+    announce("sym full size n=2000 m=100")
+    inst = qi.random_qcqp_torch(n, m, qi.config_seed(2), shift=0.01, device="cuda")
+    L0 = float(torch.linalg.matrix_norm(inst.Q[0], ord=2))
+    s = _solver(inst, device=True, tau_bar=1.0 / L0, gamma0=0.1, spec_trials=3, sym_pass=1)
+    x, y, info = s.solve()
+    s.close()
+    assert info["status"] == "ok", info
+    host = dataclasses.replace(inst, Q=inst.Q.cpu().numpy())
+    del inst
+    torch.cuda.empty_cache()
+    kk = oracle.kkt(oracle.Problem(host), to_np(x), to_np(y))
+    assert kk["rel_kkt"] <= 1e-6, kk
+    assert abs(info["rel_kkt"] - kk["rel_kkt"]) <= 1e-9
+
+
+def test_sym_refusals():
+    from paper_2605_29291_amd import Batch, QCQPError
+    inst = qi.random_qcqp(100, 2, seed=45, shift=0.01)
+    announce("sym refusals")
+    with pytest.raises(QCQPError) as e:
+        _solver(qi.round_instance(inst, "bfloat16"), storage="bfloat16", tau_bar=1.0, sym_pass=1)
+    assert e.value.code == 1
+    s = _solver(inst, tau_bar=1.0, sym_pass=1)
+    b = Batch(max_slots=2)
+    with pytest.raises(QCQPError) as e:
+        b.admit(s)
+    assert e.value.code == 1
+    b.close()
+    x, y, info = s.solve()
+    assert info["status"] == "ok"
