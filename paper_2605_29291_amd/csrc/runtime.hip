@@ -894,9 +894,10 @@ qcqp_status qcqp_solve(qcqp_handle *h, const double *x0, const double *y0, doubl
         poll = std::max<int64_t>(4, (int64_t)std::ceil(1e-3 / group_s));
     }
     const bool timing = h->opt.timing != 0;
+    // timing: two sets of per-group events, one per chunk of the pipelined polls below
     std::vector<hipEvent_t> ev;
     if (timing) {
-        ev.resize(2 * poll);
+        ev.resize(4 * poll);
         for (auto &x : ev) HIPCHK(hipEventCreate(&x));
     }
     double pass_secs = 0.0;
@@ -905,13 +906,13 @@ qcqp_status qcqp_solve(qcqp_handle *h, const double *x0, const double *y0, doubl
     Slot snap = S0;           // the last status snapshot read on the host
     qcqp_status result = QCQP_OK;
     int64_t passes_before = 0;
-    auto launch_chunk = [&](hipStream_t s, bool with_events) -> hipError_t {
+    auto launch_chunk = [&](hipStream_t s, bool with_events, int set = 0) -> hipError_t {
         for (int64_t g = 0; g < poll; ++g) {
             hipError_t e = launch_group(s, h->dslot, h->dlive0, 1, h->dtiles, ntiles, h->dstarts, h->B, h->dtype,
                                         h->hslot.variant == VAR_XY ? HAS_XY : HAS_YX, h->nblk_step, (int)std::max<int64_t>(h->ny, 1), (int)h->nw,
                                         (int)(h->m + 1 + h->p), h->pass_grid, h->nt,
-                                        with_events ? ev[2 * g] : nullptr,
-                                        with_events ? ev[2 * g + 1] : nullptr,
+                                        with_events ? ev[2 * (set * poll + g)] : nullptr,
+                                        with_events ? ev[2 * (set * poll + g) + 1] : nullptr,
                                         h->use_sym ? &h->sym : nullptr);
             if (e != hipSuccess) return e;
         }
@@ -924,13 +925,14 @@ qcqp_status qcqp_solve(qcqp_handle *h, const double *x0, const double *y0, doubl
         HIPCHK(capture_graph(h->stream, [&](hipStream_t s) { return launch_chunk(s, false); }, &h->gexec));
         h->gexec_groups = poll;
     }
-    // Pipelined polls (eager launches without timing, and graphs): one chunk is always queued
-    // behind the one whose status snapshot the host reads, so the device does not idle for the
-    // host round trip.  Once the slot stops running every later group returns at once, so the
-    // extra chunk is a no-op; at a pending G_xi evaluation the queue is drained first.
-    if (!timing) {
+    // Pipelined polls: one chunk is always queued behind the one whose status snapshot the host
+    // reads, so the device does not idle for the host round trip.  Once the slot stops running
+    // every later group returns at once, so the extra chunk is a no-op; at a pending G_xi
+    // evaluation the queue is drained first.  With timing, chunk buffer `buf` records its
+    // groups' pass events in event set `buf`, read once its snapshot has arrived.
+    {
         auto enqueue = [&](int buf) -> hipError_t {
-            hipError_t e = graphs ? hipGraphLaunch(h->gexec, h->stream) : launch_chunk(h->stream, false);
+            hipError_t e = graphs ? hipGraphLaunch(h->gexec, h->stream) : launch_chunk(h->stream, timing, buf);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(&h->h_poll[buf], h->dslot, sizeof(Slot), hipMemcpyDeviceToHost, h->stream);
             if (e == hipSuccess) e = hipEventRecord(h->ev_snap[buf], h->stream);
@@ -943,6 +945,20 @@ qcqp_status qcqp_solve(qcqp_handle *h, const double *x0, const double *y0, doubl
             if (e == hipSuccess) e = hipEventSynchronize(h->ev_snap[pending]);
             if (e != hipSuccess) break;
             const Slot &sn = h->h_poll[pending];
+            if (timing) {
+                // the groups that streamed a pass are the first (passes now - passes before) of
+                // the chunk: once the slot stops running every later group is a no-op
+                const int64_t worked = std::min<int64_t>(poll, sn.passes - passes_before);
+                for (int64_t g = 0; g < worked; ++g) {
+                    float ms = 0.f;
+                    if (hipEventElapsedTime(&ms, ev[2 * (pending * poll + g)], ev[2 * (pending * poll + g) + 1]) ==
+                        hipSuccess) {
+                        pass_secs += ms * 1e-3;
+                        timed += 1;
+                    }
+                }
+                passes_before = sn.passes;
+            }
             if (sn.status == ST_GAP_PENDING) {
                 e = hipStreamSynchronize(h->stream);   // the queued chunk saw the same pending state
                 if (e != hipSuccess) break;
@@ -961,33 +977,6 @@ qcqp_status qcqp_solve(qcqp_handle *h, const double *x0, const double *y0, doubl
             pending = 1 - pending;
         }
         if (e != hipSuccess && !result) result = fail(QCQP_E_DEVICE, "launch/poll: %s", hipGetErrorString(e));
-    }
-    for (; timing && !result;) {
-        hipError_t el = launch_chunk(h->stream, true);
-        if (el != hipSuccess) { result = fail(QCQP_E_DEVICE, "launch: %s", hipGetErrorString(el)); break; }
-        hipError_t e = hipMemcpyAsync(&h->h_poll[0], h->dslot, sizeof(Slot), hipMemcpyDeviceToHost, h->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-        if (e != hipSuccess) { result = fail(QCQP_E_DEVICE, "poll: %s", hipGetErrorString(e)); break; }
-        snap = h->h_poll[0];
-        {
-            // the groups that streamed a pass are the first (passes now - passes before) of the
-            // chunk: once the slot stops running every later group is a no-op
-            const int64_t worked = std::min<int64_t>(poll, snap.passes - passes_before);
-            for (int64_t g = 0; g < worked; ++g) {
-                float ms = 0.f;
-                if (hipEventElapsedTime(&ms, ev[2 * g], ev[2 * g + 1]) == hipSuccess) {
-                    pass_secs += ms * 1e-3;
-                    timed += 1;
-                }
-            }
-        }
-        passes_before = snap.passes;
-        if (snap.status == ST_GAP_PENDING) {
-            double gval = 0.0, kk[6];
-            if ((result = run_gap_for(h, h->dslot, snap, &gval, kk))) break;
-            continue;
-        }
-        if (snap.status != ST_RUNNING) break;
     }
     for (auto &x : ev) (void)hipEventDestroy(x);
     if (result) return result;

@@ -182,3 +182,21 @@ def test_graph_replays_match_eager_launches():
         b.close()
     np.testing.assert_array_equal(res[0][0], res[1][0])
     np.testing.assert_array_equal(res[0][0], xe)
+
+
+@pytest.mark.parametrize("sym", [0, 1])
+def test_timing_mode_matches_and_times_every_pass(sym):
+    """options.timing records HIP events around every pass of pipelined chunks (two event sets,
+    read once a chunk's status snapshot is back): the same iterates as without timing, and
+    every streamed pass timed, over several chunks and through a fixed restart."""
+    inst = qi.random_qcqp(300, 8, seed=51, shift=0.01)
+    tb = tau_bar_of(inst)
+    kw = gpu_opts(tb, spec_trials=3, sym_pass=sym, poll_every=3, restart_every=20)
+    announce(f"timing mode sym={sym}")
+    x0, y0, i0 = _solver(inst, **kw).solve()
+    x1, y1, i1 = _solver(inst, timing=1, **kw).solve()
+    np.testing.assert_array_equal(to_np(x1), to_np(x0))
+    np.testing.assert_array_equal(to_np(y1), to_np(y0))
+    assert i1["status"] == "ok" and i1["q_passes"] == i0["q_passes"] and i1["restarts"] >= 1
+    assert i1["timed_passes"] == i1["q_passes"]
+    assert i1["pass_seconds"] > 0.0
