@@ -139,6 +139,8 @@ def stream_ceilings(Q):
 # speculative candidates per pass for the config-2 solves: the iterates and trial counts are
 # those of sequential backtracking for any value; 3 streams 60 passes per solve instead of 67
 CONFIG2_SPEC = 3
+# candidates for the packed symmetric pass, whose per-wave registers grow with B
+CONFIG2_SYM_SPEC = 3
 
 
 def workload_config2(args):
@@ -155,10 +157,11 @@ def workload_config2(args):
     tau_bar, gamma0 = 1.0 / L0, 0.1
     res = {}
     for name, storage, sym in (("sym", "float64", 1), ("float64", "float64", 0), ("float32", "float32", 0)):
+        spec = CONFIG2_SYM_SPEC if sym else CONFIG2_SPEC
         Qs = inst.Q if storage == "float64" else inst.Q.to(torch.float32)
         inst_s = qi.Instance(n, m, 0, Qs, inst.q, inst.c, inst.lb, inst.ub)
         s = Solver(inst_s, device=True, storage=storage, tau_bar=tau_bar, gamma0=gamma0, timing=1,
-                   spec_trials=CONFIG2_SPEC, sym_pass=sym)
+                   spec_trials=spec, sym_pass=sym)
         if storage != "float64":
             del Qs
         wall, lat, infos, x, y = run_solves(s, args.steps, args.warmup)
@@ -166,7 +169,7 @@ def workload_config2(args):
         pb = infos[0]["pass_bytes"]
         ok = all(i["status"] == "ok" and i["rel_kkt"] <= 1e-6 for i in infos)
         res[name] = dict(wall=wall, lat=lat, infos=infos, avg_pass=avg_pass, timed=tp,
-                         pass_bytes=pb, ok=ok, x=x.cpu().numpy(), y=y.cpu().numpy())
+                         pass_bytes=pb, ok=ok, x=x.cpu().numpy(), y=y.cpu().numpy(), spec=spec)
         log(f"{name}: {args.steps} solves in {wall:.3f} s; iters={infos[0]['iters']} "
             f"trials={infos[0]['trials']} passes={infos[0]['q_passes']} rel_kkt={infos[0]['rel_kkt']:.2e} "
             f"pass {avg_pass * 1e6:.1f} us = {pb / avg_pass / 1e9:.0f} GB/s")
@@ -192,7 +195,7 @@ def workload_config2(args):
         return {"solves_per_s": args.steps / rr["wall"], "q_pass_us": rr["avg_pass"] * 1e6,
                 "q_pass_bytes": rr["pass_bytes"], "q_pass_GBs": gbs, "q_pass_frac": gbs / HBM_PEAK_GBS,
                 "iters": rr["infos"][0]["iters"], "q_passes": rr["infos"][0]["q_passes"],
-                "rel_kkt": rr["infos"][0]["rel_kkt"], "all_converged": rr["ok"]}
+                "rel_kkt": rr["infos"][0]["rel_kkt"], "all_converged": rr["ok"], "spec_trials": rr["spec"]}
 
     out = {
         "metric": METRIC,
@@ -211,13 +214,13 @@ def workload_config2(args):
                                "row-major, 1.62 GB upper triangles), rAPDB-yx non-monotone, fixed "
                                "restart 400, rel-KKT<=1e-6",
                    "n": 2000, "m": 100, "storage": "float64", "sym_pass": 1,
-                   "spec_trials": CONFIG2_SPEC, "tau_bar": tau_bar, "gamma0": gamma0},
+                   "spec_trials": CONFIG2_SYM_SPEC, "tau_bar": tau_bar, "gamma0": gamma0},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic("traffic_bytes_per_launch_f64_sym"),
                      "traffic_unit": "bytes per pass (rocprofv3 FETCH_SIZE + WRITE_SIZE of k_spass and "
                                      "k_sred, copy-calibrated)",
-                     "kernel": f"k_spass<{CONFIG2_SPEC}> + k_sred<{CONFIG2_SPEC}> (packed upper-triangle "
+                     "kernel": f"k_spass<{CONFIG2_SYM_SPEC}> + k_sred<{CONFIG2_SYM_SPEC}> (packed upper-triangle "
                                "tiles; algorithmic bytes (m+1) n(n+1)/2 x 8)",
                      "avg_pass_us": r["avg_pass"] * 1e6, "bytes_per_pass": r["pass_bytes"],
                      "timed_passes": r["timed"]},
@@ -709,7 +712,7 @@ def workload_traffic(args):
     s.time_pass(reps=3)
     out["f64_pass_bytes"] = 101 * 2000 * 2000 * 8
     s.close()
-    s = Solver(inst, device=True, storage="float64", tau_bar=1.0, spec_trials=CONFIG2_SPEC, sym_pass=1)
+    s = Solver(inst, device=True, storage="float64", tau_bar=1.0, spec_trials=CONFIG2_SYM_SPEC, sym_pass=1)
     s.time_pass(reps=3)
     out["f64_sym_pass_bytes"] = 101 * (2000 * 2001 // 2) * 8
     s.close()

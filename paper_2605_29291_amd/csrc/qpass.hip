@@ -543,7 +543,7 @@ __device__ __forceinline__ void sym_tile(const double *__restrict__ q, int n, in
 }
 
 template <int B>
-__global__ void __launch_bounds__(64, 4) k_spass(Slot *__restrict__ slots, SymPass sp)
+__global__ void __launch_bounds__(64, B <= 2 ? 4 : 3) k_spass(Slot *__restrict__ slots, SymPass sp)
 {
     Slot *S = slots;
     if (S->status != ST_RUNNING) return;
