@@ -579,12 +579,29 @@ __global__ void __launch_bounds__(SYM_T) k_sred(Slot *__restrict__ slots, SymPas
     const int nb = anchor ? 1 : B;
     const size_t stride = (size_t)2 * sp.B * SYM_T;
     const size_t ob = (size_t)sp.ubase[s] + gr;
+    // the terms in the order (J = I .. NT-1 row results, then K = 0 .. I-1 column results),
+    // loaded eight at a time so that the loads are in flight together
+    const int nterm = sp.NT;
     for (int b = 0; b < nb; ++b) {
         double v = 0.0;
-        for (int J = I; J < sp.NT; ++J)
-            v += sp.ws[(size_t)sym_tile_index(s, I, J, sp.NT, sp.ntt) * stride + b * SYM_T + rr];
-        for (int K = 0; K < I; ++K)
-            v += sp.ws[(size_t)sym_tile_index(s, K, I, sp.NT, sp.ntt) * stride + (size_t)(sp.B + b) * SYM_T + rr];
+        for (int k0 = 0; k0 < nterm; k0 += 8) {
+            double t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = k0 + u;
+                t[u] = 0.0;
+                if (k < nterm) {
+                    const int J = I + k;
+                    t[u] = J < sp.NT
+                               ? sp.ws[(size_t)sym_tile_index(s, I, J, sp.NT, sp.ntt) * stride + b * SYM_T + rr]
+                               : sp.ws[(size_t)sym_tile_index(s, J - sp.NT, I, sp.NT, sp.ntt) * stride +
+                                       (size_t)(sp.B + b) * SYM_T + rr];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (k0 + u < nterm) v += t[u];
+        }
         double *out = anchor ? S->Uc[0] : S->Uc[b];
         out[ob] = v;
     }
