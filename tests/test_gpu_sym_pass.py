@@ -7,10 +7,11 @@ The packed stack holds only the upper-triangle 128 x 128 tiles of every Q_i; the
   multiple of 128, one past it, ragged, a single tile, with an equality block, without Q_0 and
   with affine constraints that store no matrix;
 * trajectories: the same iterates as the oracle's (rtol 1e-10) for K iterations with two and
-  three speculative candidates, and the row-major pass's iterates within the same bar;
+  three speculative candidates, and the row-major pass's iterates within the same bar; the
+  APDB-xy routine as well;
 * final solutions: relative KKT <= 1e-6 evaluated by the oracle; two solves bitwise equal;
-* the random convex QCQP n = 2000, m = 100 (the config-2 workload): converged, KKT by the oracle
-  on sampled operator rows of the returned point;
+* the random convex QCQP n = 2000, m = 100 (the config-2 workload): converged, relative KKT of
+  the returned point by the oracle's evaluation <= 1e-6;
 * refusals: 16-bit storage with sym_pass, and a batch admitting a sym_pass handle.
 """
 import dataclasses
@@ -80,6 +81,20 @@ def test_sym_trajectory_matches_oracle_and_row_major(spec):
     np.testing.assert_allclose(to_np(xs), ref["x"], rtol=1e-10, atol=1e-11)
     np.testing.assert_allclose(to_np(ys), ref["y"], rtol=1e-10, atol=1e-11)
     np.testing.assert_allclose(to_np(xs), to_np(xr), rtol=1e-10, atol=1e-11)
+
+
+def test_sym_xy_trajectory_matches_oracle():
+    inst = qi.random_qcqp(260, 6, seed=47, shift=0.01, p=1)
+    tb = tau_bar_of(inst)
+    K = 50
+    kw = dict(tau_bar=tb, gamma0=0.1, max_iter=K, tol=0.0)
+    xy = dict(c_alpha=0.25, c_beta=0.3, delta=0.4)
+    announce("sym trajectory xy")
+    ref = oracle.solve(oracle.Problem(inst), oracle.Options.xy(**kw))
+    x, y, info = _solver(inst, spec_trials=2, sym_pass=1, variant="xy", **xy, **kw).solve()
+    assert info["iters"] == K and info["trials"] == ref["info"]["trials"]
+    np.testing.assert_allclose(to_np(x), ref["x"], rtol=1e-10, atol=1e-11)
+    np.testing.assert_allclose(to_np(y), ref["y"], rtol=1e-10, atol=1e-11)
 
 
 def test_sym_final_solution_and_determinism():
