@@ -518,11 +518,12 @@ def workload_kml_minmax(args):
     from paper_2605_29291_amd import Solver
     out = {}
     for npts in (4000, 10000):
-        for storage in ("float64", "bfloat16"):
+        for label, storage, sym in (("float64", "float64", 0), ("float64_sym", "float64", 1),
+                                    ("bfloat16", "bfloat16", 0)):
             sd = {"float64": torch.float64, "bfloat16": torch.bfloat16}[storage]
-            log(f"kml min-max: n={npts} {storage}")
+            log(f"kml min-max: n={npts} {label}")
             inst = qi.kml_minmax(npts, seed=qi.config_seed(4), device="cuda", store_dtype=sd)
-            kw = dict(tau_bar=0.5, gamma0=0.1, mu=2.0, restart_every=200)
+            kw = dict(tau_bar=0.5, gamma0=0.1, mu=2.0, restart_every=200, sym_pass=sym)
             s = Solver(inst, device=True, storage=storage, **kw)
             wall, lat, infos, x, y = run_solves(s, args.steps, args.warmup)
             st = Solver(inst, device=True, storage=storage, timing=1, **kw)
@@ -530,13 +531,13 @@ def workload_kml_minmax(args):
             avg, tp = pass_stats(tinfos)
             info = infos[-1]
             pb = info["pass_bytes"]
-            out[f"n{npts}_{storage}"] = dict(
+            out[f"n{npts}_{label}"] = dict(
                 solves_per_s=args.steps / wall, ms_per_solve=wall / args.steps * 1e3,
                 iters=info["iters"], trials=info["trials"], q_passes=info["q_passes"],
                 rel_kkt=info["rel_kkt"], status=info["status"],
                 q_pass_us=avg * 1e6, q_pass_GBs=pb / avg / 1e9, bytes_per_pass=pb,
                 lambda_=[float(v) for v in y[1:].tolist()])
-            log(f"  {out[f'n{npts}_{storage}']}")
+            log(f"  {out[f'n{npts}_{label}']}")
             s.close()
             st.close()
             del inst

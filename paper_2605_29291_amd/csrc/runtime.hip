@@ -514,8 +514,11 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
     h->ld = round_up(n, 128 / es);
     h->nw = round_up(n, vec_width(h->dtype));
     {
+        // the row-major trial pass stages B candidates in LDS; the packed symmetric pass keeps
+        // them in registers, and only the single-vector products (step-size estimate) stage x
         const size_t acc = h->dtype == DT_F64 ? 8 : 4;
-        const size_t lds = std::max<size_t>((size_t)h->nw * 8, (size_t)h->B * h->nw * acc);
+        const size_t trial = o.sym_pass ? 0 : (size_t)h->B * h->nw * acc;
+        const size_t lds = std::max<size_t>((size_t)h->nw * 8, trial);
         if (lds > (size_t)max_lds) {
             delete h;
             return fail(QCQP_E_INVALID, "n = %lld with spec_trials = %d needs %zu bytes of LDS (device allows %d)",

@@ -134,6 +134,29 @@ def test_sym_full_size_random_qcqp():
     assert abs(info["rel_kkt"] - kk["rel_kkt"]) <= 1e-9
 
 
+def test_sym_large_n_three_candidates():
+    """n = 10000 with three candidates: the row-major pass would need 240 KB of LDS for the staged
+    trial points and is refused; the packed pass holds them in registers."""
+    import torch
+    from paper_2605_29291_amd import QCQPError
+    n = 10000
+    announce("sym n=10000 spec=3")
+    inst = qi.random_qcqp_torch(n, 0, 409, shift=0.01, device="cuda")
+    with pytest.raises(QCQPError):
+        _solver(inst, device=True, tau_bar=1.0, spec_trials=3)
+    s = _solver(inst, device=True, tau_bar=1.0, spec_trials=3, sym_pass=1)
+    rng = np.random.default_rng(2)
+    x = rng.uniform(-1, 1, n)
+    out = s.eval_operator(x)
+    s.close()
+    host = dataclasses.replace(inst, Q=inst.Q.cpu().numpy())
+    del inst
+    torch.cuda.empty_cache()
+    ref = oracle.operator(oracle.Problem(host), x, np.zeros(0))
+    U = to_np(out["U"])
+    assert np.max(np.abs(U - ref["U"])) <= 1e-11 * np.max(np.abs(ref["U"]))
+
+
 def test_sym_refusals():
     from paper_2605_29291_amd import Batch, QCQPError
     inst = qi.random_qcqp(100, 2, seed=45, shift=0.01)
