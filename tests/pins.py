@@ -7,7 +7,9 @@ None of these share code with the oracle or the GPU path:
     with the multipliers found by (nested) bisection on the monotone map lambda -> g(x(lambda));
   * barrier_qcqp: a textbook log-barrier interior-point method (Newton with backtracking,
     equality-constrained Newton steps when p > 0) giving f* independently;
-  * box_qp_enumerate: exact minimiser of a strictly convex box QP by enumerating faces.
+  * box_qp_enumerate: exact minimiser of a strictly convex box QP by enumerating faces;
+  * smoothed_gap: the self-centred smoothed duality gap of a plain QCQP (lambda >= 0, no
+    equalities) with the y-part in closed form and the x-part by box_qp_enumerate (tiny n).
 """
 import itertools
 
@@ -225,3 +227,23 @@ def box_qp_enumerate(H, h, lo, hi):
         if best is None or val < best[1]:
             best = (D, val)
     return best
+
+
+def smoothed_gap(Q, q, c, lb, ub, x, lam, xi):
+    """G_xi(z; z) of the Definition "Smoothed duality gap" (§4) at z = (x, lambda), Euclidean
+    distances, for min f s.t. g_i <= 0 over a box: sup over lambda' >= 0 of
+    Phi(x, lambda') - xi ||lambda' - lambda||^2 minus inf over x' in X of
+    Phi(x', lambda) + xi ||x' - x||^2, both centred at z.
+
+    The y-part is concave and separable: lambda'_i = max(0, lambda_i + g_i(x) / (2 xi)).  The
+    x-part is a strictly convex box QP in D = x' - x with Hessian Q(lambda) + 2 xi I and gradient
+    grad_x Phi(x, lambda), minimised exactly by face enumeration (3^n faces)."""
+    Q = np.asarray(Q, dtype=float)
+    m = len(lam)
+    g = np.array([0.5 * x @ Q[i] @ x + q[i] @ x + c[i] for i in range(1, m + 1)])
+    lp = np.maximum(0.0, lam + g / (2.0 * xi))
+    py = (lp - lam) @ g - xi * np.sum((lp - lam) ** 2)
+    gx = Q[0] @ x + q[0] + sum(lam[i - 1] * (Q[i] @ x + q[i]) for i in range(1, m + 1))
+    H = Q[0] + sum(lam[i - 1] * Q[i] for i in range(1, m + 1)) + 2.0 * xi * np.eye(len(x))
+    _, val = box_qp_enumerate(H, gx, lb - x, ub - x)
+    return py - val
