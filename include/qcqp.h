@@ -210,6 +210,22 @@ qcqp_status qcqp_solve(qcqp_handle *h, const double *x0, const double *y0, doubl
 qcqp_status qcqp_eval_operator(qcqp_handle *h, const double *x, const double *y, double *Qx,
                                double *g, double *f, double *grad_x);
 
+/* The Q pass of one backtracking trial group, exactly as qcqp_solve launches it (the same
+ * kernels, grid, tiles, candidate count and accumulation type), on caller-given points: x is
+ * the iterate x^k (n) and xc holds nb = options.spec_trials trial points x^{k+1}_b (nb x n,
+ * row-major).  out (nb x (m+1) x n, row-major, rows of matrices that are not stored are 0)
+ * receives per candidate
+ *   - [Q_i x^{k+1}_b] for i = 0..m in the direct mode (FP64 storage), accumulated in FP64;
+ *   - W_b = [Q_i (x^{k+1}_b - x^k)] in the incremental mode (the default for 32/16-bit
+ *     storage): the step is rounded to FP32, each lane of the kernel sums its share of a row
+ *     (at most ceil(n / 8) products) in FP32, and the lanes' partial sums are combined in FP64.
+ * This is the product the test function E_k of §3.2 (eq. (apdb-yx-y)) and Algorithm 1 uses
+ * through U^{k+1} = U^k + W.  Host or device pointers as for the handle.  Errors:
+ * QCQP_E_INVALID (null pointer, nb != spec_trials, handle in a batch), QCQP_E_DEVICE.  Must not
+ * overlap a solve on the same handle. */
+qcqp_status qcqp_eval_trial_pass(qcqp_handle *h, const double *x, const double *xc, int64_t nb,
+                                 double *out);
+
 /* Relative KKT residual at (x, y) (the residual r(x,v,lambda) of the Theorem in §4.3 in
  * relative form): out6 = {rel_kkt, rel_dual, rel_pri, rel_comp, f, max_violation}; out6 is
  * always host memory. */

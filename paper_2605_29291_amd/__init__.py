@@ -178,6 +178,17 @@ class Solver:
         abi.check(L.qcqp_eval_operator(self.handle, xp, yp, Up, gp, fp, grp))
         return dict(U=U, g=g[: self.m], f=f, grad=gr)
 
+    def eval_trial_pass(self, x, xc):
+        """The trial group's Q pass at iterate x for the spec_trials points xc (rows):
+        [Q_i x_b] (direct mode) or [Q_i (x_b - x)] (incremental mode), shape (B, m+1, n)."""
+        L = load()
+        B = int(self.options.spec_trials)
+        xk, xp = self._in(x, self.n)
+        ck, cp = self._in(xc, B * self.n)
+        out, op = self._out(B, self.m + 1, self.n)
+        abi.check(L.qcqp_eval_trial_pass(self.handle, xp, cp, B, op))
+        return out
+
     def eval_kkt(self, x, y=None):
         L = load()
         xk, xp = self._in(x, self.n)

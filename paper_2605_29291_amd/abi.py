@@ -13,8 +13,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# QCQP_LIB may name another build of the same library (A/B measurements of kernel variants)
-LIB_PATH = os.environ.get("QCQP_LIB") or os.path.join(_HERE, "libqcqp_hip.so")
+LIB_PATH = os.path.join(_HERE, "libqcqp_hip.so")
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_NOT_CONVERGED, E_NUMERICAL, E_NO_ROOM = range(7)
 STATUS_NAMES = {0: "ok", 1: "invalid", 2: "nomem", 3: "device", 4: "not_converged",
@@ -69,7 +68,7 @@ class Info(C.Structure):
 
 
 SYMBOLS = ["qcqp_options_default", "qcqp_last_error", "qcqp_create", "qcqp_solve",
-           "qcqp_eval_operator", "qcqp_eval_kkt", "qcqp_eval_gap", "qcqp_destroy",
+           "qcqp_eval_operator", "qcqp_eval_trial_pass", "qcqp_eval_kkt", "qcqp_eval_gap", "qcqp_destroy",
            "qcqp_batch_create", "qcqp_batch_admit", "qcqp_batch_step", "qcqp_batch_poll",
            "qcqp_batch_fetch", "qcqp_batch_stats", "qcqp_batch_pass_stats", "qcqp_batch_destroy",
            "qcqp_handle_bytes", "qcqp_time_pass"]
@@ -98,6 +97,7 @@ def load(path: str = LIB_PATH):
     L.qcqp_create.argtypes = [P(Problem), P(Options), P(vp)]
     L.qcqp_solve.argtypes = [vp, vp, vp, vp, vp, P(Info)]
     L.qcqp_eval_operator.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.qcqp_eval_trial_pass.argtypes = [vp, vp, vp, i64, vp]
     L.qcqp_eval_kkt.argtypes = [vp, vp, vp, vp]
     L.qcqp_eval_gap.argtypes = [vp, vp, vp, C.c_double, vp]
     L.qcqp_destroy.argtypes = [vp]

@@ -1096,6 +1096,37 @@ qcqp_status qcqp_eval_operator(qcqp_handle *h, const double *x, const double *y,
     return QCQP_OK;
 }
 
+qcqp_status qcqp_eval_trial_pass(qcqp_handle *h, const double *x, const double *xc, int64_t nb,
+                                 double *out)
+{
+    g_err.clear();
+    if (!h || !x || !xc || !out) return fail(QCQP_E_INVALID, "null argument");
+    if (h->owner) return fail(QCQP_E_INVALID, "handle is admitted to a batch");
+    if (nb != h->B)
+        return fail(QCQP_E_INVALID, "nb = %lld must equal options.spec_trials = %d", (long long)nb, h->B);
+    HIPCHK(join_streams(h->stream, h->ustream, h->ev_join));
+    Slot S = h->hslot;
+    reset_run_scalars(S);
+    S.mode = MODE_TRIAL;
+    S.x = h->d_xe;
+    const int64_t n = h->n, un = (h->m + 1) * n;
+    const hipMemcpyKind kin = h->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const hipMemcpyKind kout = h->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    HIPCHK(hipMemcpyAsync(S.x, x, n * 8, kin, h->stream));
+    double *res[MAXB];
+    for (int b = 0; b < h->B; ++b) {
+        HIPCHK(hipMemcpyAsync(S.xc[b], xc + b * n, n * 8, kin, h->stream));
+        res[b] = (h->incremental && !h->use_sym) ? S.W[b] : S.Uc[b];
+        HIPCHK(hipMemsetAsync(res[b], 0, un * 8, h->stream));   // rows of matrices not stored
+    }
+    HIPCHK(hipMemcpyAsync(h->dslot_eval, &S, sizeof(Slot), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(launch_pass_only(h->stream, h->dslot_eval, h->dtiles, (int)h->tiles.size(), h->dstarts, h->B,
+                            h->dtype, (int)h->nw, h->pass_grid, h->nt, h->use_sym ? &h->sym : nullptr));
+    for (int b = 0; b < h->B; ++b) HIPCHK(hipMemcpyAsync(out + b * un, res[b], un * 8, kout, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return QCQP_OK;
+}
+
 qcqp_status qcqp_eval_kkt(qcqp_handle *h, const double *x, const double *y, double *out6)
 {
     g_err.clear();

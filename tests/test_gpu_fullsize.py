@@ -14,7 +14,7 @@ needs one pass) on exactly the stored instance.
 import numpy as np
 import pytest
 
-from tests.gpu_common import announce, oracle, qi, to_np
+from tests.gpu_common import announce, assert_operator_parity, oracle, qi, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -61,11 +61,7 @@ def test_kml_workload_full_size_operator(storage):
     del inst
     torch.cuda.empty_cache()
     ref = oracle.operator(oracle.Problem(host), x, y)
-    U = to_np(out["U"])
-    assert np.max(np.abs(U - ref["U"])) <= 1e-12 * np.max(np.abs(ref["U"])) * 10
-    np.testing.assert_allclose(to_np(out["g"]), ref["G"][1:], rtol=1e-11, atol=1e-12)
-    np.testing.assert_allclose(to_np(out["grad"]), ref["grad"], rtol=1e-11,
-                               atol=1e-12 * np.max(np.abs(ref["grad"])))
+    assert_operator_parity(host, x, y, out, ref)
 
 
 @pytest.mark.parametrize("storage", ["float64", "bfloat16"])

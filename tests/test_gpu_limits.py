@@ -10,7 +10,7 @@
 import numpy as np
 import pytest
 
-from tests.gpu_common import announce, oracle, qi, tau_bar_of, to_np
+from tests.gpu_common import announce, assert_operator_parity, oracle, qi, tau_bar_of, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -39,12 +39,7 @@ def test_largest_n_operator_parity(storage, spec):
     torch.cuda.empty_cache()
     announce("oracle operator at n=16384")
     ref = oracle.operator(oracle.Problem(host), x, y)
-    U = to_np(out["U"])
-    assert np.max(np.abs(U - ref["U"])) <= 1e-12 * np.max(np.abs(ref["U"])) * 10
-    np.testing.assert_allclose(to_np(out["grad"]), ref["grad"], rtol=1e-11,
-                               atol=1e-12 * np.max(np.abs(ref["grad"])))
-    if m:
-        np.testing.assert_allclose(to_np(out["g"]), ref["G"], rtol=1e-11, atol=1e-12)
+    assert_operator_parity(host, x, y, out, ref)
 
 
 @pytest.mark.parametrize("n,m,p", [(48, 1024, 0), (200, 12, 64)])
