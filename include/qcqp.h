@@ -238,6 +238,23 @@ qcqp_status qcqp_eval_kkt(qcqp_handle *h, const double *x, const double *y, doub
 qcqp_status qcqp_eval_gap(qcqp_handle *h, const double *x, const double *y, double xi,
                           double *out4);
 
+/* Largest n that qcqp_eval_gap_noalloc serves. */
+#define QCQP_NOALLOC_MAX_N 1024
+
+/* qcqp_eval_gap for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels and the
+ * same result, but the G_xi scratch (H = Q(lambda) + 2 xi I as n x n FP64 plus a few
+ * vectors, about 8.1 MiB at the limit) lives in a static device array that the library
+ * holds on each GPU it runs on until the process ends, instead of memory the handle
+ * allocates on its first qcqp_eval_gap.  The call itself allocates nothing.  Arguments,
+ * pointer kinds and out4 as for qcqp_eval_gap.  Errors: QCQP_E_INVALID for n >
+ * QCQP_NOALLOC_MAX_N, a null pointer, xi <= 0 or a handle in a batch; QCQP_E_DEVICE.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (from two
+ * host threads, or on handles whose streams run concurrently) race and must be serialised
+ * by the caller. */
+qcqp_status qcqp_eval_gap_noalloc(qcqp_handle *h, const double *x, const double *y, double xi,
+                                  double *out4);
+
 /* Release all device memory of the handle.  NULL is accepted. */
 qcqp_status qcqp_destroy(qcqp_handle *h);
 

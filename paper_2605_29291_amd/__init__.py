@@ -198,12 +198,14 @@ class Solver:
         return dict(zip(("rel_kkt", "rel_dual", "rel_pri", "rel_comp", "f", "max_violation"),
                         map(float, out)))
 
-    def eval_gap(self, x, y=None, xi=0.04):
+    def eval_gap(self, x, y=None, xi=0.04, noalloc=False):
+        """G_xi at (x, y); noalloc=True calls qcqp_eval_gap_noalloc (n <= abi.NOALLOC_MAX_N)."""
         L = load()
         xk, xp = self._in(x, self.n)
         yk, yp = self._in(y, self.p + self.m)
         out = np.empty(4)
-        abi.check(L.qcqp_eval_gap(self.handle, xp, yp, float(xi), out.ctypes.data))
+        fn = L.qcqp_eval_gap_noalloc if noalloc else L.qcqp_eval_gap
+        abi.check(fn(self.handle, xp, yp, float(xi), out.ctypes.data))
         return dict(G=float(out[0]), Py=float(out[1]), Px=float(out[2]), inner_iters=int(out[3]))
 
     def time_pass(self, reps=20):

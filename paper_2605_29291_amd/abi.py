@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqcqp_hip.so")
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_NOT_CONVERGED, E_NUMERICAL, E_NO_ROOM = range(7)
+NOALLOC_MAX_N = 1024   # QCQP_NOALLOC_MAX_N of include/qcqp.h
 STATUS_NAMES = {0: "ok", 1: "invalid", 2: "nomem", 3: "device", 4: "not_converged",
                 5: "numerical", 6: "no_room"}
 DTYPES = {"float64": 0, "float32": 1, "bfloat16": 2, "float16": 3}
@@ -68,7 +69,8 @@ class Info(C.Structure):
 
 
 SYMBOLS = ["qcqp_options_default", "qcqp_last_error", "qcqp_create", "qcqp_solve",
-           "qcqp_eval_operator", "qcqp_eval_trial_pass", "qcqp_eval_kkt", "qcqp_eval_gap", "qcqp_destroy",
+           "qcqp_eval_operator", "qcqp_eval_trial_pass", "qcqp_eval_kkt", "qcqp_eval_gap",
+           "qcqp_eval_gap_noalloc", "qcqp_destroy",
            "qcqp_batch_create", "qcqp_batch_admit", "qcqp_batch_step", "qcqp_batch_poll",
            "qcqp_batch_fetch", "qcqp_batch_stats", "qcqp_batch_pass_stats", "qcqp_batch_destroy",
            "qcqp_handle_bytes", "qcqp_time_pass"]
@@ -100,6 +102,7 @@ def load(path: str = LIB_PATH):
     L.qcqp_eval_trial_pass.argtypes = [vp, vp, vp, i64, vp]
     L.qcqp_eval_kkt.argtypes = [vp, vp, vp, vp]
     L.qcqp_eval_gap.argtypes = [vp, vp, vp, C.c_double, vp]
+    L.qcqp_eval_gap_noalloc.argtypes = [vp, vp, vp, C.c_double, vp]
     L.qcqp_destroy.argtypes = [vp]
     L.qcqp_batch_create.argtypes = [P(Options), C.c_size_t, i64, P(vp)]
     L.qcqp_batch_admit.argtypes = [vp, vp, vp, vp, P(i64)]

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -172,6 +173,46 @@ std::vector<int> balanced_starts(const std::vector<int64_t> &tile_bytes, int gri
     return st;
 }
 
+}  // namespace
+
+// Doubles of G_xi scratch for dimension n: H (n x ldh, ldh = n rounded up to 16), six vectors
+// of n rounded up to 32, two partial sums per step block and 64 control words.
+constexpr int64_t gap_scratch_doubles(int64_t n)
+{
+    return n * ((n + 15) / 16 * 16) + 6 * ((n + 31) / 32 * 32) + 2 * ((n + STEP_BS - 1) / STEP_BS) + 64;
+}
+
+// ---------------------------------------------------------------------------------------
+// Static scratch of qcqp_eval_gap_noalloc: G_xi scratch for n <= QCQP_NOALLOC_MAX_N, one copy
+// per GPU for the life of the process.  In host code `scratch` names a host-side stand-in, so
+// its device address is looked up once per device (hipGetSymbolAddress, with that device
+// current) and only that address is handed to kernels and copies.
+
+static __device__ __align__(256) double scratch[gap_scratch_doubles(QCQP_NOALLOC_MAX_N)];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_addr[SCRATCH_MAX_DEVICES] = {};
+
+qcqp_status static_scratch_for(int dev, double **out)
+{
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return fail(QCQP_E_DEVICE, "device id %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        int cur = 0;
+        HIPCHK(hipGetDevice(&cur));
+        if (cur != dev) HIPCHK(hipSetDevice(dev));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) HIPCHK(hipSetDevice(cur));
+        if (e != hipSuccess || !p)
+            return fail(QCQP_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_addr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_addr[dev];
+    return QCQP_OK;
+}
 }  // namespace
 
 // ---------------------------------------------------------------------------------------
@@ -1030,17 +1071,10 @@ static qcqp_status eval_point(qcqp_handle *h, const double *x, const double *y)
     return eval_loaded_point(h);
 }
 
-// G_xi at the device point (x_dev, y_dev); out4 = {G, Py, Px, inner iterations}
-static qcqp_status gap_at_device_point(qcqp_handle *h, const double *x_dev, const double *y_dev,
-                                       double xi, double *out4)
+// the handle's own G_xi scratch, (re)allocated when the handle first needs it
+static qcqp_status ensure_gap_mem(qcqp_handle *h)
 {
-    qcqp_status st = load_point(h, x_dev, y_dev, true);
-    if (st) return st;
-    if ((st = eval_loaded_point(h))) return st;
-    HIPCHK(launch_grad(h->stream, h->dslot_eval, (int)h->n, h->d_ueval, h->d_ye, h->d_grad));
-    const int64_t n = h->n, ldh = round_up(n, 16);
-    const int nblk = (int)((n + STEP_BS - 1) / STEP_BS);
-    const size_t need = (size_t)(n * ldh + 6 * round_up(n, 32) + 2 * nblk + 64) * sizeof(double);
+    const size_t need = (size_t)gap_scratch_doubles(h->n) * sizeof(double);
     if (h->gap_bytes < need) {
         if (h->gap_mem) (void)hipFree(h->gap_mem);
         h->gap_mem = nullptr;
@@ -1048,7 +1082,21 @@ static qcqp_status gap_at_device_point(qcqp_handle *h, const double *x_dev, cons
         if (hipMalloc(&h->gap_mem, need) != hipSuccess) return fail(QCQP_E_NOMEM, "G_xi scratch (%zu bytes)", need);
         h->gap_bytes = need;
     }
-    double *H = h->gap_mem;
+    return QCQP_OK;
+}
+
+// G_xi at the device point (x_dev, y_dev) with `mem` (gap_scratch_doubles(n) doubles of device
+// memory) as scratch; out4 = {G, Py, Px, inner iterations}.  Allocates nothing.
+static qcqp_status gap_at_device_point(qcqp_handle *h, const double *x_dev, const double *y_dev,
+                                       double xi, double *mem, double *out4)
+{
+    qcqp_status st = load_point(h, x_dev, y_dev, true);
+    if (st) return st;
+    if ((st = eval_loaded_point(h))) return st;
+    HIPCHK(launch_grad(h->stream, h->dslot_eval, (int)h->n, h->d_ueval, h->d_ye, h->d_grad));
+    const int64_t n = h->n, ldh = round_up(n, 16);
+    const int nblk = (int)((n + STEP_BS - 1) / STEP_BS);
+    double *H = mem;
     double *v0 = H + n * ldh;
     const int64_t vs = round_up(n, 32);
     double *rowabs = v0, *Z = v0 + vs, *D = v0 + 2 * vs, *Dn = v0 + 3 * vs, *Hz = v0 + 4 * vs;
@@ -1152,7 +1200,26 @@ qcqp_status qcqp_eval_gap(qcqp_handle *h, const double *x, const double *y, doub
     HIPCHK(join_streams(h->stream, h->ustream, h->ev_join));
     qcqp_status st = load_point(h, x, y, h->on_device != 0);
     if (st) return st;
-    return gap_at_device_point(h, h->d_xe, h->d_ye, xi, out4);
+    if ((st = ensure_gap_mem(h))) return st;
+    return gap_at_device_point(h, h->d_xe, h->d_ye, xi, h->gap_mem, out4);
+}
+
+qcqp_status qcqp_eval_gap_noalloc(qcqp_handle *h, const double *x, const double *y, double xi,
+                                  double *out4)
+{
+    g_err.clear();
+    if (!h || !x || !out4) return fail(QCQP_E_INVALID, "null argument");
+    if (!(xi > 0.0)) return fail(QCQP_E_INVALID, "xi must be > 0");
+    if (h->owner) return fail(QCQP_E_INVALID, "handle is admitted to a batch");
+    if (h->n > QCQP_NOALLOC_MAX_N)
+        return fail(QCQP_E_INVALID, "qcqp_eval_gap_noalloc: n = %lld exceeds QCQP_NOALLOC_MAX_N = %d",
+                    (long long)h->n, QCQP_NOALLOC_MAX_N);
+    double *mem = nullptr;
+    qcqp_status st = static_scratch_for(h->dev, &mem);
+    if (st) return st;
+    HIPCHK(join_streams(h->stream, h->ustream, h->ev_join));
+    if ((st = load_point(h, x, y, h->on_device != 0))) return st;
+    return gap_at_device_point(h, h->d_xe, h->d_ye, xi, mem, out4);
 }
 
 // adaptive restart: evaluate G_xi at the slot's iterate and let the device decide
@@ -1160,8 +1227,9 @@ static qcqp_status run_gap_for(qcqp_handle *h, Slot *dslot, const Slot &snap, do
 {
     (void)kk;
     double out4[4];
-    qcqp_status st = gap_at_device_point(h, snap.x, snap.y, h->opt.xi, out4);
+    qcqp_status st = ensure_gap_mem(h);
     if (st) return st;
+    if ((st = gap_at_device_point(h, snap.x, snap.y, h->opt.xi, h->gap_mem, out4))) return st;
     *gval = out4[0];
     const int first = snap.k == snap.ada_first ? 1 : 0;
     HIPCHK(launch_restart_decision(h->stream, dslot, out4[0], first));

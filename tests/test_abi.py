@@ -77,3 +77,10 @@ def test_oracle_and_library_share_nothing():
         text = open(os.path.join(ROOT, "paper_2605_29291_amd", f)).read()
         assert "import oracle" not in text and "from oracle" not in text
     assert oracle.lib() is not None
+
+
+def test_noalloc_limit_matches_header():
+    from paper_2605_29291_amd import abi
+    text = open(HEADER).read()
+    m = re.search(r"#define\s+QCQP_NOALLOC_MAX_N\s+(\d+)", text)
+    assert m and int(m.group(1)) == abi.NOALLOC_MAX_N
