@@ -11,9 +11,11 @@ same coupling.  Arrays follow one convention everywhere:
     Q  : (m+1, n, n) float64, Q[0] is the objective (or (m, n, n) with has_q0=False)
     q  : (m+1, n), c : (m+1,), lb/ub : (n,), A : (p, n), b : (p,)
 """
-from .gen import (Instance, random_qcqp, random_qcqp_torch, paper_random_qcqp, random_conic_qcqp,
-                  kml_qcqp, kml_minmax, round_instance, config_seed, serving_trace)
+from .gen import (Instance, random_qcqp, random_qcqp_torch, random_qcqp_exact, stack_sha256,
+                  paper_random_qcqp, random_conic_qcqp, kml_qcqp, kml_minmax, round_instance,
+                  config_seed, serving_trace)
 
-__all__ = ["Instance", "random_qcqp", "random_qcqp_torch", "paper_random_qcqp", "random_conic_qcqp",
+__all__ = ["Instance", "random_qcqp", "random_qcqp_torch", "random_qcqp_exact", "stack_sha256",
+           "paper_random_qcqp", "random_conic_qcqp",
            "kml_qcqp", "kml_minmax",
            "round_instance", "config_seed", "serving_trace"]

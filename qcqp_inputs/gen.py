@@ -107,6 +107,69 @@ def random_qcqp_torch(n: int, m: int, seed: int, shift: float = 0.0, box: float 
     return Instance(n, m, 0, Q, q, c, lb, ub, None, None, True, f"randT_n{n}_m{m}_s{seed}")
 
 
+EXACT_FRAC_BITS = 16   # A entries are multiples of 2^-16 (random_qcqp_exact)
+
+
+def _exact_gaussian(rng, n):
+    """n x n standard normal draws rounded to multiples of 2^-16 and clipped to [-8, 8]: every
+    product of two entries is an integer multiple of 2^-32 below 2^38 of those units, so the
+    n-term sums of A A' stay below 2^53 units for n <= 2^15 and are exact in FP64 in any
+    summation order."""
+    scale = float(2 ** EXACT_FRAC_BITS)
+    return np.clip(np.rint(rng.standard_normal((n, n)) * scale), -8 * scale, 8 * scale) / scale
+
+
+def random_qcqp_exact(n: int, m: int, seed: int, shift: float = 0.0, box: float = 10.0,
+                      device=None) -> Instance:
+    """The random convex QCQP recipe with bitwise-reproducible matrices on any machine.
+
+    A_i is drawn on the host (numpy PCG64) and rounded to multiples of 2^-16, so A_i A_i' is
+    exact in FP64 whatever BLAS or GPU computes it; Q_i = (A_i A_i') / n (one correctly rounded
+    division per entry) + shift I.  With device="cuda" the products run on the GPU (torch), the
+    stack stays there, and the bytes equal the host version's.  q_i ~ N(0, I), c_0 = 0,
+    c_i ~ U(-1, -0.1), X = [-box, box]^n, all host float64.
+    """
+    if n > 2 ** 15:
+        raise ValueError("random_qcqp_exact needs n <= 32768 for exact products")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if device is None:
+        Q = np.empty((m + 1, n, n))
+        for i in range(m + 1):
+            A = _exact_gaussian(rng, n)
+            Qi = (A @ A.T) / float(n)
+            if shift:
+                Qi[np.diag_indices(n)] += shift
+            Q[i] = Qi
+    else:
+        import torch
+        Q = torch.empty((m + 1, n, n), dtype=torch.float64, device=device)
+        # a device tensor divisor keeps the division a true per-element division
+        nt = torch.tensor(float(n), dtype=torch.float64, device=device)
+        for i in range(m + 1):
+            A = torch.from_numpy(_exact_gaussian(rng, n)).to(device)
+            Qi = torch.div(A @ A.T, nt)
+            if shift:
+                Qi.diagonal().add_(shift)
+            Q[i].copy_(Qi)
+            del A, Qi
+    q = rng.standard_normal((m + 1, n))
+    c = np.concatenate([[0.0], rng.uniform(-1.0, -0.1, m)])
+    lb, ub = _box(n, -box, box)
+    return Instance(n, m, 0, Q, q, c, lb, ub, None, None, True, f"randX_n{n}_m{m}_s{seed}")
+
+
+def stack_sha256(Q) -> str:
+    """sha256 of a Q stack's bytes (numpy or torch, any device), matrix by matrix."""
+    import hashlib
+    h = hashlib.sha256()
+    for i in range(Q.shape[0]):
+        Qi = Q[i]
+        if hasattr(Qi, "detach"):
+            Qi = Qi.detach().cpu().numpy()
+        h.update(np.ascontiguousarray(Qi).tobytes())
+    return h.hexdigest()
+
+
 def paper_random_qcqp(n: int = 1000, m: int = 10, seed: int = 0) -> Instance:
     """The random QCQPs of the paper's first experiment (§5.1), drawn afresh (its instances and
     seeds are not published): Q_i = L_i' S_i L_i for i = 0..m with L_i the orthonormal factor of

@@ -9,7 +9,10 @@ needs one pass) on exactly the stored instance.
     parity (U, g, f, grad) at 1e-12;
   * the paper's kernel-learning min-max form, n=4000 (lambda on the simplex, x >= 0, mu = 2),
     FP64 and BF16: oracle natural-residual KKT of the GPU solution <= 1e-6;
-  * serving requests of the full size range, solved together in one batch: oracle KKT <= 1e-6.
+  * serving requests of the full size range, solved together in one batch: oracle KKT <= 1e-6;
+  * the random convex QCQP n=2000, m=100 (bit-identical on host and GPU, checked by hash) against
+    the oracle's own solve stored under tests/golden: objective within 1e-6 (1 + |f*|), with the
+    packed symmetric and the row-major pass.
 """
 import numpy as np
 import pytest
@@ -115,3 +118,40 @@ def test_serving_requests_full_size_range_in_one_batch():
         assert info["status"] == "ok"
         kk = oracle.kkt(oracle.Problem(host), x, y)
         assert kk["rel_kkt"] <= 1e-6, (k, kk)
+
+
+def test_exact_generator_on_the_gpu_equals_the_host_bytes():
+    """random_qcqp_exact gives the same stack on the GPU (torch products) as on the host (numpy):
+    the products are exact and the division by n is one correctly rounded operation."""
+    announce("exact generator: device bytes == host bytes")
+    dev = qi.random_qcqp_exact(300, 3, seed=17, shift=0.01, device="cuda")
+    host = qi.random_qcqp_exact(300, 3, seed=17, shift=0.01)
+    np.testing.assert_array_equal(dev.Q.cpu().numpy(), host.Q)
+    np.testing.assert_array_equal(dev.q, host.q)
+    np.testing.assert_array_equal(dev.c, host.c)
+
+
+@pytest.mark.parametrize("sym_pass", [1, 0])
+def test_random_qcqp_n2000_objective_matches_the_oracle_solution(sym_pass):
+    """The random convex QCQP n = 2000, m = 100 at full size against the oracle's own solve
+    (stored by tests/golden/make_golden.py, relative KKT 5.7e-11): the GPU stops at relative
+    KKT <= 1e-6 with |f - f*| <= 1e-6 (1 + |f*|); ||x - x*|| / (1 + ||x*||) is reported."""
+    import json
+    import os
+    from paper_2605_29291_amd import Solver
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "random_qcqp_n2000_m100.json")))
+    announce(f"n=2000 m=100 objective against the oracle's solution, sym_pass={sym_pass}")
+    inst = qi.random_qcqp_exact(2000, 100, qi.config_seed(2), shift=0.01, device="cuda")
+    assert qi.stack_sha256(inst.Q) == gold["q_stack_sha256"], "not the stored instance"
+    s = Solver(inst, device=True, tau_bar=gold["oracle_options"]["tau_bar"], gamma0=0.1, spec_trials=3,
+               sym_pass=sym_pass)
+    x, y, info = s.solve()
+    s.close()
+    assert info["status"] == "ok" and info["rel_kkt"] <= 1e-6, info
+    fs = gold["f_star"]
+    xs = np.array(gold["x_star"])
+    dx = float(np.linalg.norm(to_np(x) - xs) / (1 + np.linalg.norm(xs)))
+    print(f"[gpu-test] f = {info['f']:.12f}  f* = {fs:.12f}  |f - f*|/(1+|f*|) = "
+          f"{abs(info['f'] - fs) / (1 + abs(fs)):.2e}  ||x - x*||/(1+||x*||) = {dx:.2e}", flush=True)
+    assert abs(info["f"] - fs) <= 1e-6 * (1 + abs(fs))
+    assert dx <= 1e-4

@@ -62,6 +62,7 @@ def test_conversion_from_fp64_rounds_to_nearest_even():
     Q = rng.standard_normal((m + 1, n, n)) * np.exp(rng.uniform(-8, 8, (m + 1, n, n)))
     # include exact ties for bf16: values halfway between two bf16 numbers
     Q[0, 0, :8] = (1.0 + np.arange(8) * 2.0 ** -7) + 2.0 ** -8
+    Q = np.triu(Q) + np.transpose(np.triu(Q, 1), (0, 2, 1))   # the library stores symmetric Q_i
     inst = qi.Instance(n, m, 0, Q, np.zeros((m + 1, n)), np.zeros(m + 1), -np.ones(n), np.ones(n))
     for storage in ("float32", "bfloat16", "float16"):
         announce(f"conversion {storage}")
@@ -105,7 +106,7 @@ def test_operator_config2_full_size():
     the oracle computes every row."""
     import torch
     announce("operator config-2 full size")
-    inst = qi.random_qcqp_torch(2000, 100, qi.config_seed(2), shift=0.01, device="cuda")
+    inst = qi.random_qcqp_exact(2000, 100, qi.config_seed(2), shift=0.01, device="cuda")
     from paper_2605_29291_amd import Solver
     s = Solver(inst, device=True, tau_bar=1.0)
     rng = np.random.default_rng(9)
