@@ -84,8 +84,11 @@ typedef struct {
     int64_t n, m, p;           /* n > 0, m >= 0, 0 <= p < n (rank(A) = p is assumed, not checked) */
     const void *Q;             /* the stored matrices (m + has_q0 of them, or as q_stored lists),
                                   each n rows of ldq elements, row-major, element type Q_dtype,
-                                  in index order (Q_0 first when has_q0).  Must be symmetric:
-                                  the library uses Q_i x = Q_i' x. */
+                                  in index order (Q_0 first when has_q0).  Must be finite
+                                  and symmetric (the library uses Q_i x = Q_i' x): after
+                                  conversion to the storage type, qcqp_create refuses a matrix
+                                  with a non-finite entry or max |Q_rc - Q_cr| > 1e-12 max |Q_rc|
+                                  (QCQP_E_INVALID). */
     qcqp_dtype Q_dtype;        /* element type of the caller's Q */
     int64_t ldq;               /* leading dimension in elements (>= n; 0 means n) */
     int has_q0;                /* 0: Q_0 = 0 and is neither stored nor streamed */

@@ -56,8 +56,10 @@ class _Info(C.Structure):
 def lib():
     global _LIB
     if _LIB is None:
-        path = _build.LIB
-        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+        # ORACLE_LIB names another build of the same source (the sanitizer run of the pins)
+        path = os.environ.get("ORACLE_LIB") or _build.LIB
+        if path == _build.LIB and (not os.path.exists(path) or
+                                   os.path.getmtime(path) < os.path.getmtime(_build.SRC)):
             _build.build()
         L = C.CDLL(path)
         vp = C.c_void_p

@@ -21,6 +21,16 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_sanitized(out_path: str) -> str:
+    """AddressSanitizer + UndefinedBehaviorSanitizer build of the oracle (host code only), for
+    running the CPU pins under the sanitizers; any report aborts the process."""
+    cmd = ["gcc", "-O1", "-g", "-std=c11", "-fPIC", "-shared", "-fno-omit-frame-pointer",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-Wall", "-Wextra", "-Wno-unused-parameter", "-o", out_path, SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out_path
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)

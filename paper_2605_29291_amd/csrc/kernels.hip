@@ -1473,6 +1473,67 @@ __global__ void k_convert(const void *__restrict__ src, int sdt, int64_t lds,
     }
 }
 
+// Symmetry and finiteness of the stored stack (the problem class has symmetric Q_i, and the
+// packed pass reads only upper triangles).  Block (I, J), I <= J, of matrix `mat` compares the
+// 32 x 32 tile (I, J) with the transpose of tile (J, I), staged in LDS, and folds into
+// res[3 mat ..] the maximum |Q_rc - Q_cr|, the maximum |Q_rc| and a non-finite flag.  The two
+// maxima are non-negative doubles, whose bit patterns order like their values, so unsigned
+// atomic maxima over the bits give the same result in any block order.
+constexpr int SC_T = 32;
+
+__global__ void __launch_bounds__(256) k_sym_check(const void *__restrict__ Q, int dt, int64_t ld, int n,
+                                                   int ntile, int nq, unsigned long long *__restrict__ res)
+{
+    __shared__ double tb[SC_T][SC_T + 1];
+    __shared__ double red[2][256 / 64];
+    __shared__ int s_bad;
+    const int I = blockIdx.x / ntile, J = blockIdx.x - I * ntile;
+    if (I > J) return;
+    const int tx = threadIdx.x % SC_T, ty = threadIdx.x / SC_T;
+    const size_t mat_elems = (size_t)n * ld;
+    for (int mat = blockIdx.y; mat < nq; mat += gridDim.y) {
+        if (threadIdx.x == 0) s_bad = 0;
+        // tb[r][c] = Q[J*T + r][I*T + c]
+        for (int r = ty; r < SC_T; r += 256 / SC_T) {
+            const int row = J * SC_T + r, col = I * SC_T + tx;
+            tb[r][tx] = (row < n && col < n) ? load_any(Q, dt, mat * mat_elems + (size_t)row * ld + col) : 0.0;
+        }
+        __syncthreads();
+        double dmax = 0.0, amax = 0.0;
+        bool bad = false;
+        for (int r = ty; r < SC_T; r += 256 / SC_T) {
+            const int row = I * SC_T + r, col = J * SC_T + tx;
+            if (row < n && col < n) {
+                const double a = load_any(Q, dt, mat * mat_elems + (size_t)row * ld + col);
+                const double b = tb[tx][r];          // Q[col][row]
+                bad |= !isfinite(a) || !isfinite(b);
+                dmax = fmax(dmax, fabs(a - b));
+                amax = fmax(amax, fmax(fabs(a), fabs(b)));
+            }
+        }
+        if (bad) s_bad = 1;
+        for (int o = 32; o > 0; o >>= 1) {
+            dmax = fmax(dmax, __shfl_xor(dmax, o));
+            amax = fmax(amax, __shfl_xor(amax, o));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            red[0][threadIdx.x >> 6] = dmax;
+            red[1][threadIdx.x >> 6] = amax;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double d = red[0][0], a = red[1][0];
+            for (int w = 1; w < 256 / 64; ++w) {
+                d = fmax(d, red[0][w]);
+                a = fmax(a, red[1][w]);
+            }
+            atomicMax(res + 3 * mat, (unsigned long long)__builtin_bit_cast(uint64_t, d));
+            atomicMax(res + 3 * mat + 1, (unsigned long long)__builtin_bit_cast(uint64_t, a));
+            if (s_bad) atomicMax(res + 3 * mat + 2, 1ull);
+        }
+        __syncthreads();
+    }
+}
 
 // ---------------------------------------------------------------------------------------
 // smoothed duality gap G_xi(z) (Definition in §4; Euclidean evaluation of the Remark in §4.2)
@@ -1749,6 +1810,15 @@ hipError_t launch_convert(hipStream_t s, const void *src, int src_dtype, int64_t
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
     k_convert<<<(unsigned)blocks, 256, 0, s>>>(src, src_dtype, ld_src, dst, dst_dtype, ld_dst, rows, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_sym_check(hipStream_t s, const void *Q, int dtype, int64_t ld, int n, int nq,
+                            unsigned long long *res)
+{
+    const int ntile = (n + SC_T - 1) / SC_T;
+    const dim3 grid((unsigned)((int64_t)ntile * ntile), (unsigned)(nq < 65535 ? nq : 65535));
+    k_sym_check<<<grid, 256, 0, s>>>(Q, dtype, ld, n, ntile, nq, res);
     return hipGetLastError();
 }
 

@@ -118,6 +118,7 @@ struct Tile {
 // tiles.  One 64-lane block per tile yields the row products Q_IJ w_J and, for I < J, the
 // column products Q_IJ' w_I; a second kernel adds them per output row in a fixed order.
 constexpr int SYM_T = 128;
+constexpr int SYM_TILE_STRIDE = SYM_T * SYM_T;   // doubles from one packed tile to the next
 struct SymPass {
     const double *P;         // nq * ntt packed tiles
     double *ws;              // per tile: row results [B][SYM_T], then column results [B][SYM_T]
@@ -150,6 +151,9 @@ hipError_t launch_kkt(hipStream_t s, const Slot *slot, int n, int ny, const doub
                       double *out6);
 hipError_t launch_convert(hipStream_t s, const void *src, int src_dtype, int64_t ld_src,
                           void *dst, int dst_dtype, int64_t ld_dst, int64_t rows, int64_t n);
+// res: 3 zeroed words per stored matrix {max |Q_rc - Q_cr|, max |Q_rc|} as double bits, non-finite flag
+hipError_t launch_sym_check(hipStream_t s, const void *Q, int dtype, int64_t ld, int n, int nq,
+                            unsigned long long *res);
 hipError_t launch_start(hipStream_t s, Slot *slot);
 hipError_t launch_restart_decision(hipStream_t s, Slot *slot, double gap, int first);
 hipError_t launch_gap_setup(hipStream_t s, const Slot *slot, int n, int ny, const double *y,

@@ -102,6 +102,8 @@ double now_s()
 }
 
 constexpr double CACHE_RESIDENT_BYTES = 256e6;   // Infinity Cache (MALL) of one MI355X
+// largest accepted asymmetry of a stored matrix, relative to its largest entry
+constexpr double SYMMETRY_TOL = 1e-12;
 
 // Lanes per row and rows per tile for a stack of `rows` rows of n elements of type dt.
 // A lane should issue at least one full batch of 8 loads per row, so short rows share a wave
@@ -111,12 +113,9 @@ constexpr double CACHE_RESIDENT_BYTES = 256e6;   // Infinity Cache (MALL) of one
 void tile_shape(int64_t n, int dt, int64_t rows, int *lpr, int *rows_per_tile)
 {
     const int64_t vpr = (n + vec_width(dt) - 1) / vec_width(dt);   // 16-byte vectors per row
-    // lanes per row: the widest group in which each lane still streams `loads` vectors of a row
-    // (tuning overrides: QCQP_PASS_LOADS, QCQP_PASS_MIN_LPR)
-    int loads = 8, min_lpr = 8;
-    if (const char *ev = std::getenv("QCQP_PASS_LOADS")) loads = std::max(1, std::atoi(ev));
-    if (const char *ev = std::getenv("QCQP_PASS_MIN_LPR")) min_lpr = std::min(64, std::max(8, std::atoi(ev)));
-    while (min_lpr & (min_lpr - 1)) min_lpr &= min_lpr - 1;   // a power of two in [8, 64]
+    // lanes per row: the widest group (64 .. 8 lanes) in which each lane still streams `loads`
+    // vectors of a row
+    constexpr int loads = 8, min_lpr = 8;
     int l = min_lpr;
     for (int c = 64; c > min_lpr; c /= 2)
         if (vpr >= (int64_t)loads * c) {
@@ -602,13 +601,44 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
             }
         }
         if (stage) (void)hipFree(stage);
+        // the stored matrices must be finite and symmetric
+        unsigned long long *dchk = nullptr;
+        std::vector<unsigned long long> chk(3 * nq, 0ull);
+        hipError_t e = hipMalloc(&dchk, chk.size() * sizeof(unsigned long long));
+        if (e == hipSuccess) e = hipMemsetAsync(dchk, 0, chk.size() * sizeof(unsigned long long), h->stream);
+        if (e == hipSuccess) e = launch_sym_check(h->stream, h->dQ, h->dtype, h->ld, (int)n, (int)nq, dchk);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(chk.data(), dchk, chk.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (dchk) (void)hipFree(dchk);
+        if (e != hipSuccess) {
+            free_handle_memory(h);
+            delete h;
+            return fail(QCQP_E_DEVICE, "Q symmetry check: %s", hipGetErrorString(e));
+        }
+        for (int64_t i = 0; i < nq; ++i) {
+            const double dmax = __builtin_bit_cast(double, (uint64_t)chk[3 * i]);
+            const double amax = __builtin_bit_cast(double, (uint64_t)chk[3 * i + 1]);
+            if (chk[3 * i + 2]) {
+                free_handle_memory(h);
+                delete h;
+                return fail(QCQP_E_INVALID, "stored matrix %lld of Q has a non-finite entry", (long long)i);
+            }
+            if (dmax > SYMMETRY_TOL * amax) {
+                free_handle_memory(h);
+                delete h;
+                return fail(QCQP_E_INVALID,
+                            "stored matrix %lld of Q is not symmetric: max |Q_rc - Q_cr| = %.3g > %.0e max |Q_rc| = %.3g",
+                            (long long)i, dmax, SYMMETRY_TOL, SYMMETRY_TOL * amax);
+            }
+        }
     }
 
     // ---- options.sym_pass: the packed upper-triangle copy of the stack ----
     if (o.sym_pass && nq > 0) {
         const int32_t NT = (int32_t)((n + SYM_T - 1) / SYM_T);
         const int64_t ntt = (int64_t)NT * (NT + 1) / 2;
-        const size_t pbytes = (size_t)nq * ntt * SYM_T * SYM_T * sizeof(double);
+        const size_t pbytes = (size_t)nq * ntt * SYM_TILE_STRIDE * sizeof(double);
         const size_t wbytes = (size_t)nq * ntt * 2 * h->B * SYM_T * sizeof(double);
         std::vector<int32_t> ub;
         for (int64_t i = 0; i <= m; ++i)
@@ -712,7 +742,6 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
     total += round_up((int64_t)(h->tiles.size() + 2) * sizeof(int), 256);
     h->pass_grid = pass_grid_for(B, h->dtype, (int)h->nw, (double)h->q_bytes);
     h->nt = (double)h->q_bytes > CACHE_RESIDENT_BYTES ? 1 : 0;
-    if (const char *ev = std::getenv("QCQP_PASS_NT")) h->nt = std::atoi(ev) ? 1 : 0;   // tuning override
     if (hipMalloc(&h->arena, total) != hipSuccess) {
         free_handle_memory(h);
         delete h;
@@ -1400,7 +1429,6 @@ static qcqp_status rebuild_tiles(qcqp_batch *bt)
     for (int64_t s2 = 0; s2 < bt->max_slots; ++s2)
         if (bt->handles[s2] && !bt->finished[s2]) resident += bt->handles[s2]->q_bytes;
     bt->nt = (double)resident > CACHE_RESIDENT_BYTES ? 1 : 0;
-    if (const char *ev = std::getenv("QCQP_PASS_NT")) bt->nt = std::atoi(ev) ? 1 : 0;
     if (mixed.size() > bt->tiles_cap) {
         if (bt->dtiles) (void)hipFree(bt->dtiles);
         bt->dtiles = nullptr;
