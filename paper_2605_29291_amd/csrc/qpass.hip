@@ -7,6 +7,8 @@
 // Conic Constrained Convex Optimization" (arXiv 2605.29291), eq. (qcqp-coupling) in §2.1.
 #include "qcqp_device.h"
 
+#include <type_traits>
+
 namespace qcqp {
 
 // ---------------------------------------------------------------------------------------
@@ -84,22 +86,9 @@ template <> struct Store<DT_F16> {
 // reads are 2-4 LDS bytes per streamed byte).  For FP64, R = 2 keeps 16 loads per lane in
 // flight, which large n needs: the staged trial points then fill the LDS with one block per CU
 // (n = 10000: 5.6 -> 6.35 TB/s measured, no loss at n = 2000 or 4000).
-#ifndef QCQP_PASS_R16
-#define QCQP_PASS_R16 4
-#endif
-#ifndef QCQP_PASS_UNR16
-#define QCQP_PASS_UNR16 4
-#endif
-#ifndef QCQP_PASS_R64
-#define QCQP_PASS_R64 2
-#endif
-#ifndef QCQP_PASS_UNR64
-#define QCQP_PASS_UNR64 8
-#endif
-
 template <int DT> struct PassShape {
-    static constexpr int R = DT == DT_F64 ? QCQP_PASS_R64 : QCQP_PASS_R16;
-    static constexpr int UNR = DT == DT_F64 ? QCQP_PASS_UNR64 : QCQP_PASS_UNR16;
+    static constexpr int R = DT == DT_F64 ? 2 : 4;
+    static constexpr int UNR = DT == DT_F64 ? 8 : 4;
 };
 
 template <int DT, typename AT, int B, int LPR, bool NT, int R, int UNR>
@@ -427,11 +416,17 @@ __global__ void __launch_bounds__(256) k_sym_pack(const double *__restrict__ Q, 
     const int s = t / sp.ntt;
     int I, J;
     sym_tile_ij(t - s * sp.ntt, sp.NT, I, J);
-    double *dst = P + (size_t)t * SYM_T * SYM_T;
+    double *dst = P + (size_t)t * SYM_TILE_STRIDE;
     const double *src = Q + (size_t)s * sp.n * ld;
+    // a diagonal tile keeps its upper triangle with half the diagonal: its row dots then give
+    // sum_{c >= r} and its column dots sum_{c < r} of (Q_II w)_r, each diagonal entry half in
+    // each (halving is exact)
     for (int e = threadIdx.x; e < SYM_T * SYM_T; e += 256) {
-        const int gr = I * SYM_T + e / SYM_T, gc = J * SYM_T + e % SYM_T;
-        dst[e] = (gr < sp.n && gc < sp.n) ? src[(size_t)gr * ld + gc] : 0.0;
+        const int r = e / SYM_T, c = e % SYM_T;
+        const int gr = I * SYM_T + r, gc = J * SYM_T + c;
+        double v = (gr < sp.n && gc < sp.n) ? src[(size_t)gr * ld + gc] : 0.0;
+        if (I == J) v = c > r ? v : (c == r ? 0.5 * v : 0.0);
+        dst[e] = v;
     }
 }
 
@@ -442,12 +437,18 @@ hipError_t launch_sym_pack(hipStream_t s, const double *Q, int64_t ld, const Sym
     return hipGetLastError();
 }
 
-// One tile by one 64-lane wave: lane l holds columns 2l, 2l+1 of every row.  Row dots are
-// summed over the 64 lanes eight rows at a time by a transposing reduction (three exchange
-// steps that halve the rows each lane keeps, then three butterfly steps); the column dots
-// stay in the lane's registers over all rows.  Lane l also holds w_I at rows 2l, 2l+1, and
-// each row's value is broadcast from there with readlane.  The next eight rows' loads are in
-// flight while the current eight are reduced.
+// One tile by one 64-lane wave: lane l holds columns 2l, 2l+1 of every row (one 16-byte
+// non-temporal buffer load per row).  The loads run WIN rows ahead of the arithmetic in a
+// rolling window: a group's registers are refilled with the rows WIN further down as soon as
+// the group is consumed, so about WIN KB of the tile stay in flight per wave.  The row loop is
+// unrolled at compile time so every window slot stays in one register (a rolled loop would
+// copy the slots at its back edge and wait there for all loads in flight).
+// Row dots are summed over the 64 lanes four rows at a time by a transposing reduction (two
+// half-swapping steps with the gfx950 permlane swaps, then four rotations inside 16-lane rows
+// with DPP: VALU only) and parked in LDS; the column dots stay in the lane's registers over all
+// rows.  Lane l holds w_I at rows 2l, 2l+1, and each row's value is broadcast with readlane.
+// A diagonal tile is stored as its upper triangle with half the diagonal (k_sym_pack), so it
+// runs the same code; lanes whose 16 bytes lie wholly below the diagonal fetch nothing.
 
 // the value v of lane `src` (uniform) in every lane
 __device__ __forceinline__ double lane_bcast(double v, int src)
@@ -457,26 +458,108 @@ __device__ __forceinline__ double lane_bcast(double v, int src)
     return __hiloint2double(hi, lo);
 }
 
+// Cross-lane steps on doubles, VALU only (no LDS): exchange halves of the wave with the
+// gfx950 permlane swaps, and rotate within 16-lane rows with DPP.
+__device__ __forceinline__ void swap32(double &a, double &b)
+{
+    // lanes 32..63 of a <-> lanes 0..31 of b
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(a), (unsigned)__double2loint(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(a), (unsigned)__double2hiint(b), false, false);
+    a = __hiloint2double((int)hi[0], (int)lo[0]);
+    b = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+__device__ __forceinline__ void swap16(double &a, double &b)
+{
+    // lanes 16..31 (48..63) of a <-> lanes 0..15 (32..47) of b
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(a), (unsigned)__double2loint(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(a), (unsigned)__double2hiint(b), false, false);
+    a = __hiloint2double((int)hi[0], (int)lo[0]);
+    b = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+// v of lane (i + K) mod 16 within the lane's 16-lane row
+template <int K>
+__device__ __forceinline__ double row_ror(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x120 + K, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x120 + K, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// p[k] holds each lane's share of row k (k = 0..3); returns in every lane of 16-lane row q the
+// sum over all 64 lanes of row q, in a fixed order
+__device__ __forceinline__ double reduce4(double p0, double p1, double p2, double p3)
+{
+    swap32(p0, p2);                 // lanes 0..31: row 0 (1), lanes 32..63: row 2 (3)
+    swap32(p1, p3);
+    double s0 = p0 + p2, s1 = p1 + p3;
+    swap16(s0, s1);                 // 16-lane row q now holds shares of tile row q
+    double t = s0 + s1;
+    t += row_ror<8>(t);
+    t += row_ror<4>(t);
+    t += row_ror<2>(t);
+    t += row_ror<1>(t);
+    return t;
+}
+
+constexpr int SYM_WIN = 16;   // rows in flight per wave
+constexpr int SYM_GRP = 4;    // rows per transposing reduction
+constexpr int SYM_WAVES = 3;  // register budget: waves per SIMD
+
+// A buffer resource over the first `bytes` bytes of a tile: loads beyond it return zero without
+// touching memory, so every load can be issued unconditionally (which keeps the in-order count
+// of outstanding loads exact) and masked entries are fetched from nowhere.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const void *base, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, bytes, 0x00020000);
+}
+
+constexpr int BUF_NT = 2;              // cache policy of the tile loads: non-temporal
+constexpr int OFF_NONE = 0x40000000;   // a byte offset past every tile (load returns zero)
+
+// Calls f(integral_constant<int, G>) for G = G0, G0 + 1, ... while G < GN and G * SYM_GRP < rows:
+// a row loop unrolled at compile time, so that every window slot is a fixed register.
+template <int G0, int GN>
+struct GroupLoop {
+    template <typename F>
+    __device__ __forceinline__ static void run(F &&f, int rows)
+    {
+        if constexpr (G0 < GN) {
+            if (G0 * SYM_GRP < rows) {
+                f(std::integral_constant<int, G0>{});
+                GroupLoop<G0 + 1, GN>::run(f, rows);
+            }
+        }
+    }
+};
+
 template <int NB>
 __device__ __forceinline__ void sym_tile(const double *__restrict__ q, int n, int I, int J,
                                          const double *const (&w)[NB], double *__restrict__ rp,
-                                         double *__restrict__ cp, bool diag)
+                                         double *__restrict__ cp, double (*__restrict__ rbuf)[SYM_T])
 {
     using T = Store<DT_F64>;
+    constexpr int NSLOT = SYM_WIN / SYM_GRP;     // groups in flight
     const int lane = threadIdx.x & 63;
     const int c = 2 * lane;
     const int gc = J * SYM_T + c;
     const int gi = I * SYM_T + c;
     const bool cval = gc < n;
     const int rmax = min(SYM_T, n - I * SYM_T);
-    auto load8 = [&](int r0, u32x4 (&v)[8]) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-            v[i] = (r0 + i < rmax && cval) ? ld16<true>(q, ((size_t)(r0 + i) * SYM_T + c) * 8)
-                                           : u32x4{0u, 0u, 0u, 0u};
+    // rows past rmax lie outside the resource; columns past n take an offset outside it
+    const __amdgpu_buffer_rsrc_t rs = tile_rsrc(q, rmax * SYM_T * 8);
+    const int voff = cval ? c * 8 : OFF_NONE;
+    const int dmask = I == J ? OFF_NONE : 0;
+    // row r; on the diagonal tile a lane whose two columns both lie below the diagonal
+    // (c + 1 < r) reads nothing (the packed tile holds zeros there)
+    auto load = [&](int r) -> u32x4 {
+        const int vo = voff | (dmask & ((c + 1 - r) >> 31));
+        return __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, vo, r * SYM_T * 8, BUF_NT));
     };
-    u32x4 v[8];
-    load8(0, v);
+    u32x4 v[SYM_WIN];
+#pragma unroll
+    for (int i = 0; i < SYM_WIN; ++i) v[i] = load(i);
     double xj0[NB], xj1[NB], xi0[NB], xi1[NB], ca0[NB], ca1[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -487,86 +570,76 @@ __device__ __forceinline__ void sym_tile(const double *__restrict__ q, int n, in
         ca0[b] = 0.0;
         ca1[b] = 0.0;
     }
-    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
-    for (int r0 = 0; r0 < rmax; r0 += 8) {
-        u32x4 vn[8];
-        if (r0 + 8 < rmax) load8(r0 + 8, vn);
-        double rp8[8][NB];
+    GroupLoop<0, SYM_T / SYM_GRP>::run(
+        [&](auto gconst) {
+            constexpr int G = decltype(gconst)::value;
+            constexpr int s0 = (G % NSLOT) * SYM_GRP;   // the group's window slots
+            constexpr int r0 = G * SYM_GRP;
+            // keep each group's broadcasts and partial sums together (bounded register use)
+            __builtin_amdgcn_sched_barrier(0);
+            double rp4[SYM_GRP][NB];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const double q0 = T::get(v[i], 0), q1 = T::get(v[i], 1);
+            for (int i = 0; i < SYM_GRP; ++i) {
+                const double q0 = T::get(v[s0 + i], 0), q1 = T::get(v[s0 + i], 1);
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                rp8[i][b] = fma(q1, xj1[b], q0 * xj0[b]);
-                if (!diag) {
-                    // rows r0 + i = 2 k + e live in lane k, element e (zero past n)
+                for (int b = 0; b < NB; ++b) {
+                    rp4[i][b] = fma(q1, xj1[b], q0 * xj0[b]);
+                    // rows r = 2 k + e live in lane k, element e (zero past n)
                     const double xv = lane_bcast((i & 1) ? xi1[b] : xi0[b], (r0 + i) >> 1);
                     ca0[b] = fma(q0, xv, ca0[b]);
                     ca1[b] = fma(q1, xv, ca1[b]);
                 }
             }
-        }
+            __builtin_amdgcn_sched_barrier(0);
+            // the group's rows are consumed: refill its slots with the rows WIN further down
+            if constexpr (r0 + SYM_WIN < SYM_T) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            double v4[4], v2[2];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const double send = b5 ? rp8[k][b] : rp8[4 + k][b];
-                const double keep = b5 ? rp8[4 + k][b] : rp8[k][b];
-                v4[k] = keep + __shfl_xor(send, 32, 64);
+                for (int i = 0; i < SYM_GRP; ++i) v[s0 + i] = load(r0 + SYM_WIN + i);
             }
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const double send = b4 ? v4[k] : v4[2 + k];
-                const double keep = b4 ? v4[2 + k] : v4[k];
-                v2[k] = keep + __shfl_xor(send, 16, 64);
+            for (int b = 0; b < NB; ++b) {
+                const double t = reduce4(rp4[0][b], rp4[1][b], rp4[2][b], rp4[3][b]);
+                if ((lane & 15) == 0) rbuf[b][r0 + (lane >> 4)] = t;
             }
-            const double send = b3 ? v2[0] : v2[1];
-            const double keep = b3 ? v2[1] : v2[0];
-            double v1 = keep + __shfl_xor(send, 8, 64);
-            v1 += __shfl_xor(v1, 4, 64);
-            v1 += __shfl_xor(v1, 2, 64);
-            v1 += __shfl_xor(v1, 1, 64);
-            const int row = r0 + (b5 ? 4 : 0) + (b4 ? 2 : 0) + (b3 ? 1 : 0);
-            if ((lane & 7) == 0 && row < rmax) rp[b * SYM_T + row] = v1;
-        }
+        },
+        rmax);
+    __builtin_amdgcn_sched_barrier(0);
+    // coalesced stores (a wave's LDS accesses complete in order, so the reads see the writes)
 #pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = vn[i];
-    }
-    if (!diag) {
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            if (cval) cp[b * SYM_T + c] = ca0[b];
-            if (gc + 1 < n) cp[b * SYM_T + c + 1] = ca1[b];
-        }
+    for (int b = 0; b < NB; ++b) {
+        for (int r = lane; r < rmax; r += 64) rp[b * SYM_T + r] = rbuf[b][r];
+        if (cval) cp[b * SYM_T + c] = ca0[b];
+        if (gc + 1 < n) cp[b * SYM_T + c + 1] = ca1[b];
     }
 }
 
 template <int B>
-__global__ void __launch_bounds__(64, B <= 2 ? 4 : 3) k_spass(Slot *__restrict__ slots, SymPass sp)
+__global__ void __launch_bounds__(64, SYM_WAVES) k_spass(Slot *__restrict__ slots, SymPass sp)
 {
+    __shared__ double rbuf[B][SYM_T];
     Slot *S = slots;
     if (S->status != ST_RUNNING) return;
     const int t = blockIdx.x;
     const int s = t / sp.ntt;
     int I, J;
     sym_tile_ij(t - s * sp.ntt, sp.NT, I, J);
-    const double *q = sp.P + (size_t)t * SYM_T * SYM_T;
+    const double *q = sp.P + (size_t)t * SYM_TILE_STRIDE;
     double *rp = sp.ws + (size_t)t * 2 * sp.B * SYM_T;
     double *cp = rp + (size_t)sp.B * SYM_T;
     if (S->mode == MODE_ANCHOR) {
         const double *const w1[1] = {S->x};
-        sym_tile<1>(q, sp.n, I, J, w1, rp, cp, I == J);
+        sym_tile<1>(q, sp.n, I, J, w1, rp, cp, rbuf);
     } else {
         const double *wb[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) wb[b] = S->xc[b];
-        sym_tile<B>(q, sp.n, I, J, wb, rp, cp, I == J);
+        sym_tile<B>(q, sp.n, I, J, wb, rp, cp, rbuf);
     }
 }
 
 // (Q_s w)_r for the rows of tile row I: the row results of tiles (I, J >= I), then the column
-// results of tiles (K < I, I), in that order
+// results of tiles (K <= I, I) (the diagonal tile's column results carry its entries below
+// the diagonal), in that order
 template <int B>
 __global__ void __launch_bounds__(SYM_T) k_sred(Slot *__restrict__ slots, SymPass sp)
 {
@@ -579,9 +652,9 @@ __global__ void __launch_bounds__(SYM_T) k_sred(Slot *__restrict__ slots, SymPas
     const int nb = anchor ? 1 : B;
     const size_t stride = (size_t)2 * sp.B * SYM_T;
     const size_t ob = (size_t)sp.ubase[s] + gr;
-    // the terms in the order (J = I .. NT-1 row results, then K = 0 .. I-1 column results),
-    // loaded eight at a time so that the loads are in flight together
-    const int nterm = sp.NT;
+    // terms k = 0 .. NT - I - 1: row result of (I, I + k); k = NT - I .. NT: column result of
+    // (k - (NT - I), I); loaded eight at a time so that the loads are in flight together
+    const int nrow = sp.NT - I, nterm = sp.NT + 1;
     for (int b = 0; b < nb; ++b) {
         double v = 0.0;
         for (int k0 = 0; k0 < nterm; k0 += 8) {
@@ -591,10 +664,9 @@ __global__ void __launch_bounds__(SYM_T) k_sred(Slot *__restrict__ slots, SymPas
                 const int k = k0 + u;
                 t[u] = 0.0;
                 if (k < nterm) {
-                    const int J = I + k;
-                    t[u] = J < sp.NT
-                               ? sp.ws[(size_t)sym_tile_index(s, I, J, sp.NT, sp.ntt) * stride + b * SYM_T + rr]
-                               : sp.ws[(size_t)sym_tile_index(s, J - sp.NT, I, sp.NT, sp.ntt) * stride +
+                    t[u] = k < nrow
+                               ? sp.ws[(size_t)sym_tile_index(s, I, I + k, sp.NT, sp.ntt) * stride + b * SYM_T + rr]
+                               : sp.ws[(size_t)sym_tile_index(s, k - nrow, I, sp.NT, sp.ntt) * stride +
                                        (size_t)(sp.B + b) * SYM_T + rr];
                 }
             }

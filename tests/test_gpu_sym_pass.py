@@ -7,9 +7,9 @@ The packed stack holds only the upper-triangle 128 x 128 tiles of every Q_i; the
   the sum of its terms' magnitudes, for n a
   multiple of 128, one past it, ragged, a single tile, with an equality block, without Q_0 and
   with affine constraints that store no matrix;
-* trajectories: the same iterates as the oracle's (rtol 1e-10) for K iterations with two and
-  three speculative candidates, and the row-major pass's iterates within the same bar; the
-  APDB-xy routine as well;
+* trajectories: the same iterates as the oracle's (rtol 1e-10) for K iterations with two to
+  four speculative candidates, and the row-major pass's iterates within the same bar; at
+  n = 1100 (nine tile rows); the APDB-xy routine as well;
 * final solutions: relative KKT <= 1e-6 evaluated by the oracle; two solves bitwise equal;
 * the random convex QCQP n = 2000, m = 100 (the config-2 workload): converged, relative KKT of
   the returned point by the oracle's evaluation <= 1e-6;
@@ -61,7 +61,7 @@ def test_sym_operator_without_q0_and_with_unstored_matrices():
     _operator_parity(sparse, seed=1)
 
 
-@pytest.mark.parametrize("spec", [2, 3])
+@pytest.mark.parametrize("spec", [2, 3, 4])
 def test_sym_trajectory_matches_oracle_and_row_major(spec):
     inst = qi.random_qcqp(300, 8, seed=41, shift=0.01)
     tb = tau_bar_of(inst)
@@ -75,6 +75,22 @@ def test_sym_trajectory_matches_oracle_and_row_major(spec):
     np.testing.assert_allclose(to_np(xs), ref["x"], rtol=1e-10, atol=1e-11)
     np.testing.assert_allclose(to_np(ys), ref["y"], rtol=1e-10, atol=1e-11)
     np.testing.assert_allclose(to_np(xs), to_np(xr), rtol=1e-10, atol=1e-11)
+
+
+@pytest.mark.parametrize("spec", [2, 4])
+def test_sym_trajectory_many_tile_rows(spec):
+    """n = 1100: nine tile rows, so the per-row sums of the tile results take more than one
+    chunk of eight terms, with several candidates per pass."""
+    inst = qi.random_qcqp(1100, 3, seed=48, shift=0.01)
+    tb = tau_bar_of(inst)
+    K = 20
+    kw = dict(tau_bar=tb, gamma0=0.1, max_iter=K, tol=0.0)
+    announce(f"sym trajectory n=1100 spec={spec}")
+    ref = oracle.solve(oracle.Problem(inst), oracle.Options(**kw))
+    x, y, info = _solver(inst, spec_trials=spec, sym_pass=1, **kw).solve()
+    assert info["iters"] == K and info["trials"] == ref["info"]["trials"]
+    np.testing.assert_allclose(to_np(x), ref["x"], rtol=1e-10, atol=1e-11)
+    np.testing.assert_allclose(to_np(y), ref["y"], rtol=1e-10, atol=1e-11)
 
 
 def test_sym_xy_trajectory_matches_oracle():
@@ -114,7 +130,7 @@ def test_sym_full_size_random_qcqp():
     import torch
     n, m = 2000, 100
     announce("sym full size n=2000 m=100")
-    inst = qi.random_qcqp_torch(n, m, qi.config_seed(2), shift=0.01, device="cuda")
+    inst = qi.random_qcqp_exact(n, m, qi.config_seed(2), shift=0.01, device="cuda")
     L0 = float(torch.linalg.matrix_norm(inst.Q[0], ord=2))
     s = _solver(inst, device=True, tau_bar=1.0 / L0, gamma0=0.1, spec_trials=3, sym_pass=1)
     x, y, info = s.solve()
