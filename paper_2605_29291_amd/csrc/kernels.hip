@@ -1475,11 +1475,26 @@ __global__ void k_convert(const void *__restrict__ src, int sdt, int64_t lds,
 
 // Symmetry and finiteness of the stored stack (the problem class has symmetric Q_i, and the
 // packed pass reads only upper triangles).  Block (I, J), I <= J, of matrix `mat` compares the
-// 32 x 32 tile (I, J) with the transpose of tile (J, I), staged in LDS, and folds into
+// 64 x 64 tile (I, J) with the transpose of tile (J, I), staged in LDS; both tiles are read as
+// 16-byte vectors (stored rows are 16-byte aligned and padded with zeros).  It folds into
 // res[3 mat ..] the maximum |Q_rc - Q_cr|, the maximum |Q_rc| and a non-finite flag.  The two
 // maxima are non-negative doubles, whose bit patterns order like their values, so unsigned
 // atomic maxima over the bits give the same result in any block order.
-constexpr int SC_T = 32;
+constexpr int SC_T = 64;
+
+__device__ __forceinline__ double vec_elem(const uint4 &v, int dt, int e)
+{
+    if (dt == DT_F64) {
+        const unsigned lo = e == 0 ? v.x : v.z, hi = e == 0 ? v.y : v.w;
+        return __hiloint2double((int)hi, (int)lo);
+    }
+    const unsigned w = dt == DT_F32 ? (e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w)
+                                    : ((e >> 1) == 0 ? v.x : (e >> 1) == 1 ? v.y : (e >> 1) == 2 ? v.z : v.w);
+    if (dt == DT_F32) return (double)__uint_as_float(w);
+    const uint16_t h = (e & 1) ? (uint16_t)(w >> 16) : (uint16_t)(w & 0xffffu);
+    if (dt == DT_BF16) return (double)__uint_as_float((uint32_t)h << 16);
+    return (double)(float)__builtin_bit_cast(_Float16, h);
+}
 
 __global__ void __launch_bounds__(256) k_sym_check(const void *__restrict__ Q, int dt, int64_t ld, int n,
                                                    int ntile, int nq, unsigned long long *__restrict__ res)
@@ -1489,26 +1504,37 @@ __global__ void __launch_bounds__(256) k_sym_check(const void *__restrict__ Q, i
     __shared__ int s_bad;
     const int I = blockIdx.x / ntile, J = blockIdx.x - I * ntile;
     if (I > J) return;
-    const int tx = threadIdx.x % SC_T, ty = threadIdx.x / SC_T;
-    const size_t mat_elems = (size_t)n * ld;
+    const int es = dt == DT_F64 ? 8 : (dt == DT_F32 ? 4 : 2);
+    const int V = 16 / es;                    // elements per 16-byte vector
+    const int vpr = SC_T / V;                 // vectors per tile row
+    const int nvec = SC_T * vpr;
+    const size_t mat_bytes = (size_t)n * ld * es;
     for (int mat = blockIdx.y; mat < nq; mat += gridDim.y) {
+        const char *base = (const char *)Q + mat * mat_bytes;
         if (threadIdx.x == 0) s_bad = 0;
         // tb[r][c] = Q[J*T + r][I*T + c]
-        for (int r = ty; r < SC_T; r += 256 / SC_T) {
-            const int row = J * SC_T + r, col = I * SC_T + tx;
-            tb[r][tx] = (row < n && col < n) ? load_any(Q, dt, mat * mat_elems + (size_t)row * ld + col) : 0.0;
+        for (int k = threadIdx.x; k < nvec; k += 256) {
+            const int r = k / vpr, c0 = (k - r * vpr) * V;
+            const int row = J * SC_T + r, col = I * SC_T + c0;
+            uint4 v = {0u, 0u, 0u, 0u};
+            if (row < n && col < ld) v = *(const uint4 *)(base + ((size_t)row * ld + col) * es);
+            for (int e = 0; e < V; ++e) tb[r][c0 + e] = vec_elem(v, dt, e);
         }
         __syncthreads();
         double dmax = 0.0, amax = 0.0;
         bool bad = false;
-        for (int r = ty; r < SC_T; r += 256 / SC_T) {
-            const int row = I * SC_T + r, col = J * SC_T + tx;
-            if (row < n && col < n) {
-                const double a = load_any(Q, dt, mat * mat_elems + (size_t)row * ld + col);
-                const double b = tb[tx][r];          // Q[col][row]
-                bad |= !isfinite(a) || !isfinite(b);
-                dmax = fmax(dmax, fabs(a - b));
-                amax = fmax(amax, fmax(fabs(a), fabs(b)));
+        for (int k = threadIdx.x; k < nvec; k += 256) {
+            const int r = k / vpr, c0 = (k - r * vpr) * V;
+            const int row = I * SC_T + r, col = J * SC_T + c0;
+            if (row < n && col < ld) {
+                const uint4 v = *(const uint4 *)(base + ((size_t)row * ld + col) * es);
+                for (int e = 0; e < V; ++e) {
+                    const double a = vec_elem(v, dt, e);
+                    const double b = tb[c0 + e][r];          // Q[col + e][row]
+                    bad |= !isfinite(a) || !isfinite(b);
+                    dmax = fmax(dmax, fabs(a - b));
+                    amax = fmax(amax, fmax(fabs(a), fabs(b)));
+                }
             }
         }
         if (bad) s_bad = 1;
@@ -1819,6 +1845,44 @@ hipError_t launch_sym_check(hipStream_t s, const void *Q, int dtype, int64_t ld,
     const int ntile = (n + SC_T - 1) / SC_T;
     const dim3 grid((unsigned)((int64_t)ntile * ntile), (unsigned)(nq < 65535 ? nq : 65535));
     k_sym_check<<<grid, 256, 0, s>>>(Q, dtype, ld, n, ntile, nq, res);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_fill(double *__restrict__ v, int64_t n, double value)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) v[i] = value;
+}
+
+hipError_t launch_fill(hipStream_t s, double *v, int64_t n, double value)
+{
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    k_fill<<<(unsigned)blocks, 256, 0, s>>>(v, n, value);
+    return hipGetLastError();
+}
+
+// lam = ||z|| (fixed-order block sum), v = z / lam
+__global__ void __launch_bounds__(STEP_BS) k_pow_normalize(const double *__restrict__ z, int n,
+                                                           double *__restrict__ v, double *__restrict__ lam)
+{
+    double acc[1] = {0.0};
+    for (int j = threadIdx.x; j < n; j += STEP_BS) acc[0] += z[j] * z[j];
+    block_sum<1>(acc);
+    __shared__ double s_l;
+    if (threadIdx.x == 0) {
+        s_l = sqrt(acc[0]);
+        lam[0] = s_l;
+    }
+    __syncthreads();
+    const double l = s_l;
+    if (l > 0.0)
+        for (int j = threadIdx.x; j < n; j += STEP_BS) v[j] = z[j] / l;
+}
+
+hipError_t launch_pow_normalize(hipStream_t s, const double *z, int n, double *v, double *lam)
+{
+    k_pow_normalize<<<1, STEP_BS, 0, s>>>(z, n, v, lam);
     return hipGetLastError();
 }
 

@@ -154,6 +154,10 @@ hipError_t launch_convert(hipStream_t s, const void *src, int src_dtype, int64_t
 // res: 3 zeroed words per stored matrix {max |Q_rc - Q_cr|, max |Q_rc|} as double bits, non-finite flag
 hipError_t launch_sym_check(hipStream_t s, const void *Q, int dtype, int64_t ld, int n, int nq,
                             unsigned long long *res);
+// v[0..n) = value
+hipError_t launch_fill(hipStream_t s, double *v, int64_t n, double value);
+// one power-iteration normalisation: lam[0] = ||z||, v = z / ||z|| (v unchanged when z = 0)
+hipError_t launch_pow_normalize(hipStream_t s, const double *z, int n, double *v, double *lam);
 hipError_t launch_start(hipStream_t s, Slot *slot);
 hipError_t launch_restart_decision(hipStream_t s, Slot *slot, double gap, int first);
 hipError_t launch_gap_setup(hipStream_t s, const Slot *slot, int n, int ny, const double *y,

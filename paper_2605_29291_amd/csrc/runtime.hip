@@ -399,27 +399,21 @@ static void free_handle_memory(qcqp_handle *h)
     h->h_out = nullptr;
 }
 
-// largest eigenvalue estimate of stored matrix `mat` by power iteration from 1/sqrt(n)
+// largest eigenvalue estimate of stored matrix `mat` by 30 power iterations from 1/sqrt(n),
+// all on the device (the normalisation is a one-block kernel); one synchronisation at the end
 static qcqp_status power_norm(qcqp_handle *h, int mat, double *out)
 {
     const int64_t n = h->n;
     double *v = h->d_xe, *z = h->d_grad;
-    std::vector<double> hv(n, 1.0 / std::sqrt((double)n)), hz(n);
-    HIPCHK(hipMemcpyAsync(v, hv.data(), n * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    double lam = 0.0;
+    HIPCHK(launch_fill(h->stream, v, n, 1.0 / std::sqrt((double)n)));
     for (int it = 0; it < 30; ++it) {
         HIPCHK(launch_matvec1(h->stream, h->dQ, h->dtype, (int)n, (int)h->ld, (int)(mat * n), v,
                               (int)h->nw, z));
-        HIPCHK(hipMemcpyAsync(hz.data(), z, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipStreamSynchronize(h->stream));
-        double s = 0.0;
-        for (int64_t j = 0; j < n; ++j) s += hz[j] * hz[j];
-        lam = std::sqrt(s);
-        if (!(lam > 0.0)) break;
-        for (int64_t j = 0; j < n; ++j) hv[j] = hz[j] / lam;
-        HIPCHK(hipMemcpyAsync(v, hv.data(), n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(launch_pow_normalize(h->stream, z, (int)n, v, h->d_out6));
     }
-    *out = lam;
+    HIPCHK(hipMemcpyAsync(h->h_out, h->d_out6, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    *out = h->h_out[0];
     return QCQP_OK;
 }
 
@@ -566,14 +560,31 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
         }
     }
     h->q_bytes = (size_t)nq * n * h->ld * es;
+    // three words per stored matrix for the symmetry check, after the stack
+    const size_t chk_bytes = (size_t)round_up(3 * nq * (int64_t)sizeof(unsigned long long), 256);
     if (nq > 0) {
-        if (hipMalloc(&h->dQ, h->q_bytes) != hipSuccess) {
+        if (hipMalloc(&h->dQ, h->q_bytes + chk_bytes) != hipSuccess) {
             delete h;
             return fail(QCQP_E_NOMEM, "Q stack (%zu bytes)", h->q_bytes);
         }
         const int sdt = (int)P->Q_dtype;
         const size_t smat = (size_t)n * ldq * elem_size(sdt);
         void *stage = nullptr;
+        if (sdt == h->dtype) {
+            // same element type: one pitched copy of the whole stack (the stored rows are
+            // padded to ld), and the padding columns cleared
+            hipError_t e = hipMemcpy2DAsync(h->dQ, (size_t)h->ld * es, P->Q, (size_t)ldq * es, (size_t)n * es,
+                                            (size_t)nq * n, h->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                            h->stream);
+            if (e == hipSuccess && h->ld > n)
+                e = hipMemset2DAsync((char *)h->dQ + (size_t)n * es, (size_t)h->ld * es, 0, (size_t)(h->ld - n) * es,
+                                     (size_t)nq * n, h->stream);
+            if (e != hipSuccess) {
+                free_handle_memory(h);
+                delete h;
+                return fail(QCQP_E_DEVICE, "Q upload: %s", hipGetErrorString(e));
+            }
+        } else {
         if (!h->on_device) {
             if (hipMalloc(&stage, smat) != hipSuccess) {
                 free_handle_memory(h);
@@ -600,17 +611,16 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
                 return fail(QCQP_E_DEVICE, "Q upload/convert: %s", hipGetErrorString(e));
             }
         }
+        }
         if (stage) (void)hipFree(stage);
         // the stored matrices must be finite and symmetric
-        unsigned long long *dchk = nullptr;
+        unsigned long long *dchk = (unsigned long long *)((char *)h->dQ + h->q_bytes);
         std::vector<unsigned long long> chk(3 * nq, 0ull);
-        hipError_t e = hipMalloc(&dchk, chk.size() * sizeof(unsigned long long));
-        if (e == hipSuccess) e = hipMemsetAsync(dchk, 0, chk.size() * sizeof(unsigned long long), h->stream);
+        hipError_t e = hipMemsetAsync(dchk, 0, chk.size() * sizeof(unsigned long long), h->stream);
         if (e == hipSuccess) e = launch_sym_check(h->stream, h->dQ, h->dtype, h->ld, (int)n, (int)nq, dchk);
         if (e == hipSuccess)
             e = hipMemcpyAsync(chk.data(), dchk, chk.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-        if (dchk) (void)hipFree(dchk);
         if (e != hipSuccess) {
             free_handle_memory(h);
             delete h;
