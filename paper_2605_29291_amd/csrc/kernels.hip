@@ -1254,31 +1254,6 @@ __global__ void __launch_bounds__(STEP_BS) k_start(Slot *__restrict__ S)
     project_dual_block(S, S->y);
 }
 
-// adaptive restart decision after the host evaluated G_xi at the iterate (eq. (ada_restart)):
-// first = 1 records the reference value G_ref only; otherwise restart when
-// G_xi(candidate) <= q G_ref and take the candidate's value as the new reference.
-__global__ void __launch_bounds__(STEP_BS) k_restart_decision(Slot *__restrict__ S, double gap,
-                                                              int first)
-{
-    __shared__ int s_rs;
-    const int tid = threadIdx.x;
-    if (tid == 0) {
-        S->gap_evals += 1;
-        S->last_gap = gap;
-        int rs = 0;
-        if (first) {
-            S->Gref = gap;
-        } else if (gap <= S->q_restart * S->Gref) {
-            S->Gref = gap;
-            rs = (S->restart_from_avg && S->T > 0.0) ? 2 : 1;
-        }
-        S->status = ST_RUNNING;
-        s_rs = rs;
-    }
-    __syncthreads();
-    if (s_rs) restart_epoch(S, s_rs);
-}
-
 // ---------------------------------------------------------------------------------------
 // standalone evaluations: gradient and KKT residual at an arbitrary (x, y), given U = [Q_i x]
 
@@ -1568,7 +1543,7 @@ __global__ void __launch_bounds__(256) k_sym_check(const void *__restrict__ Q, i
 // The box QP runs accelerated projected gradient with gradient restart, step 1/L, L the
 // Gershgorin bound of H = Q(lambda) + 2 xi I, until L ||D+ - Z|| <= tol (1 + ||grad||).
 // ctl layout: [0] t, [1] beta, [2] restart, [3] done, [4] iters, [5] L, [6] gnorm, [7] tol,
-//             [8] skip, [9] Py, [10] Px
+//             [9] Py, [10] Px; words 32..33 hold the inner loop's grid barrier
 
 __global__ void __launch_bounds__(STEP_BS) k_gap_py(const Slot *__restrict__ S,
                                                     const double *__restrict__ y,
@@ -1648,80 +1623,6 @@ __global__ void __launch_bounds__(STEP_BS) k_gap_init(int n, const double *__res
     }
 }
 
-__global__ void __launch_bounds__(STEP_BS) k_fista_u1(const Slot *__restrict__ S,
-                                                      const double *__restrict__ x,
-                                                      const double *__restrict__ grad,
-                                                      const double *__restrict__ Hz,
-                                                      const double *__restrict__ Z,
-                                                      const double *__restrict__ D,
-                                                      double *__restrict__ Dn,
-                                                      const double *__restrict__ ctl,
-                                                      double *__restrict__ part)
-{
-    if (ctl[3] != 0.0) return;
-    const int n = S->n;
-    const int j = blockIdx.x * STEP_BS + threadIdx.x;
-    const double L = ctl[5];
-    double v[2] = {0.0, 0.0};
-    if (j < n) {
-        const double gz = grad[j] + Hz[j];
-        const double xj = x[j];
-        const double dn = clipd(Z[j] - gz / L, S->lb[j] - xj, S->ub[j] - xj);
-        Dn[j] = dn;
-        const double a = dn - Z[j];
-        v[0] = a * a;
-        v[1] = (Z[j] - dn) * (dn - D[j]);
-    }
-    block_sum<2>(v);
-    if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = v[0];
-        part[2 * blockIdx.x + 1] = v[1];
-    }
-}
-
-__global__ void __launch_bounds__(STEP_BS) k_fista_sc(int nblk, const double *__restrict__ part,
-                                                      double *__restrict__ ctl, int64_t max_inner)
-{
-    if (ctl[3] != 0.0) {
-        if (threadIdx.x == 0) ctl[8] = 1.0;
-        return;
-    }
-    double v[2] = {0.0, 0.0};
-    for (int b = threadIdx.x; b < nblk; b += STEP_BS) {
-        v[0] += part[2 * b];
-        v[1] += part[2 * b + 1];
-    }
-    block_sum<2>(v);
-    if (threadIdx.x == 0) {
-        const double t = ctl[0];
-        double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
-        if (v[1] > 0.0) {          // gradient restart
-            tn = 1.0;
-            ctl[2] = 1.0;
-        } else {
-            ctl[2] = 0.0;
-            ctl[1] = (t - 1.0) / tn;
-        }
-        ctl[0] = tn;
-        ctl[4] += 1.0;
-        ctl[8] = 0.0;
-        if (ctl[5] * sqrt(v[0]) <= ctl[7] * (1.0 + ctl[6]) || ctl[4] >= (double)max_inner) ctl[3] = 1.0;
-    }
-}
-
-__global__ void __launch_bounds__(STEP_BS) k_fista_u2(int n, const double *__restrict__ Dn,
-                                                      double *__restrict__ D,
-                                                      double *__restrict__ Z,
-                                                      const double *__restrict__ ctl)
-{
-    if (ctl[8] != 0.0) return;
-    const int j = blockIdx.x * STEP_BS + threadIdx.x;
-    if (j >= n) return;
-    const double dn = Dn[j];
-    Z[j] = ctl[2] != 0.0 ? dn : dn + ctl[1] * (dn - D[j]);
-    D[j] = dn;
-}
-
 // Px = -(grad'D + 1/2 D'(H D))
 __global__ void __launch_bounds__(STEP_BS) k_gap_px(int n, const double *__restrict__ grad,
                                                     const double *__restrict__ D,
@@ -1734,6 +1635,338 @@ __global__ void __launch_bounds__(STEP_BS) k_gap_px(int n, const double *__restr
     if (threadIdx.x == 0) ctl[10] = -v[0];
 }
 
+// ---- the box QP in one cooperative launch -------------------------------------------------
+// Every block owns rows r = 4 b + w + 4 G k of H (one wave per row at a time) and the same
+// entries of Z, D and Dn.  An iteration is: (A) (H Z)_r, the projected step Dn_r and the two
+// partial sums of the rows owned, per block; grid barrier; (B) every block sums all blocks'
+// partials in the same fixed order, so all take the same momentum, restart and stop decision,
+// then applies Z, D to its rows; grid barrier.  The stop decision is therefore uniform and every
+// block leaves the loop at the same iteration (at the latest after max_inner iterations).
+// The barrier counts arrivals with agent-scope atomics (release on arrival, acquire on the
+// generation word) and gives up after a bounded spin, flagging bar->err, so a launch cannot hang.
+
+constexpr int FISTA_BS = 256;
+constexpr int FISTA_ROWS = 4;
+constexpr long long BAR_SPIN_LIMIT = 1ll << 25;   // ~2 s of 64-cycle sleeps
+
+__device__ __forceinline__ bool grid_barrier(GridBar *bar, unsigned nblocks, unsigned &gen)
+{
+    __shared__ int s_ok;
+    __syncthreads();       // the block's writes of this phase are ordered before thread 0's arrival
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        const unsigned g = gen;
+        // release: the block's writes become visible at device scope before the arrival counts
+        const unsigned arrived = __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nblocks - 1) {
+            __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&bar->gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            // spin on coherent relaxed loads (no cache invalidation per probe)
+            long long spins = 0;
+            while (__hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > BAR_SPIN_LIMIT) {
+                    ok = 0;
+                    __hip_atomic_store(&bar->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+        // acquire once: the other blocks' writes are read afresh by this block
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        gen = g + 1u;
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+__global__ void __launch_bounds__(FISTA_BS) k_fista_coop(const Slot *__restrict__ S, int n,
+                                                         const double *__restrict__ x,
+                                                         const double *__restrict__ grad,
+                                                         const double *__restrict__ H, int ldh,
+                                                         double *Z, double *D, double *Dn,
+                                                         double *part, double *ctl, int64_t max_inner,
+                                                         GridBar *bar)
+{
+    __shared__ double s_dec[3];   // t, beta, flags (restart + 2 done)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const unsigned G = gridDim.x;
+    const int rstep = (int)G * (FISTA_BS / 64);
+    unsigned gen = __hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double t = ctl[0], beta = ctl[1];
+    const double L = ctl[5], gn = ctl[6], tol = ctl[7];
+    double iters = ctl[4];
+    bool done = ctl[3] != 0.0 || iters >= (double)max_inner;
+    while (!done) {
+        // (A) rows owned: (H Z)_r, projected step, partial sums
+        double v[2] = {0.0, 0.0};
+        for (int r = (int)blockIdx.x * (FISTA_BS / 64) + wave; r < n; r += rstep) {
+            const double *h = H + (size_t)r * ldh;
+            double acc = 0.0;
+            for (int j = 2 * lane; j < n; j += 128) {      // ldh and Z are padded with zeros
+                acc = fma(h[j], Z[j], acc);
+                acc = fma(h[j + 1], Z[j + 1], acc);
+            }
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            if (lane == 0) {
+                const double zr = Z[r], xr = x[r];
+                const double dn = clipd(zr - (grad[r] + acc) / L, S->lb[r] - xr, S->ub[r] - xr);
+                Dn[r] = dn;
+                const double a = dn - zr;
+                v[0] += a * a;
+                v[1] += (zr - dn) * (dn - D[r]);
+            }
+        }
+        block_sum<2>(v);
+        if (threadIdx.x == 0) {
+            part[2 * blockIdx.x] = v[0];
+            part[2 * blockIdx.x + 1] = v[1];
+        }
+        if (!grid_barrier(bar, G, gen)) return;
+        // (B) every block: the same fixed-order total, the same decision
+        double u[2] = {0.0, 0.0};
+        for (int b = threadIdx.x; b < (int)G; b += FISTA_BS) {
+            u[0] += part[2 * b];
+            u[1] += part[2 * b + 1];
+        }
+        block_sum<2>(u);
+        if (threadIdx.x == 0) {
+            double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+            double fl = 0.0;
+            if (u[1] > 0.0) {          // gradient restart
+                tn = 1.0;
+                fl = 1.0;
+            } else {
+                beta = (t - 1.0) / tn;
+            }
+            iters += 1.0;
+            if (L * sqrt(u[0]) <= tol * (1.0 + gn) || iters >= (double)max_inner) fl += 2.0;
+            s_dec[0] = tn;
+            s_dec[1] = beta;
+            s_dec[2] = fl;
+        }
+        __syncthreads();
+        t = s_dec[0];
+        beta = s_dec[1];
+        const bool rst = ((int)s_dec[2] & 1) != 0;
+        done = ((int)s_dec[2] & 2) != 0;
+        for (int r = (int)blockIdx.x * (FISTA_BS / 64) + wave; r < n; r += rstep) {
+            if (lane == 0) {
+                const double dn = Dn[r];
+                Z[r] = rst ? dn : dn + beta * (dn - D[r]);
+                D[r] = dn;
+            }
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            ctl[0] = t;
+            ctl[1] = beta;
+            ctl[2] = rst ? 1.0 : 0.0;
+            ctl[3] = done ? 1.0 : 0.0;
+            ctl[4] = iters;
+        }
+        if (!grid_barrier(bar, G, gen)) return;
+    }
+}
+
+// The same loop with Z and D held by every block in LDS (n small enough): phase B then has
+// every block update all of Z and D itself from the step Dn that all blocks wrote in phase A,
+// so one grid barrier per iteration suffices.  Dn and the partial sums alternate between two
+// buffers by iteration parity: a block that runs ahead writes the other buffer, which every
+// slower block has finished reading (it passed the previous barrier).  Block 0 writes the
+// final D back to global memory.
+__global__ void __launch_bounds__(FISTA_BS) k_fista_coop_lds(const Slot *__restrict__ S, int n,
+                                                             const double *__restrict__ x,
+                                                             const double *__restrict__ grad,
+                                                             const double *__restrict__ H, int ldh,
+                                                             double *D, double *Dn2, int nstride,
+                                                             double *part2, double *ctl,
+                                                             int64_t max_inner, GridBar *bar)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nw = (n + 1) & ~1;
+    double *Zs = reinterpret_cast<double *>(smem);
+    double *Ds = Zs + nw;
+    __shared__ double s_dec[3];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const unsigned G = gridDim.x;
+    const int rstep = (int)G * (FISTA_BS / 64);
+    for (int j = threadIdx.x; j < nw; j += FISTA_BS) {
+        Zs[j] = 0.0;
+        Ds[j] = 0.0;
+    }
+    unsigned gen = __hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double t = ctl[0], beta = ctl[1];
+    const double L = ctl[5], gn = ctl[6], tol = ctl[7];
+    double iters = ctl[4];
+    bool done = ctl[3] != 0.0 || iters >= (double)max_inner;
+    __syncthreads();
+    int par = 0;
+    while (!done) {
+        double *Dn = Dn2 + (size_t)par * nstride;
+        double *part = part2 + (size_t)par * GAP_MAX_BLOCKS;   // G <= GAP_MAX_BLOCKS / 2
+        // (A) rows owned: (H Z)_r from the block's own Z, projected step, partial sums
+        double v[2] = {0.0, 0.0};
+        for (int r = (int)blockIdx.x * (FISTA_BS / 64) + wave; r < n; r += rstep) {
+            // 16-byte loads, four in flight per lane (ldh is padded with zeros, Zs[n] = 0)
+            const double2 *h2 = reinterpret_cast<const double2 *>(H + (size_t)r * ldh);
+            const double2 *z2 = reinterpret_cast<const double2 *>(Zs);
+            const int nv = nw >> 1;
+            double acc = 0.0;
+            int jv = lane;
+            for (; jv + 192 < nv; jv += 256) {
+                const double2 a0 = h2[jv], a1 = h2[jv + 64], a2 = h2[jv + 128], a3 = h2[jv + 192];
+                const double2 b0 = z2[jv], b1 = z2[jv + 64], b2 = z2[jv + 128], b3 = z2[jv + 192];
+                acc = fma(a0.x, b0.x, acc);
+                acc = fma(a0.y, b0.y, acc);
+                acc = fma(a1.x, b1.x, acc);
+                acc = fma(a1.y, b1.y, acc);
+                acc = fma(a2.x, b2.x, acc);
+                acc = fma(a2.y, b2.y, acc);
+                acc = fma(a3.x, b3.x, acc);
+                acc = fma(a3.y, b3.y, acc);
+            }
+            for (; jv < nv; jv += 64) {
+                const double2 a = h2[jv], b = z2[jv];
+                acc = fma(a.x, b.x, acc);
+                acc = fma(a.y, b.y, acc);
+            }
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            if (lane == 0) {
+                const double zr = Zs[r], xr = x[r];
+                const double dn = clipd(zr - (grad[r] + acc) / L, S->lb[r] - xr, S->ub[r] - xr);
+                Dn[r] = dn;
+                const double a = dn - zr;
+                v[0] += a * a;
+                v[1] += (zr - dn) * (dn - Ds[r]);
+            }
+        }
+        block_sum<2>(v);
+        if (threadIdx.x == 0) {
+            part[2 * blockIdx.x] = v[0];
+            part[2 * blockIdx.x + 1] = v[1];
+        }
+        if (!grid_barrier(bar, G, gen)) return;
+        // (B) every block: the same fixed-order totals and decision, then all of Z and D
+        double u[2] = {0.0, 0.0};
+        for (int b = threadIdx.x; b < (int)G; b += FISTA_BS) {
+            u[0] += part[2 * b];
+            u[1] += part[2 * b + 1];
+        }
+        block_sum<2>(u);
+        if (threadIdx.x == 0) {
+            double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+            double fl = 0.0;
+            if (u[1] > 0.0) {          // gradient restart
+                tn = 1.0;
+                fl = 1.0;
+            } else {
+                beta = (t - 1.0) / tn;
+            }
+            iters += 1.0;
+            if (L * sqrt(u[0]) <= tol * (1.0 + gn) || iters >= (double)max_inner) fl += 2.0;
+            s_dec[0] = tn;
+            s_dec[1] = beta;
+            s_dec[2] = fl;
+        }
+        __syncthreads();
+        t = s_dec[0];
+        beta = s_dec[1];
+        const bool rst = ((int)s_dec[2] & 1) != 0;
+        done = ((int)s_dec[2] & 2) != 0;
+        for (int j = threadIdx.x; j < n; j += FISTA_BS) {
+            const double dn = Dn[j];
+            Zs[j] = rst ? dn : dn + beta * (dn - Ds[j]);
+            Ds[j] = dn;
+        }
+        __syncthreads();
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            ctl[0] = t;
+            ctl[1] = beta;
+            ctl[2] = rst ? 1.0 : 0.0;
+            ctl[3] = done ? 1.0 : 0.0;
+            ctl[4] = iters;
+        }
+        par ^= 1;
+    }
+    if (blockIdx.x == 0)
+        for (int j = threadIdx.x; j < n; j += FISTA_BS) D[j] = Ds[j];
+}
+
+hipError_t launch_fista_coop(hipStream_t s, const Slot *slot, int n, const double *x,
+                             const double *grad, const double *H, int ldh, double *Z, double *D,
+                             double *Dn, double *part, double *ctl, int64_t max_inner, GridBar *bar,
+                             int max_blocks, int max_lds, int nstride)
+{
+    // a block per 4 x FISTA_ROWS rows (each wave about FISTA_ROWS rows of H per iteration):
+    // fewer blocks make the barrier cheaper
+    int G = (n + FISTA_BS / 64 * FISTA_ROWS - 1) / (FISTA_BS / 64 * FISTA_ROWS);
+    if (G > max_blocks) G = max_blocks;
+    if (G > GAP_MAX_BLOCKS / 2) G = GAP_MAX_BLOCKS / 2;
+    if (G < 1) G = 1;
+    const size_t lds = (size_t)2 * ((n + 1) & ~1) * sizeof(double);
+    if (lds + 1024 <= (size_t)max_lds) {
+        // Dn in two buffers nstride apart; the partials in the two halves of `part`
+        double *Dn2 = Dn;
+        (void)Z;
+        void *args[] = {(void *)&slot, (void *)&n, (void *)&x, (void *)&grad, (void *)&H, (void *)&ldh,
+                        (void *)&D, (void *)&Dn2, (void *)&nstride, (void *)&part, (void *)&ctl,
+                        (void *)&max_inner, (void *)&bar};
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_fista_coop_lds), dim3(G),
+                                          dim3(FISTA_BS), args, lds, s);
+    }
+    void *args[] = {(void *)&slot, (void *)&n, (void *)&x, (void *)&grad, (void *)&H, (void *)&ldh,
+                    (void *)&Z, (void *)&D, (void *)&Dn, (void *)&part, (void *)&ctl,
+                    (void *)&max_inner, (void *)&bar};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_fista_coop), dim3(G), dim3(FISTA_BS),
+                                      args, 0, s);
+}
+
+hipError_t prepare_fista_coop(int max_lds)
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fista_coop_lds),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, max_lds - 1024);
+}
+
+// decision of eq. (ada_restart) with G_xi = Py + Px from the device
+__global__ void __launch_bounds__(STEP_BS) k_restart_decision_dev(Slot *__restrict__ S,
+                                                                  const double *__restrict__ ctl)
+{
+    __shared__ int s_rs;
+    if (threadIdx.x == 0) {
+        s_rs = 0;
+        if (reinterpret_cast<const GridBar *>(ctl + 32)->err) {
+            S->status = ST_NUMERICAL;   // the inner loop's barrier gave up: no decision on partial values
+            s_rs = -1;
+        }
+    }
+    __syncthreads();
+    if (s_rs == -1) return;
+    if (threadIdx.x == 0) {
+        const double gap = ctl[9] + ctl[10];
+        S->gap_evals += 1;
+        S->last_gap = gap;
+        int rs = 0;
+        if (S->k == S->ada_first) {
+            S->Gref = gap;
+        } else if (gap <= S->q_restart * S->Gref) {
+            S->Gref = gap;
+            rs = (S->restart_from_avg && S->T > 0.0) ? 2 : 1;
+        }
+        S->status = ST_RUNNING;
+        s_rs = rs;
+    }
+    __syncthreads();
+    if (s_rs) restart_epoch(S, s_rs);
+}
+
+hipError_t launch_restart_decision_dev(hipStream_t s, Slot *slot, const double *ctl)
+{
+    k_restart_decision_dev<<<1, STEP_BS, 0, s>>>(slot, ctl);
+    return hipGetLastError();
+}
+
 hipError_t launch_gap_setup(hipStream_t s, const Slot *slot, int n, int ny, const double *y,
                             const double *G, const double *grad, double xi, double *H, int ldh,
                             double *rowabs, double tol, double *ctl)
@@ -1741,22 +1974,6 @@ hipError_t launch_gap_setup(hipStream_t s, const Slot *slot, int n, int ny, cons
     k_gap_py<<<1, STEP_BS, (size_t)(ny > 0 ? ny : 1) * sizeof(double), s>>>(slot, y, G, xi, ctl);
     k_form_h<<<n, STEP_BS, 0, s>>>(slot, y, xi, H, ldh, rowabs);
     k_gap_init<<<1, STEP_BS, 0, s>>>(n, grad, rowabs, tol, ctl);
-    return hipGetLastError();
-}
-
-hipError_t launch_gap_iters(hipStream_t s, const Slot *slot, int n, const double *x,
-                            const double *grad, const double *H, int ldh, int nw, double *Z,
-                            double *D, double *Dn, double *Hz, double *part, double *ctl,
-                            int iters, int64_t max_inner)
-{
-    const int nblk = (n + STEP_BS - 1) / STEP_BS;
-    for (int it = 0; it < iters; ++it) {
-        hipError_t e = launch_hmv(s, H, n, ldh, Z, nw, Hz, ctl, 0);
-        if (e != hipSuccess) return e;
-        k_fista_u1<<<nblk, STEP_BS, 0, s>>>(slot, x, grad, Hz, Z, D, Dn, ctl, part);
-        k_fista_sc<<<1, STEP_BS, 0, s>>>(nblk, part, ctl, max_inner);
-        k_fista_u2<<<nblk, STEP_BS, 0, s>>>(n, Dn, D, Z, ctl);
-    }
     return hipGetLastError();
 }
 
@@ -1892,10 +2109,5 @@ hipError_t launch_start(hipStream_t s, Slot *slot)
     return hipGetLastError();
 }
 
-hipError_t launch_restart_decision(hipStream_t s, Slot *slot, double gap, int first)
-{
-    k_restart_decision<<<1, STEP_BS, 0, s>>>(slot, gap, first);
-    return hipGetLastError();
-}
 
 }  // namespace qcqp

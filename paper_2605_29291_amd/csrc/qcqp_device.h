@@ -154,19 +154,35 @@ hipError_t launch_convert(hipStream_t s, const void *src, int src_dtype, int64_t
 // res: 3 zeroed words per stored matrix {max |Q_rc - Q_cr|, max |Q_rc|} as double bits, non-finite flag
 hipError_t launch_sym_check(hipStream_t s, const void *Q, int dtype, int64_t ld, int n, int nq,
                             unsigned long long *res);
+// Grid barrier of the cooperative G_xi inner loop (device memory, zero-initialised count)
+struct GridBar {
+    unsigned count;   // blocks arrived at the current barrier
+    unsigned gen;     // barriers completed
+    unsigned err;     // set when a wait exceeded its spin limit
+    unsigned pad;
+};
+// Partial sums of the G_xi inner loop: at most this many blocks
+constexpr int GAP_MAX_BLOCKS = 1024;
+// the G_xi box QP by accelerated projected gradient to convergence in one cooperative launch
+// (at most max_blocks blocks); ctl as for launch_gap_setup; bar->count must be 0.  Z, D, Dn:
+// n-vectors (Z, D zero); with Z and D in LDS (when 2n doubles fit max_lds) Dn and the n doubles
+// nstride after it are the two step buffers, and `part` holds 2 GAP_MAX_BLOCKS doubles
+hipError_t launch_fista_coop(hipStream_t s, const Slot *slot, int n, const double *x,
+                             const double *grad, const double *H, int ldh, double *Z, double *D,
+                             double *Dn, double *part, double *ctl, int64_t max_inner, GridBar *bar,
+                             int max_blocks, int max_lds, int nstride);
+hipError_t prepare_fista_coop(int max_lds);
+// adaptive restart decision with G_xi = ctl[9] + ctl[10] read on the device; the first
+// evaluation of a run (k = ada_first) only records the reference
+hipError_t launch_restart_decision_dev(hipStream_t s, Slot *slot, const double *ctl);
 // v[0..n) = value
 hipError_t launch_fill(hipStream_t s, double *v, int64_t n, double value);
 // one power-iteration normalisation: lam[0] = ||z||, v = z / ||z|| (v unchanged when z = 0)
 hipError_t launch_pow_normalize(hipStream_t s, const double *z, int n, double *v, double *lam);
 hipError_t launch_start(hipStream_t s, Slot *slot);
-hipError_t launch_restart_decision(hipStream_t s, Slot *slot, double gap, int first);
 hipError_t launch_gap_setup(hipStream_t s, const Slot *slot, int n, int ny, const double *y,
                             const double *G, const double *grad, double xi, double *H, int ldh,
                             double *rowabs, double tol, double *ctl);
-hipError_t launch_gap_iters(hipStream_t s, const Slot *slot, int n, const double *x,
-                            const double *grad, const double *H, int ldh, int nw, double *Z,
-                            double *D, double *Dn, double *Hz, double *part, double *ctl,
-                            int iters, int64_t max_inner);
 hipError_t launch_gap_finish(hipStream_t s, int n, const double *grad, const double *H, int ldh,
                              int nw, const double *D, double *HD, double *ctl);
 hipError_t launch_hmv(hipStream_t s, const double *H, int n, int ldh, const double *v, int nw,

@@ -67,6 +67,7 @@ qcqp_status ensure_prepared()
         max_lds = v;
         HIPCHK(hipDeviceGetAttribute(&num_cus, hipDeviceAttributeMultiprocessorCount, dev));
         HIPCHK(prepare_kernels(v));
+        HIPCHK(prepare_fista_coop(v));
         prepared = true;
         prepared_dev = dev;
     }
@@ -175,10 +176,11 @@ std::vector<int> balanced_starts(const std::vector<int64_t> &tile_bytes, int gri
 }  // namespace
 
 // Doubles of G_xi scratch for dimension n: H (n x ldh, ldh = n rounded up to 16), six vectors
-// of n rounded up to 32, two partial sums per step block and 64 control words.
+// of n rounded up to 32, two partial sums per block of the inner loop and 64 control words
+// (the inner loop's grid barrier lives in the last of them).
 constexpr int64_t gap_scratch_doubles(int64_t n)
 {
-    return n * ((n + 15) / 16 * 16) + 6 * ((n + 31) / 32 * 32) + 2 * ((n + STEP_BS - 1) / STEP_BS) + 64;
+    return n * ((n + 15) / 16 * 16) + 6 * ((n + 31) / 32 * 32) + 2 * GAP_MAX_BLOCKS + 64;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -246,6 +248,7 @@ struct qcqp_handle {
     qcqp_batch *owner = nullptr;
     double *gap_mem = nullptr;  // G_xi scratch: H (n x ldh), 6 vectors, partials, control
     size_t gap_bytes = 0;
+    double *gap_ctl = nullptr;  // control words of the last G_xi enqueued (in gap_mem)
     // options.sym_pass: the packed upper-triangle copy of the stack, its per-tile results and
     // the output row base of each stored matrix
     bool use_sym = false;
@@ -285,6 +288,9 @@ struct qcqp_batch {
     double pass_seconds = 0.0, pass_bytes = 0.0;
     int64_t passes = 0;
     std::vector<int64_t> last_passes;     // per slot, device pass counter at the last poll
+    hipStream_t gstream = nullptr;        // G_xi evaluations of pending slots (default priority)
+    std::vector<int> gap_busy;            // per slot: a G_xi is in flight on gstream
+    std::vector<hipEvent_t> gev;          // per slot: recorded after that G_xi
 };
 
 // ---------------------------------------------------------------------------------------
@@ -954,7 +960,8 @@ static qcqp_status slot_status_code(int st)
     }
 }
 
-static qcqp_status run_gap_for(qcqp_handle *h, Slot *dslot, const Slot &snap, double *gval, double *kk);
+static qcqp_status run_gap_for(qcqp_handle *h, Slot *dslot, const double *x_dev, const double *y_dev,
+                               hipStream_t decide_stream);
 
 qcqp_status qcqp_solve(qcqp_handle *h, const double *x0, const double *y0, double *x_out,
                        double *y_out, qcqp_info *info)
@@ -1043,11 +1050,10 @@ qcqp_status qcqp_solve(qcqp_handle *h, const double *x0, const double *y0, doubl
                 passes_before = sn.passes;
             }
             if (sn.status == ST_GAP_PENDING) {
-                e = hipStreamSynchronize(h->stream);   // the queued chunk saw the same pending state
-                if (e != hipSuccess) break;
-                double gval = 0.0, kk[6];
+                // the chunk queued behind this snapshot returns at once (the slot is not
+                // running); G_xi and the decision follow it on the stream, then the next chunks
                 snap = sn;
-                if ((result = run_gap_for(h, h->dslot, snap, &gval, kk))) break;
+                if ((result = run_gap_for(h, h->dslot, sn.x, sn.y, h->stream))) break;
                 pending = 0;
                 e = enqueue(0);
                 continue;
@@ -1125,37 +1131,49 @@ static qcqp_status ensure_gap_mem(qcqp_handle *h)
 }
 
 // G_xi at the device point (x_dev, y_dev) with `mem` (gap_scratch_doubles(n) doubles of device
-// memory) as scratch; out4 = {G, Py, Px, inner iterations}.  Allocates nothing.
-static qcqp_status gap_at_device_point(qcqp_handle *h, const double *x_dev, const double *y_dev,
-                                       double xi, double *mem, double *out4)
+// memory) as scratch, enqueued on h->stream with no host synchronisation: anchor pass and
+// epilogue at the point, gradient, Py, H = Q(lambda) + 2 xi I, the box QP to convergence in one
+// cooperative launch, Px.  *ctl_out receives the control words (ctl[9] = Py, ctl[10] = Px,
+// ctl[4] = inner iterations).  Allocates nothing.
+static qcqp_status gap_enqueue(qcqp_handle *h, const double *x_dev, const double *y_dev, double xi,
+                               double *mem, double **ctl_out)
 {
     qcqp_status st = load_point(h, x_dev, y_dev, true);
     if (st) return st;
     if ((st = eval_loaded_point(h))) return st;
     HIPCHK(launch_grad(h->stream, h->dslot_eval, (int)h->n, h->d_ueval, h->d_ye, h->d_grad));
     const int64_t n = h->n, ldh = round_up(n, 16);
-    const int nblk = (int)((n + STEP_BS - 1) / STEP_BS);
     double *H = mem;
     double *v0 = H + n * ldh;
     const int64_t vs = round_up(n, 32);
     double *rowabs = v0, *Z = v0 + vs, *D = v0 + 2 * vs, *Dn = v0 + 3 * vs, *Hz = v0 + 4 * vs;
-    double *part = v0 + 6 * vs, *ctl = part + 2 * nblk;
+    double *part = v0 + 6 * vs, *ctl = part + 2 * GAP_MAX_BLOCKS;
+    GridBar *bar = reinterpret_cast<GridBar *>(ctl + 32);
     HIPCHK(hipMemsetAsync(Z, 0, 2 * vs * 8, h->stream));   // Z and D
+    HIPCHK(hipMemsetAsync(bar, 0, sizeof(GridBar), h->stream));
     HIPCHK(launch_gap_setup(h->stream, h->dslot_eval, (int)n, (int)h->ny, h->d_ye, h->d_geval, h->d_grad, xi, H,
                             (int)ldh, rowabs, h->opt.inner_tol, ctl));
-    const int chunk = 32;
-    for (int64_t done_it = 0;;) {
-        HIPCHK(launch_gap_iters(h->stream, h->dslot_eval, (int)n, h->d_xe, h->d_grad, H, (int)ldh,
-                                (int)round_up(n, 2), Z, D, Dn, Hz, part, ctl, chunk, h->opt.max_inner));
-        done_it += chunk;
-        HIPCHK(hipMemcpyAsync(h->h_out, ctl, 11 * 8, hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipStreamSynchronize(h->stream));
-        if (h->h_out[3] != 0.0) break;
-        if (done_it > h->opt.max_inner + chunk) break;
-    }
+    // the LDS form uses Hz (written only after the loop) as the second step buffer
+    HIPCHK(launch_fista_coop(h->stream, h->dslot_eval, (int)n, h->d_xe, h->d_grad, H, (int)ldh, Z, D, Dn, part, ctl,
+                             h->opt.max_inner, bar, std::max(1, num_cus), max_lds, (int)(Hz - Dn)));
     HIPCHK(launch_gap_finish(h->stream, (int)n, h->d_grad, H, (int)ldh, (int)round_up(n, 2), D, Hz, ctl));
+    *ctl_out = ctl;
+    return QCQP_OK;
+}
+
+// G_xi at the device point, read back: out4 = {G, Py, Px, inner iterations}
+static qcqp_status gap_at_device_point(qcqp_handle *h, const double *x_dev, const double *y_dev,
+                                       double xi, double *mem, double *out4)
+{
+    double *ctl = nullptr;
+    qcqp_status st = gap_enqueue(h, x_dev, y_dev, xi, mem, &ctl);
+    if (st) return st;
     HIPCHK(hipMemcpyAsync(h->h_out, ctl, 11 * 8, hipMemcpyDeviceToHost, h->stream));
+    unsigned berr = 0;
+    HIPCHK(hipMemcpyAsync(&berr, &reinterpret_cast<GridBar *>(ctl + 32)->err, sizeof(unsigned),
+                          hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
+    if (berr) return fail(QCQP_E_DEVICE, "G_xi inner loop: a grid barrier wait exceeded its limit");
     const double Py = h->h_out[9], Px = h->h_out[10];
     out4[0] = Py + Px;
     out4[1] = Py;
@@ -1261,17 +1279,17 @@ qcqp_status qcqp_eval_gap_noalloc(qcqp_handle *h, const double *x, const double 
     return gap_at_device_point(h, h->d_xe, h->d_ye, xi, mem, out4);
 }
 
-// adaptive restart: evaluate G_xi at the slot's iterate and let the device decide
-static qcqp_status run_gap_for(qcqp_handle *h, Slot *dslot, const Slot &snap, double *gval, double *kk)
+// adaptive restart: evaluate G_xi at the slot's iterate (x_dev, y_dev from its last snapshot)
+// and let the device decide on `decide_stream` (eq. (ada_restart)); nothing returns to the host
+static qcqp_status run_gap_for(qcqp_handle *h, Slot *dslot, const double *x_dev, const double *y_dev,
+                               hipStream_t decide_stream)
 {
-    (void)kk;
-    double out4[4];
     qcqp_status st = ensure_gap_mem(h);
     if (st) return st;
-    if ((st = gap_at_device_point(h, snap.x, snap.y, h->opt.xi, h->gap_mem, out4))) return st;
-    *gval = out4[0];
-    const int first = snap.k == snap.ada_first ? 1 : 0;
-    HIPCHK(launch_restart_decision(h->stream, dslot, out4[0], first));
+    double *ctl = nullptr;
+    if ((st = gap_enqueue(h, x_dev, y_dev, h->opt.xi, h->gap_mem, &ctl))) return st;
+    if (decide_stream == h->stream) HIPCHK(launch_restart_decision_dev(h->stream, dslot, ctl));
+    h->gap_ctl = ctl;
     return QCQP_OK;
 }
 
@@ -1324,12 +1342,16 @@ qcqp_status qcqp_batch_create(const qcqp_options *opt, size_t budget, int64_t ma
     bt->max_slots = max_slots;
     bt->ustream = (hipStream_t)o.stream;
     if (hipStreamCreateWithFlags(&bt->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&bt->gstream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&bt->ev_join, hipEventDisableTiming) != hipSuccess) {
         if (bt->stream) (void)hipStreamDestroy(bt->stream);
+        if (bt->gstream) (void)hipStreamDestroy(bt->gstream);
         delete bt;
         return fail(QCQP_E_DEVICE, "stream creation");
     }
     (void)hipGetDevice(&bt->dev);
+    bt->gap_busy.assign(max_slots, 0);
+    bt->gev.assign(max_slots, nullptr);
     bt->handles.assign(max_slots, nullptr);
     bt->finished.assign(max_slots, 0);
     bt->last_passes.assign(max_slots, 0);
@@ -1538,18 +1560,32 @@ qcqp_status qcqp_batch_step(qcqp_batch *bt, int64_t groups)
         }
         bt->last_passes[s] = bt->h_poll[s].passes;
     }
-    // adaptive restarts pending: evaluate G_xi per slot, then resume
+    // adaptive restarts pending: each pending slot's G_xi runs on the batch's gap stream while
+    // the other slots keep stepping; once it has completed, the decision (on the device, from
+    // the device's G_xi) is enqueued on the batch stream ahead of the next groups
     for (int64_t s = 0; s < bt->max_slots; ++s) {
         qcqp_handle *h = bt->handles[s];
         if (!h || bt->finished[s]) continue;
         const Slot &S = bt->h_poll[s];
         if (S.status == ST_GAP_PENDING) {
-            hipStream_t saved = h->stream;
-            h->stream = bt->stream;
-            double gval, kk[6];
-            st = run_gap_for(h, bt->dslots + s, S, &gval, kk);
-            h->stream = saved;
-            if (st) return st;
+            if (!bt->gap_busy[s]) {
+                if (!bt->gev[s]) HIPCHK(hipEventCreateWithFlags(&bt->gev[s], hipEventDisableTiming));
+                hipStream_t saved = h->stream;
+                h->stream = bt->gstream;
+                st = run_gap_for(h, bt->dslots + s, S.x, S.y, nullptr);
+                h->stream = saved;
+                if (st) return st;
+                HIPCHK(hipEventRecord(bt->gev[s], bt->gstream));
+                bt->gap_busy[s] = 1;
+            } else {
+                const hipError_t q = hipEventQuery(bt->gev[s]);
+                if (q == hipSuccess) {
+                    HIPCHK(launch_restart_decision_dev(bt->stream, bt->dslots + s, h->gap_ctl));
+                    bt->gap_busy[s] = 0;
+                } else if (q != hipErrorNotReady) {
+                    return fail(QCQP_E_DEVICE, "G_xi of slot %lld: %s", (long long)s, hipGetErrorString(q));
+                }
+            }
         } else if (S.status != ST_RUNNING) {
             if (!bt->finished[s]) {
                 bt->finished[s] = 1;
@@ -1620,6 +1656,7 @@ qcqp_status qcqp_batch_destroy(qcqp_batch *bt)
 {
     if (!bt) return QCQP_OK;
     (void)hipStreamSynchronize(bt->stream);
+    (void)hipStreamSynchronize(bt->gstream);
     for (auto *h : bt->handles)
         if (h) {
             h->owner = nullptr;
@@ -1634,7 +1671,10 @@ qcqp_status qcqp_batch_destroy(qcqp_batch *bt)
     for (auto &e : bt->ev) (void)hipEventDestroy(e);
     if (bt->gexec) (void)hipGraphExecDestroy(bt->gexec);
     if (bt->ev_join) (void)hipEventDestroy(bt->ev_join);
+    for (auto &e : bt->gev)
+        if (e) (void)hipEventDestroy(e);
     if (bt->stream) (void)hipStreamDestroy(bt->stream);
+    if (bt->gstream) (void)hipStreamDestroy(bt->gstream);
     delete bt;
     return QCQP_OK;
 }

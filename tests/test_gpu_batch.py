@@ -103,8 +103,9 @@ def test_admission_respects_hbm_budget():
 
 
 def test_adaptive_restarts_inside_a_batch():
-    """A slot whose schedule asks for the smoothed gap is parked, evaluated by the host-side
-    G_xi path and resumed; the result matches the same solve alone."""
+    """A slot whose schedule asks for the smoothed gap is parked, its G_xi evaluated on the
+    device (one cooperative launch for the inner box QP) and the decision taken there; the result
+    matches the same solve alone."""
     from paper_2605_29291_amd import Batch, Solver
     insts = [qi.random_qcqp(n, m, seed=7000 + n, shift=0.01) for n, m in ((120, 8), (90, 5))]
     kw = dict(restart="adaptive", ada_first=5, ada_every=10, c_nm=0)
@@ -128,3 +129,52 @@ def test_adaptive_restarts_inside_a_batch():
         np.testing.assert_array_equal(got[k][0], alone[k][0])
         assert got[k][1]["gap_evals"] == alone[k][1]["gap_evals"]
         assert got[k][1]["status"] == "ok"
+
+
+def test_mixed_adaptive_and_fixed_restarts_alone_equals_mix():
+    """Adaptive-restart slots evaluate G_xi on the batch's side stream while fixed-restart and
+    other adaptive slots keep stepping; the decision is taken on the device from the device's
+    G_xi.  Every request returns the same bits (and the same restart and gap counts) alone and
+    in the mix."""
+    from paper_2605_29291_amd import Batch, Solver
+    specs = [((150, 10), dict(restart="adaptive", ada_first=5, ada_every=10, c_nm=0)),
+             ((97, 6), dict(restart="fixed", restart_every=15)),
+             ((60, 3), dict(restart="adaptive", ada_first=8, ada_every=12, c_nm=1)),
+             ((211, 12), dict(restart="fixed", restart_every=40, c_nm=0)),
+             ((120, 8), dict(restart="adaptive", ada_first=5, ada_every=7, c_nm=0))]
+    insts = [qi.random_qcqp(n, m, seed=7100 + k, shift=0.01) for k, ((n, m), _) in enumerate(specs)]
+    alone = []
+    for inst, (_, kw) in zip(insts, specs):
+        announce(f"alone {inst.name} {kw['restart']}")
+        b = Batch(max_slots=1)
+        slot = b.admit(Solver(inst, tau_bar=tau_bar_of(inst), gamma0=0.1, **kw))
+        while not b.poll():
+            b.step(3)
+        _, x, y, info = b.fetch(slot)
+        b.close()
+        assert info["status"] == "ok"
+        if kw["restart"] == "adaptive":
+            assert info["gap_evals"] >= 2
+        alone.append((to_np(x), to_np(y), info))
+    announce("mix of adaptive and fixed restarts")
+    b = Batch(max_slots=8)
+    slot_of = {}
+    for k in (0, 1, 2):
+        slot_of[b.admit(Solver(insts[k], tau_bar=tau_bar_of(insts[k]), gamma0=0.1, **specs[k][1]))] = k
+    b.step(2)
+    for k in (3, 4):
+        slot_of[b.admit(Solver(insts[k], tau_bar=tau_bar_of(insts[k]), gamma0=0.1, **specs[k][1]))] = k
+    got, guard = {}, 0
+    while len(got) < len(insts):
+        b.step(2)
+        for slot in b.poll():
+            _, x, y, info = b.fetch(slot)
+            got[slot_of[slot]] = (to_np(x), to_np(y), info)
+        guard += 1
+        assert guard < 20000
+    b.close()
+    for k in range(len(insts)):
+        np.testing.assert_array_equal(got[k][0], alone[k][0])
+        np.testing.assert_array_equal(got[k][1], alone[k][1])
+        for key in ("iters", "trials", "restarts", "gap_evals"):
+            assert got[k][2][key] == alone[k][2][key], (k, key)
