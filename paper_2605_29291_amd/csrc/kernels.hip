@@ -219,12 +219,10 @@ __device__ void project_dual_block(const Slot *S, double *w)
 // Also the KKT partials of the iterate (x^k, y^k).
 
 template <int B>
-__global__ void __launch_bounds__(STEP_BS) k_step(Slot *__restrict__ slots,
-                                                  const int *__restrict__ live)
+__device__ __forceinline__ void step_yx(Slot *__restrict__ S, const int bx)
 {
-    Slot *S = slots + live[blockIdx.y];
     if (S->variant != VAR_YX || S->status != ST_RUNNING || S->mode != MODE_TRIAL) return;
-    if ((int)blockIdx.x >= S->nblk_step) return;
+    if (bx >= S->nblk_step) return;
     const int n = S->n, m = S->m, p = S->p, ny = S->ny;
     extern __shared__ double sm[];
     double *ycur = sm;
@@ -242,6 +240,30 @@ __global__ void __launch_bounds__(STEP_BS) k_step(Slot *__restrict__ slots,
             t *= eta;
         }
     }
+    // block = STEP_COLS columns; wave w sums matrices i = 1 + w, 1 + w + STEP_WAVES, ... in
+    // batches of SB.  The values the primal step needs and the first batch of U_i + q_i are
+    // loaded before the dual step and its projection, so their round trip overlaps them.
+    constexpr int SB = 8;
+    const int lane = threadIdx.x % STEP_COLS, wave = threadIdx.x / STEP_COLS;
+    const int j = bx * STEP_COLS + lane;
+    const double *U = S->U, *q = S->q;
+    double xj = 0.0, lo = 0.0, hi = 0.0, u0 = 0.0;
+    if (wave == 0 && j < n) {
+        xj = S->x[j];
+        lo = S->lb[j];
+        hi = S->ub[j];
+        u0 = U[j] + q[j];
+    }
+    double t[SB];
+    auto load_batch = [&](int i0) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int ii = i0 + u * STEP_WAVES;
+            const size_t o = (size_t)(ii <= m ? ii : 0) * n + j;
+            t[u] = (ii <= m && j < n) ? U[o] + q[o] : 0.0;
+        }
+    };
+    load_batch(1 + wave);
     const double *G = S->G, *Gp = S->Gp, *y = S->y;
     for (int l = threadIdx.x; l < ny; l += STEP_BS) {
         const double yl = y[l], gl = G[l], gpl = Gp[l];
@@ -255,66 +277,31 @@ __global__ void __launch_bounds__(STEP_BS) k_step(Slot *__restrict__ slots,
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < B; ++b) project_dual_block(S, ynew + b * ny);
-    if (blockIdx.x == 0) {
+    if (bx == 0) {
         for (int l = threadIdx.x; l < ny; l += STEP_BS) {
 #pragma unroll
             for (int b = 0; b < B; ++b) S->yc[b][l] = ynew[b * ny + l];
         }
     }
-    // block = STEP_COLS columns; wave w sums matrices i = 1 + w, 1 + w + STEP_WAVES, ...
-    const int lane = threadIdx.x % STEP_COLS, wave = threadIdx.x / STEP_COLS;
-    const int j = blockIdx.x * STEP_COLS + lane;
-    const double *U = S->U, *q = S->q;
-    // the values the primal step needs at the end are loaded now, while the sums below stream
-    double xj = 0.0, lo = 0.0, hi = 0.0, u0 = 0.0;
-    if (wave == 0 && j < n) {
-        xj = S->x[j];
-        lo = S->lb[j];
-        hi = S->ub[j];
-        u0 = U[j] + q[j];
-    }
     double acc[B], kk = 0.0;
 #pragma unroll
     for (int b = 0; b < B; ++b) acc[b] = 0.0;
     if (j < n) {
-        // 8 (then 4) matrices per step so 16 (8) independent loads are in flight; the
-        // multiply-adds keep the ascending order of i
-        int i = 1 + wave;
-        for (; i + 7 * STEP_WAVES <= m; i += 8 * STEP_WAVES) {
-            double t[8];
+        // ascending i; the next batch is loaded before the current one is summed
+        for (int i = 1 + wave; i <= m; i += SB * STEP_WAVES) {
+            double c[SB];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const size_t o = (size_t)(i + u * STEP_WAVES) * n + j;
-                t[u] = U[o] + q[o];
-            }
+            for (int u = 0; u < SB; ++u) c[u] = t[u];
+            if (i + SB * STEP_WAVES <= m) load_batch(i + SB * STEP_WAVES);
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < SB; ++u) {
                 const int ii = i + u * STEP_WAVES;
+                if (ii <= m) {
 #pragma unroll
-                for (int b = 0; b < B; ++b) acc[b] = fma(ynew[b * ny + p + ii - 1], t[u], acc[b]);
-                kk = fma(ycur[p + ii - 1], t[u], kk);
+                    for (int b = 0; b < B; ++b) acc[b] = fma(ynew[b * ny + p + ii - 1], c[u], acc[b]);
+                    kk = fma(ycur[p + ii - 1], c[u], kk);
+                }
             }
-        }
-        for (; i + 3 * STEP_WAVES <= m; i += 4 * STEP_WAVES) {
-            double t[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const size_t o = (size_t)(i + u * STEP_WAVES) * n + j;
-                t[u] = U[o] + q[o];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int ii = i + u * STEP_WAVES;
-#pragma unroll
-                for (int b = 0; b < B; ++b) acc[b] = fma(ynew[b * ny + p + ii - 1], t[u], acc[b]);
-                kk = fma(ycur[p + ii - 1], t[u], kk);
-            }
-        }
-        for (; i <= m; i += STEP_WAVES) {
-            const double t = U[(size_t)i * n + j] + q[(size_t)i * n + j];
-#pragma unroll
-            for (int b = 0; b < B; ++b) acc[b] = fma(ynew[b * ny + p + i - 1], t, acc[b]);
-            kk = fma(ycur[p + i - 1], t, kk);
         }
     }
     if (wave > 0) {
@@ -361,8 +348,15 @@ __global__ void __launch_bounds__(STEP_BS) k_step(Slot *__restrict__ slots,
     block_sum<NPART>(part);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int f = 0; f < NPART; ++f) S->part[(size_t)blockIdx.x * NPART + f] = part[f];
+        for (int f = 0; f < NPART; ++f) S->part[(size_t)bx * NPART + f] = part[f];
     }
+}
+
+template <int B>
+__global__ void __launch_bounds__(STEP_BS) k_step(Slot *__restrict__ slots,
+                                                  const int *__restrict__ live)
+{
+    step_yx<B>(slots + (live ? live[blockIdx.y] : (int)blockIdx.y), (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -375,12 +369,10 @@ __global__ void __launch_bounds__(STEP_BS) k_step(Slot *__restrict__ slots,
 // the previous iterate, except at the first iteration of an epoch, where x^{-1} = x^0.
 
 template <int B>
-__global__ void __launch_bounds__(STEP_BS) k_step_xy(Slot *__restrict__ slots,
-                                                     const int *__restrict__ live)
+__device__ __forceinline__ void step_xy(Slot *__restrict__ S, const int bx)
 {
-    Slot *S = slots + live[blockIdx.y];
     if (S->variant != VAR_XY || S->status != ST_RUNNING || S->mode != MODE_TRIAL) return;
-    if ((int)blockIdx.x >= S->nblk_step) return;
+    if (bx >= S->nblk_step) return;
     const int n = S->n, m = S->m, p = S->p, ny = S->ny;
     extern __shared__ double sm[];
     double *ycur = sm;
@@ -396,37 +388,48 @@ __global__ void __launch_bounds__(STEP_BS) k_step_xy(Slot *__restrict__ slots,
             t *= eta;
         }
     }
+    // wave w sums matrices i = 1 + w, 1 + w + STEP_WAVES, ... in batches of SB; the first batch
+    // is loaded before the barrier that publishes y
+    constexpr int SB = 8;
+    const int lane = threadIdx.x % STEP_COLS, wave = threadIdx.x / STEP_COLS;
+    const int j = bx * STEP_COLS + lane;
+    const double *U = S->U, *q = S->q;
+    double t[SB];
+    auto load_batch = [&](int i0) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int ii = i0 + u * STEP_WAVES;
+            const size_t o = (size_t)(ii <= m ? ii : 0) * n + j;
+            t[u] = (ii <= m && j < n) ? U[o] + q[o] : 0.0;
+        }
+    };
+    load_batch(1 + wave);
+    // the per-column values of the primal step, loaded now too
+    const bool first = S->ke == 0;
+    double xj = 0.0, lo = 0.0, hi = 0.0, u0 = 0.0, gxp = 0.0;
+    if (wave == 0 && j < n) {
+        xj = S->x[j];
+        lo = S->lb[j];
+        hi = S->ub[j];
+        u0 = U[j] + q[j];
+        if (!first) gxp = S->gxp[j];
+    }
     const double *y = S->y;
     for (int l = threadIdx.x; l < ny; l += STEP_BS) ycur[l] = y[l];
     __syncthreads();
-    const int lane = threadIdx.x % STEP_COLS, wave = threadIdx.x / STEP_COLS;
-    const int j = blockIdx.x * STEP_COLS + lane;
-    const double *U = S->U, *q = S->q;
     double kk = 0.0;
     if (j < n) {
-        int i = 1 + wave;
-        for (; i + 7 * STEP_WAVES <= m; i += 8 * STEP_WAVES) {
-            double t[8];
+        for (int i = 1 + wave; i <= m; i += SB * STEP_WAVES) {
+            double c[SB];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const size_t o = (size_t)(i + u * STEP_WAVES) * n + j;
-                t[u] = U[o] + q[o];
+            for (int u = 0; u < SB; ++u) c[u] = t[u];
+            if (i + SB * STEP_WAVES <= m) load_batch(i + SB * STEP_WAVES);
+#pragma unroll
+            for (int u = 0; u < SB; ++u) {
+                const int ii = i + u * STEP_WAVES;
+                if (ii <= m) kk = fma(ycur[p + ii - 1], c[u], kk);
             }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) kk = fma(ycur[p + i + u * STEP_WAVES - 1], t[u], kk);
         }
-        for (; i + 3 * STEP_WAVES <= m; i += 4 * STEP_WAVES) {
-            double t[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const size_t o = (size_t)(i + u * STEP_WAVES) * n + j;
-                t[u] = U[o] + q[o];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) kk = fma(ycur[p + i + u * STEP_WAVES - 1], t[u], kk);
-        }
-        for (; i <= m; i += STEP_WAVES)
-            kk = fma(ycur[p + i - 1], U[(size_t)i * n + j] + q[(size_t)i * n + j], kk);
     }
     if (wave > 0) s_acc[wave - 1][lane] = kk;
     __syncthreads();
@@ -436,13 +439,11 @@ __global__ void __launch_bounds__(STEP_BS) k_step_xy(Slot *__restrict__ slots,
     if (wave == 0 && j < n) {
 #pragma unroll
         for (int w = 1; w < STEP_WAVES; ++w) kk += s_acc[w - 1][lane];
-        const double u0 = U[j] + q[j];
         double av = 0.0;
         for (int l = 0; l < p; ++l) av = fma(ycur[l], S->A[(size_t)l * n + j], av);
-        const double gk = u0 + kk + av;                 // grad_x Phi(x^k, y^k)
-        const double gp = S->ke == 0 ? gk : S->gxp[j];   // grad_x Phi(x^{k-1}, y^{k-1})
+        const double gk = u0 + kk + av;          // grad_x Phi(x^k, y^k)
+        const double gp = first ? gk : gxp;      // grad_x Phi(x^{k-1}, y^{k-1})
         S->gxk[j] = gk;
-        const double xj = S->x[j], lo = S->lb[j], hi = S->ub[j];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const double sdir = (1.0 + th_b[b]) * gk - th_b[b] * gp;
@@ -460,8 +461,15 @@ __global__ void __launch_bounds__(STEP_BS) k_step_xy(Slot *__restrict__ slots,
     block_sum<NPART>(part);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int f = 0; f < NPART; ++f) S->part[(size_t)blockIdx.x * NPART + f] = part[f];
+        for (int f = 0; f < NPART; ++f) S->part[(size_t)bx * NPART + f] = part[f];
     }
+}
+
+template <int B>
+__global__ void __launch_bounds__(STEP_BS) k_step_xy(Slot *__restrict__ slots,
+                                                     const int *__restrict__ live)
+{
+    step_xy<B>(slots + (live ? live[blockIdx.y] : (int)blockIdx.y), (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -473,13 +481,11 @@ __global__ void __launch_bounds__(STEP_BS) k_step_xy(Slot *__restrict__ slots,
 // G arrays are laid out (Ax-b [p], g [m], f [1]).
 
 template <int B>
-__global__ void __launch_bounds__(STEP_BS) k_epi(Slot *__restrict__ slots,
-                                                 const int *__restrict__ live)
+__device__ __forceinline__ void epi_rows(Slot *__restrict__ S, const int bx)
 {
-    Slot *S = slots + live[blockIdx.y];
     if (S->status != ST_RUNNING) return;
     const int n = S->n, m = S->m, p = S->p, ny = S->ny;
-    const int row = blockIdx.x;
+    const int row = bx;
     if (row > m + p) return;
     const bool anchor = S->mode == MODE_ANCHOR;
     const bool inc = S->incremental != 0;
@@ -491,6 +497,8 @@ __global__ void __launch_bounds__(STEP_BS) k_epi(Slot *__restrict__ slots,
     const double keep0 = S->has_q0 ? 1.0 : 0.0;
     if (row <= m) {
         const int gi = row == 0 ? ny : p + row - 1;
+        // G_i of the iterate, for the stores at the end, is loaded with the first loads
+        const double g_old = (!anchor && tid == 0) ? S->G[gi] : 0.0;
         const double *q = S->q + (size_t)row * n;
         const double ci = S->c[row];
         const size_t off = (size_t)row * n;
@@ -595,7 +603,7 @@ __global__ void __launch_bounds__(STEP_BS) k_epi(Slot *__restrict__ slots,
                     const double dg = v[3 * b + 1] + 0.5 * e + v[3 * b + 2];
                     S->e[b * (m + 1) + row] = e;
                     S->dG[b][gi] = dg;
-                    S->Gc[b][gi] = S->G[gi] + dg;
+                    S->Gc[b][gi] = g_old + dg;
                 }
             }
         } else {
@@ -657,7 +665,7 @@ __global__ void __launch_bounds__(STEP_BS) k_epi(Slot *__restrict__ slots,
                     const double gn = 0.5 * v[3 * b + 1] + v[3 * b + 2] + ci;
                     S->e[b * (m + 1) + row] = v[3 * b];
                     S->Gc[b][gi] = gn;
-                    S->dG[b][gi] = gn - S->G[gi];
+                    S->dG[b][gi] = gn - g_old;
                 }
             }
         }
@@ -665,6 +673,7 @@ __global__ void __launch_bounds__(STEP_BS) k_epi(Slot *__restrict__ slots,
         const int l = row - (m + 1);
         const double *a = S->A + (size_t)l * n;
         const double bl = S->b[l];
+        const double g_old = (!anchor && tid == 0) ? S->G[l] : 0.0;
         if (anchor) {
             double v[1] = {0.0};
             for (int j = tid; j < n; j += STEP_BS) v[0] = fma(a[j], x[j], v[0]);
@@ -685,15 +694,22 @@ __global__ void __launch_bounds__(STEP_BS) k_epi(Slot *__restrict__ slots,
                 for (int b = 0; b < B; ++b) {
                     if (inc) {
                         S->dG[b][l] = v[b];
-                        S->Gc[b][l] = S->G[l] + v[b];
+                        S->Gc[b][l] = g_old + v[b];
                     } else {
                         S->Gc[b][l] = v[b] - bl;
-                        S->dG[b][l] = (v[b] - bl) - S->G[l];
+                        S->dG[b][l] = (v[b] - bl) - g_old;
                     }
                 }
             }
         }
     }
+}
+
+template <int B>
+__global__ void __launch_bounds__(STEP_BS) k_epi(Slot *__restrict__ slots,
+                                                 const int *__restrict__ live)
+{
+    epi_rows<B>(slots + (live ? live[blockIdx.y] : (int)blockIdx.y), (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -707,12 +723,10 @@ __global__ void __launch_bounds__(STEP_BS) k_epi(Slot *__restrict__ slots,
 // Per block: |a|^2 and |c|^2 of its columns, per candidate.
 
 template <int B>
-__global__ void __launch_bounds__(STEP_BS) k_post_xy(Slot *__restrict__ slots,
-                                                     const int *__restrict__ live)
+__device__ __forceinline__ void post_xy(Slot *__restrict__ S, const int bx)
 {
-    Slot *S = slots + live[blockIdx.y];
     if (S->variant != VAR_XY || S->status != ST_RUNNING || S->mode != MODE_TRIAL) return;
-    if ((int)blockIdx.x >= S->nblk_step) return;
+    if (bx >= S->nblk_step) return;
     const int n = S->n, m = S->m, p = S->p, ny = S->ny;
     extern __shared__ double sm[];
     double *ycur = sm;
@@ -738,14 +752,14 @@ __global__ void __launch_bounds__(STEP_BS) k_post_xy(Slot *__restrict__ slots,
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < B; ++b) project_dual_block(S, ynew + b * ny);
-    if (blockIdx.x == 0) {
+    if (bx == 0) {
         for (int l = threadIdx.x; l < ny; l += STEP_BS) {
 #pragma unroll
             for (int b = 0; b < B; ++b) S->yc[b][l] = ynew[b * ny + l];
         }
     }
     const int lane = threadIdx.x % STEP_COLS, wave = threadIdx.x / STEP_COLS;
-    const int j = blockIdx.x * STEP_COLS + lane;
+    const int j = bx * STEP_COLS + lane;
     const bool inc = S->incremental != 0;
     const double *U = S->U, *q = S->q;
     double a[B], c[B];
@@ -830,8 +844,15 @@ __global__ void __launch_bounds__(STEP_BS) k_post_xy(Slot *__restrict__ slots,
     block_sum<2 * B>(part);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int f = 0; f < 2 * B; ++f) S->part2[(size_t)blockIdx.x * NPART2 + f] = part[f];
+        for (int f = 0; f < 2 * B; ++f) S->part2[(size_t)bx * NPART2 + f] = part[f];
     }
+}
+
+template <int B>
+__global__ void __launch_bounds__(STEP_BS) k_post_xy(Slot *__restrict__ slots,
+                                                     const int *__restrict__ live)
+{
+    post_xy<B>(slots + (live ? live[blockIdx.y] : (int)blockIdx.y), (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -887,11 +908,46 @@ __device__ void restart_epoch(Slot *S, int rs)
     }
 }
 
+// The slot fields the control phase's thread 0 reads, loaded in one batch (see ctrl_slot).
+struct CtlState {
+    double cnorm, bnorm, f_star, tol, tau, gam, sig_prev, eta, sig0, c_alpha, gamma0, c_beta, delta;
+    double alpha_k, beta_k, T, mu, tau_prev, fval;
+    int64_t k, ke, max_iter, passes, trials, iter_trials, restart_every, ada_first, ada_every;
+    int32_t stop_rule, m0, n_soc, fresh, c_nm, restart, restart_from_avg, variant, dtype, incremental;
+    double *x, *U, *y, *G, *Gp, *gxp, *gxk;
+    double *xc[MAXB], *Uc[MAXB], *yc[MAXB], *Gc[MAXB];
+    double fc[MAXB];   // f at each candidate: Gc[b][ny]
+
+    template <int B>
+    __device__ __forceinline__ void load(const Slot *__restrict__ S)
+    {
+        cnorm = S->cnorm; bnorm = S->bnorm; f_star = S->f_star; tol = S->tol;
+        tau = S->tau; gam = S->gam; sig_prev = S->sig_prev; eta = S->eta; sig0 = S->sig0;
+        c_alpha = S->c_alpha; gamma0 = S->gamma0; c_beta = S->c_beta; delta = S->delta;
+        alpha_k = S->alpha_k; beta_k = S->beta_k; T = S->T; mu = S->mu; tau_prev = S->tau_prev;
+        k = S->k; ke = S->ke; max_iter = S->max_iter; passes = S->passes; trials = S->trials;
+        iter_trials = S->iter_trials; restart_every = S->restart_every; ada_first = S->ada_first;
+        ada_every = S->ada_every;
+        stop_rule = S->stop_rule; m0 = S->m0; n_soc = S->n_soc; fresh = S->fresh; c_nm = S->c_nm;
+        restart = S->restart; restart_from_avg = S->restart_from_avg; variant = S->variant;
+        dtype = S->dtype; incremental = S->incremental;
+        x = S->x; U = S->U; y = S->y; G = S->G; Gp = S->Gp; gxp = S->gxp; gxk = S->gxk;
+        const int ny = S->ny;
+        fval = G[ny];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            xc[b] = S->xc[b];
+            Uc[b] = S->Uc[b];
+            yc[b] = S->yc[b];
+            Gc[b] = S->Gc[b];
+            fc[b] = Gc[b][ny];
+        }
+    }
+};
+
 template <int B>
-__global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
-                                                  const int *__restrict__ live)
+__device__ __forceinline__ void ctrl_slot(Slot *__restrict__ S)
 {
-    Slot *S = slots + live[blockIdx.x];
     const int status = S->status;
     const int mode = S->mode;
     __syncthreads();
@@ -923,6 +979,20 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
         }
         return;
     }
+
+    // Everything thread 0 reads for the decision and the bookkeeping is loaded now, before the
+    // reductions: none of it is written before thread 0's own stores below, and the loads then
+    // overlap the reductions instead of following them as two more round trips.  Every thread
+    // takes the candidates' x and y pointers for the ergodic sums.
+    const double *xcp[B], *ycp[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        xcp[b] = S->xc[b];
+        ycp[b] = S->yc[b];
+    }
+    double *const cxp = S->cx, *const cyp = S->cy;
+    CtlState cs;
+    if (tid == 0) cs.load<B>(S);
 
     // ---- 1+2. one fixed-order block reduction of everything the decision needs:
     //   step partials (KKT pieces of the iterate, ||d_b||^2), ||min(lambda,-g)||^2,
@@ -1046,17 +1116,15 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
     }
 
     if (tid == 0) {
-        // every slot field the decision reads is loaded here, before the first store, so the
-        // loads go out together instead of one round trip after each store
-        const auto cnorm = S->cnorm, bnorm = S->bnorm, f_star = S->f_star, tol = S->tol;
-        const auto stop_rule = S->stop_rule, m0 = S->m0, n_soc = S->n_soc, fresh = S->fresh;
-        const auto kk = S->k, ke = S->ke, max_iter = S->max_iter, passes = S->passes;
-        const auto trials = S->trials, iter_trials = S->iter_trials;
-        const auto tau = S->tau, gam = S->gam, sp = S->sig_prev, eta = S->eta, sig0 = S->sig0;
-        const auto c_alpha = S->c_alpha, gamma0 = S->gamma0, c_beta = S->c_beta, delta = S->delta;
-        const auto alpha_k = S->alpha_k, beta_k = S->beta_k;
-        const bool xy = S->variant == VAR_XY;
-        const double fval = S->G[ny];
+        const auto cnorm = cs.cnorm, bnorm = cs.bnorm, f_star = cs.f_star, tol = cs.tol;
+        const auto stop_rule = cs.stop_rule, m0 = cs.m0, n_soc = cs.n_soc, fresh = cs.fresh;
+        const auto kk = cs.k, ke = cs.ke, max_iter = cs.max_iter, passes = cs.passes;
+        const auto trials = cs.trials, iter_trials = cs.iter_trials;
+        const auto tau = cs.tau, gam = cs.gam, sp = cs.sig_prev, eta = cs.eta, sig0 = cs.sig0;
+        const auto c_alpha = cs.c_alpha, gamma0 = cs.gamma0, c_beta = cs.c_beta, delta = cs.delta;
+        const auto alpha_k = cs.alpha_k, beta_k = cs.beta_k;
+        const bool xy = cs.variant == VAR_XY;
+        const double fval = cs.fval;
         const double rel_dual = sqrt(tot[0]) / (1.0 + sqrt(tot[1]) + sqrt(tot[2]) + sqrt(tot[3]));
         const double rel_comp = sqrt(kv[0]) / (1.0 + cnorm);
         const double rel_pri = sqrt(kv[1]) / (1.0 + cnorm + bnorm);
@@ -1161,29 +1229,45 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
     // ---- 3. accepted candidate `dec`: ergodic sums (Algorithm 1) ----
     {
         const double tk = s_t;
-        const double *xn = S->xc[dec], *yn = S->yc[dec];
-        double *cx = S->cx, *cy = S->cy;
-        for (int j = tid; j < n; j += STEP_BS) cx[j] = fma(tk, xn[j], cx[j]);
-        for (int l = tid; l < ny; l += STEP_BS) cy[l] = fma(tk, yn[l], cy[l]);
+        const double *xn = xcp[0], *yn = ycp[0];
+#pragma unroll
+        for (int b = 1; b < B; ++b) {
+            if (dec == b) {
+                xn = xcp[b];
+                yn = ycp[b];
+            }
+        }
+        for (int j = tid; j < n; j += STEP_BS) cxp[j] = fma(tk, xn[j], cxp[j]);
+        for (int l = tid; l < ny; l += STEP_BS) cyp[l] = fma(tk, yn[l], cyp[l]);
     }
     __syncthreads();
     if (tid == 0) {
-        // as above: all reads first, then the stores
-        const auto tau = S->tau, eta = S->eta, gam = S->gam, T = S->T, mu = S->mu;
-        const auto c_nm = S->c_nm;
-        const auto tau_prev = S->tau_prev;
-        const auto c_alpha = S->c_alpha, gamma0 = S->gamma0, c_beta = S->c_beta;
-        const auto trials = S->trials, kk = S->k, ke = S->ke;
-        const auto restart = S->restart;
-        const auto restart_every = S->restart_every;
-        const auto ada_first = S->ada_first, ada_every = S->ada_every;
-        const auto restart_from_avg = S->restart_from_avg;
-        const bool xy = S->variant == VAR_XY;
-        const bool exact = S->dtype == DT_F64 && !S->incremental;
-        double *const x = S->x, *const xn = S->xc[dec], *const U = S->U, *const Un = S->Uc[dec];
-        double *const y = S->y, *const yn = S->yc[dec];
-        double *const Gp = S->Gp, *const G = S->G, *const Gn = S->Gc[dec];
-        double *const gxp = S->gxp, *const gxk = S->gxk;
+        const auto tau = cs.tau, eta = cs.eta, gam = cs.gam, T = cs.T, mu = cs.mu;
+        const auto c_nm = cs.c_nm;
+        const auto tau_prev = cs.tau_prev;
+        const auto c_alpha = cs.c_alpha, gamma0 = cs.gamma0, c_beta = cs.c_beta;
+        const auto trials = cs.trials, kk = cs.k, ke = cs.ke;
+        const auto restart = cs.restart;
+        const auto restart_every = cs.restart_every;
+        const auto ada_first = cs.ada_first, ada_every = cs.ada_every;
+        const auto restart_from_avg = cs.restart_from_avg;
+        const bool xy = cs.variant == VAR_XY;
+        const bool exact = cs.dtype == DT_F64 && !cs.incremental;
+        double *xn = cs.xc[0], *Un = cs.Uc[0], *yn = cs.yc[0], *Gn = cs.Gc[0];
+        double fn = cs.fc[0];
+#pragma unroll
+        for (int b = 1; b < B; ++b) {
+            if (dec == b) {
+                xn = cs.xc[b];
+                Un = cs.Uc[b];
+                yn = cs.yc[b];
+                Gn = cs.Gc[b];
+                fn = cs.fc[b];
+            }
+        }
+        double *const x = cs.x, *const U = cs.U, *const y = cs.y;
+        double *const Gp = cs.Gp, *const G = cs.G;
+        double *const gxp = cs.gxp, *const gxk = cs.gxk;
         double t = tau;
         for (int b = 0; b < dec; ++b) t *= eta;
         const double sig = gam * t;
@@ -1204,7 +1288,7 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
         S->Gp = G;
         S->G = Gn;
         S->Gc[dec] = Gp;
-        S->f = Gn[ny];
+        S->f = fn;
         S->fresh = exact ? 1 : 0;
         if (xy) {
             // grad_x Phi(x^k, y^k) becomes the previous iterate's; the next step kernel
@@ -1236,6 +1320,13 @@ __global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
 
     // ---- 4. restart (Algorithm 2) ----
     restart_epoch(S, rs);
+}
+
+template <int B>
+__global__ void __launch_bounds__(STEP_BS) k_ctrl(Slot *__restrict__ slots,
+                                                  const int *__restrict__ live)
+{
+    ctrl_slot<B>(slots + (live ? live[blockIdx.x] : (int)blockIdx.x));
 }
 
 // ---------------------------------------------------------------------------------------

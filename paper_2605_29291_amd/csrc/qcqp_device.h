@@ -110,7 +110,8 @@ struct Tile {
 };
 
 // ---- launch wrappers (kernels.hip) ----
-// one trial group for the slots listed in live[0..nslots); variants = HAS_YX | HAS_XY mask
+// one trial group for the slots listed in live[0..nslots) (live = NULL: slots 0..nslots-1);
+// variants = HAS_YX | HAS_XY mask
 // tiles[starts[b] .. starts[b+1]) go to pass block b (starts: min(pass_grid, ntiles) + 1 entries,
 // or NULL for equal tile counts per block)
 // Packed symmetric stack (options.sym_pass): for every stored matrix s, the tiles (I, J), I <= J,

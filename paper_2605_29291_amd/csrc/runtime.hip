@@ -998,7 +998,7 @@ qcqp_status qcqp_solve(qcqp_handle *h, const double *x0, const double *y0, doubl
     int64_t passes_before = 0;
     auto launch_chunk = [&](hipStream_t s, bool with_events, int set = 0) -> hipError_t {
         for (int64_t g = 0; g < poll; ++g) {
-            hipError_t e = launch_group(s, h->dslot, h->dlive0, 1, h->dtiles, ntiles, h->dstarts, h->B, h->dtype,
+            hipError_t e = launch_group(s, h->dslot, nullptr, 1, h->dtiles, ntiles, h->dstarts, h->B, h->dtype,
                                         h->hslot.variant == VAR_XY ? HAS_XY : HAS_YX, h->nblk_step, (int)std::max<int64_t>(h->ny, 1), (int)h->nw,
                                         (int)(h->m + 1 + h->p), h->pass_grid, h->nt,
                                         with_events ? ev[2 * (set * poll + g)] : nullptr,
@@ -1093,7 +1093,7 @@ static qcqp_status eval_loaded_point(qcqp_handle *h)
     HIPCHK(hipMemcpyAsync(h->dslot_eval, &S, sizeof(Slot), hipMemcpyHostToDevice, h->stream));
     HIPCHK(launch_pass_only(h->stream, h->dslot_eval, h->dtiles, (int)h->tiles.size(), h->dstarts, h->B, h->dtype, (int)h->nw, h->pass_grid, h->nt,
                             h->use_sym ? &h->sym : nullptr));
-    HIPCHK(launch_epi_anchor(h->stream, h->dslot_eval, h->dlive0, 1, (int)(h->m + 1 + h->p)));
+    HIPCHK(launch_epi_anchor(h->stream, h->dslot_eval, nullptr, 1, (int)(h->m + 1 + h->p)));
     return QCQP_OK;
 }
 
@@ -1448,6 +1448,7 @@ static qcqp_status rebuild_tiles(qcqp_batch *bt)
             t.slot = (int32_t)s;
             all.push_back(t);
         }
+
         bt->max_nblk = std::max(bt->max_nblk, h->nblk_step);
         bt->max_ny = std::max<int>(bt->max_ny, (int)h->ny);
         bt->max_nw = std::max<int>(bt->max_nw, (int)h->nw);
