@@ -153,14 +153,19 @@ typedef struct {
     qcqp_stop_rule stop_rule;  /* KKT (default) or PAPER */
     double f_star;             /* the optimal value the PAPER rule compares against */
     int sym_pass;              /* 1: the Q pass streams a second copy of the stack that holds
-                                  only the upper-triangle 128 x 128 tiles of each Q_i (about
-                                  half the bytes): each off-diagonal tile serves both its rows
+                                  only the upper-triangle tiles of each Q_i (about half the
+                                  bytes): each off-diagonal tile serves both its rows
                                   (Q_IJ w_J) and, transposed, its columns (Q_IJ' w_I), and a
                                   second kernel sums the per-tile results in a fixed order.
                                   Uses only the upper triangle, so Q_i must be symmetric (as
-                                  in the problem class).  F64 storage and single-instance
-                                  solves only (a batch refuses such a handle).  0: the
-                                  row-major pass (default). */
+                                  in the problem class).  F64 storage with direct passes
+                                  (128 x 128 tiles, FP64 sums), or BF16 / F16 storage with
+                                  incremental passes (256 x 256 tiles of the stored values,
+                                  FP32 products and tile sums, FP64 sum of the tiles; the
+                                  exact FP64 anchors stream the row-major stack; create
+                                  refuses a diagonal entry whose half is not exact in the
+                                  storage type).  Single-instance solves only (a batch
+                                  refuses such a handle).  0: the row-major pass (default). */
 } qcqp_options;
 
 typedef struct {

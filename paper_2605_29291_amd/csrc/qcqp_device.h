@@ -120,14 +120,25 @@ struct Tile {
 // column products Q_IJ' w_I; a second kernel adds them per output row in a fixed order.
 constexpr int SYM_T = 128;
 constexpr int SYM_TILE_STRIDE = SYM_T * SYM_T;   // doubles from one packed tile to the next
+// With 16-bit storage (dt = DT_BF16 / DT_F16) the tiles are SYM16_T x SYM16_T stored elements
+// (P16) and the per-tile results FP32 (ws16); only the trial passes of the incremental mode use
+// them (W_b = Q d_b), the anchors stream the row-major stack.
+constexpr int SYM16_T = 256;
+constexpr int SYM16_TILE = SYM16_T * SYM16_T;    // elements from one packed 16-bit tile to the next
 struct SymPass {
-    const double *P;         // nq * ntt packed tiles
+    const double *P;         // nq * ntt packed tiles (FP64 storage)
     double *ws;              // per tile: row results [B][SYM_T], then column results [B][SYM_T]
     const int32_t *ubase;    // output row of the first row of stored matrix s: (matrix index) n
-    int32_t n, NT, ntt, nq;  // NT = ceil(n / SYM_T) tiles per side, ntt = NT (NT + 1) / 2
+    int32_t n, NT, ntt, nq;  // NT = ceil(n / tile side) tiles per side, ntt = NT (NT + 1) / 2
     int32_t B;               // candidate slots of the workspace
+    int32_t dt;              // storage type of the packed tiles
+    const uint16_t *P16;     // 16-bit storage: nq * ntt packed tiles
+    float *ws16;             // 16-bit storage: per tile [2][B][SYM16_T] (rows, then columns)
 };
 hipError_t launch_sym_pack(hipStream_t s, const double *Q, int64_t ld, const SymPass &sp, double *P);
+// *inexact |= 1 when a diagonal entry's half is not exact in the storage type
+hipError_t launch_sym_pack16(hipStream_t s, const void *Q, int64_t ld, int dt, const SymPass &sp, void *P,
+                             unsigned *inexact);
 
 // one trial group; sym != NULL streams the packed symmetric stack instead of the tiles
 hipError_t launch_group(hipStream_t s, Slot *slots, const int *live, int nslots, const Tile *tiles,

@@ -178,10 +178,12 @@ __device__ __forceinline__ void pass_rows_lpr(int lpr, const void *Q, int n, siz
 // Block b of the pass grid streams the contiguous tile range [starts[b], starts[b+1]), ranges
 // of nearly equal bytes; w is staged into LDS when the block starts and again only when the
 // tile's slot changes (tiles are grouped by slot).
+// anchor_only: streams only for slots in anchor mode (their trial passes run on the packed
+// 16-bit stack)
 template <int DT, int B, bool NT>
 __global__ void __launch_bounds__(PASS_BS) k_pass(Slot *__restrict__ slots,
                                                   const Tile *__restrict__ tiles, int ntiles,
-                                                  const int *__restrict__ starts)
+                                                  const int *__restrict__ starts, int anchor_only)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     using AT = typename Store<DT>::acc_t;
@@ -207,7 +209,7 @@ __global__ void __launch_bounds__(PASS_BS) k_pass(Slot *__restrict__ slots,
             __syncthreads();   // every wave is done with the previous slot's w
             cur = t.slot;
             Slot *S = slots + cur;
-            active = S->status == ST_RUNNING;
+            active = S->status == ST_RUNNING && (!anchor_only || S->mode == MODE_ANCHOR);
             if (active) {
                 anchor = S->mode == MODE_ANCHOR;
                 inc = S->incremental != 0;
@@ -332,24 +334,25 @@ size_t pass_lds_bytes(int B, int dtype, int max_nw)
 
 template <int DT, int B>
 static void launch_pass_dt(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles,
-                           const int *starts, size_t lds, int grid, int nt)
+                           const int *starts, size_t lds, int grid, int nt, int anchor_only)
 {
-    if (nt) k_pass<DT, B, true><<<grid, PASS_BS, lds, s>>>(slots, tiles, ntiles, starts);
-    else k_pass<DT, B, false><<<grid, PASS_BS, lds, s>>>(slots, tiles, ntiles, starts);
+    if (nt) k_pass<DT, B, true><<<grid, PASS_BS, lds, s>>>(slots, tiles, ntiles, starts, anchor_only);
+    else k_pass<DT, B, false><<<grid, PASS_BS, lds, s>>>(slots, tiles, ntiles, starts, anchor_only);
 }
 
 template <int B>
 static void launch_pass_b(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles,
-                          const int *starts, int dtype, int max_nw, int grid, int nt)
+                          const int *starts, int dtype, int max_nw, int grid, int nt, int anchor_only = 0)
 {
-    const size_t lds = pass_lds_bytes(B, dtype, max_nw);
+    // an anchor-only launch stages the FP64 iterate alone
+    const size_t lds = anchor_only ? (size_t)max_nw * sizeof(double) : pass_lds_bytes(B, dtype, max_nw);
     if (grid > ntiles) grid = ntiles;
     if (grid < 1) grid = 1;
     switch (dtype) {
-    case DT_F64: launch_pass_dt<DT_F64, B>(s, slots, tiles, ntiles, starts, lds, grid, nt); break;
-    case DT_F32: launch_pass_dt<DT_F32, B>(s, slots, tiles, ntiles, starts, lds, grid, nt); break;
-    case DT_BF16: launch_pass_dt<DT_BF16, B>(s, slots, tiles, ntiles, starts, lds, grid, nt); break;
-    default: launch_pass_dt<DT_F16, B>(s, slots, tiles, ntiles, starts, lds, grid, nt); break;
+    case DT_F64: launch_pass_dt<DT_F64, B>(s, slots, tiles, ntiles, starts, lds, grid, nt, anchor_only); break;
+    case DT_F32: launch_pass_dt<DT_F32, B>(s, slots, tiles, ntiles, starts, lds, grid, nt, anchor_only); break;
+    case DT_BF16: launch_pass_dt<DT_BF16, B>(s, slots, tiles, ntiles, starts, lds, grid, nt, anchor_only); break;
+    default: launch_pass_dt<DT_F16, B>(s, slots, tiles, ntiles, starts, lds, grid, nt, anchor_only); break;
     }
 }
 
@@ -560,13 +563,18 @@ __device__ __forceinline__ void sym_tile(const double *__restrict__ q, int n, in
     u32x4 v[SYM_WIN];
 #pragma unroll
     for (int i = 0; i < SYM_WIN; ++i) v[i] = load(i);
+    // indices past n are clamped, so that the loads are issued unconditionally and go out
+    // together; their values are then replaced by zero
     double xj0[NB], xj1[NB], xi0[NB], xi1[NB], ca0[NB], ca1[NB];
+    const int jc0 = min(gc, n - 1), jc1 = min(gc + 1, n - 1);
+    const int ic0 = min(gi, n - 1), ic1 = min(gi + 1, n - 1);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        xj0[b] = cval ? w[b][gc] : 0.0;
-        xj1[b] = gc + 1 < n ? w[b][gc + 1] : 0.0;
-        xi0[b] = gi < n ? w[b][gi] : 0.0;
-        xi1[b] = gi + 1 < n ? w[b][gi + 1] : 0.0;
+        const double a0 = w[b][jc0], a1 = w[b][jc1], b0 = w[b][ic0], b1 = w[b][ic1];
+        xj0[b] = cval ? a0 : 0.0;
+        xj1[b] = gc + 1 < n ? a1 : 0.0;
+        xi0[b] = gi < n ? b0 : 0.0;
+        xi1[b] = gi + 1 < n ? b1 : 0.0;
         ca0[b] = 0.0;
         ca1[b] = 0.0;
     }
@@ -688,10 +696,341 @@ static void launch_sym_b(hipStream_t s, Slot *slots, const SymPass &sp)
     k_sred<B><<<sp.nq * sp.NT, SYM_T, 0, s>>>(slots, sp);
 }
 
+// ---------------------------------------------------------------------------------------
+// Packed symmetric pass for 16-bit storage (BF16 / FP16), trial passes of the incremental mode:
+// W_b = Q_i d_b, d_b = x_b - x, with FP32 products and sums.  Tiles of SYM16_T x SYM16_T
+// elements (128 KB, as the FP64 tiles): one 16-byte load per lane covers 8 elements, so a row
+// of the tile is 32 lanes and one load instruction of the wave covers two rows (lanes 0..31 row
+// 2k, lanes 32..63 row 2k + 1).  The wave streams the tile's rows in order with SYM16_WIN
+// instructions in flight (the rolling window of the FP64 tiles).  Row dots: 8 products per lane,
+// then over the row's 32 lanes by a transposing step that pairs two instructions (one permlane16
+// swap) and four DPP rotations inside 16-lane rows.  Column dots: each lane keeps its 8 columns
+// over the rows of its half of the wave (d_I from LDS), the halves are added at the end.  Results
+// are FP32 per tile; k_sred16 adds them per output row in FP64 in a fixed order.
+
+constexpr int SYM16_WIN = 16;  // load instructions in flight per wave (2 rows each)
+constexpr int SYM16_GRP = 2;   // instructions per transposing reduction (4 rows)
+
+__global__ void __launch_bounds__(256) k_sym_pack16(const uint16_t *__restrict__ Q, int64_t ld, int dt,
+                                                    SymPass sp, uint16_t *__restrict__ P,
+                                                    unsigned *__restrict__ inexact)
+{
+    const int t = blockIdx.x;
+    const int s = t / sp.ntt;
+    int I, J;
+    sym_tile_ij(t - s * sp.ntt, sp.NT, I, J);
+    uint16_t *dst = P + (size_t)t * SYM16_TILE;
+    const uint16_t *src = Q + (size_t)s * sp.n * ld;
+    // a diagonal tile keeps its upper triangle with half the diagonal (exact unless the half
+    // would be subnormal in the storage type, which is flagged)
+    for (int e = threadIdx.x; e < SYM16_TILE; e += 256) {
+        const int r = e / SYM16_T, c = e % SYM16_T;
+        const int gr = I * SYM16_T + r, gc = J * SYM16_T + c;
+        uint16_t v = (gr < sp.n && gc < sp.n) ? src[(size_t)gr * ld + gc] : (uint16_t)0;
+        if (I == J) {
+            if (c < r) {
+                v = 0;
+            } else if (c == r) {
+                float f = dt == DT_BF16 ? __uint_as_float((uint32_t)v << 16)
+                                        : (float)__builtin_bit_cast(_Float16, v);
+                const float h = 0.5f * f;
+                uint16_t hv;
+                if (dt == DT_BF16) {
+                    hv = (uint16_t)(__float_as_uint(h) >> 16);
+                    if (__uint_as_float((uint32_t)hv << 16) != h) atomicOr(inexact, 1u);
+                } else {
+                    const _Float16 hh = (_Float16)h;
+                    hv = __builtin_bit_cast(uint16_t, hh);
+                    if ((float)hh != h) atomicOr(inexact, 1u);
+                }
+                v = hv;
+            }
+        }
+        dst[e] = v;
+    }
+}
+
+hipError_t launch_sym_pack16(hipStream_t s, const void *Q, int64_t ld, int dt, const SymPass &sp, void *P,
+                             unsigned *inexact)
+{
+    const int ntiles = sp.nq * sp.ntt;
+    if (ntiles > 0)
+        k_sym_pack16<<<ntiles, 256, 0, s>>>(static_cast<const uint16_t *>(Q), ld, dt, sp,
+                                            static_cast<uint16_t *>(P), inexact);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ void swap16f(float &a, float &b)
+{
+    // lanes 16..31 (48..63) of a <-> lanes 0..15 (32..47) of b
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+
+template <int K>
+__device__ __forceinline__ float row_rorf(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x120 + K, 0xf, 0xf, false));
+}
+
+// p0: each lane's share of rows 2k (lanes 0..31) and 2k+1 (lanes 32..63); p1 the same for
+// instruction k+1.  Returns in every lane of 16-lane row q the full sum of tile row
+// 2k + {0, 2, 1, 3}[q] (lanes 0..15: row 2k, 16..31: 2k+2, 32..47: 2k+1, 48..63: 2k+3)
+__device__ __forceinline__ float reduce2f(float p0, float p1)
+{
+    swap16f(p0, p1);
+    float t = p0 + p1;
+    t += row_rorf<8>(t);
+    t += row_rorf<4>(t);
+    t += row_rorf<2>(t);
+    t += row_rorf<1>(t);
+    return t;
+}
+
+// Calls f(integral_constant<int, G>) for G = G0, G0 + 1, ... while G < GN and
+// G * 2 * SYM16_GRP < rows (4 rows per group)
+template <int G0, int GN>
+struct Group16Loop {
+    template <typename F>
+    __device__ __forceinline__ static void run(F &&f, int rows)
+    {
+        if constexpr (G0 < GN) {
+            if (G0 * 2 * SYM16_GRP < rows) {
+                f(std::integral_constant<int, G0>{});
+                Group16Loop<G0 + 1, GN>::run(f, rows);
+            }
+        }
+    }
+};
+
+template <int DT, int NB>
+__device__ __forceinline__ void sym16_tile(const uint16_t *__restrict__ q, int n, int I, int J,
+                                           const double *const (&xc)[NB], const double *__restrict__ x,
+                                           float *__restrict__ res, int Bw, float (*__restrict__ wi)[SYM16_T],
+                                           float (*__restrict__ rbuf)[SYM16_T])
+{
+    using T = Store<DT>;
+    // four candidates take more registers per group: a shorter window keeps 3 waves per SIMD
+    constexpr int WIN = NB >= 4 ? 12 : SYM16_WIN;
+    constexpr int NSLOT = WIN / SYM16_GRP;          // groups in flight
+    const int lane = threadIdx.x & 63;
+    const int half = lane >> 5;
+    const int c8 = (lane & 31) * 8;
+    const int gc = J * SYM16_T + c8;
+    const int rmax = min(SYM16_T, n - I * SYM16_T);
+    const __amdgpu_buffer_rsrc_t rs = tile_rsrc(q, rmax * SYM16_T * 2);
+    const int voff = gc < n ? c8 * 2 : OFF_NONE;
+    const int dmask = I == J ? OFF_NONE : 0;
+    // row r of the tile in this lane's half; on the diagonal tile a lane whose eight columns
+    // all lie below the diagonal (c8 + 7 < r) reads nothing (the packed tile holds zeros there)
+    auto load = [&](int k) -> u32x4 {
+        const int r = 2 * k + half;
+        const int vo = voff | (dmask & ((c8 + 7 - r) >> 31));
+        return __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, vo, r * SYM16_T * 2, BUF_NT));
+    };
+    // d_J of the lane's eight columns and d_I of the tile's rows (FP32 of the FP64 differences,
+    // zero past n): the loads go out before the window and are converted behind it, so the first
+    // group waits for them and the first rows only (with three or more candidates they are
+    // converted before the window, which keeps the registers within the occupancy budget).
+    // Indices past n are clamped, so that every load is issued unconditionally; their values
+    // are then replaced by zero.
+    double xi[SYM16_T / 64], ci[NB][SYM16_T / 64];
+    float dj[NB][8];
+    double xj[NB <= 2 ? 8 : 1], cj[NB <= 2 ? NB : 1][NB <= 2 ? 8 : 1];
+    auto convert_dj = [&]() {
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) dj[b][e] = gc + e < n ? (float)(cj[b][e] - xj[e]) : 0.0f;
+    };
+    if constexpr (NB <= 2) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int j = min(gc + e, n - 1);
+            xj[e] = x[j];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) cj[b][e] = xc[b][j];
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int j = min(gc + e, n - 1);
+            const double xv = x[j];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const float d = (float)(xc[b][j] - xv);
+                dj[b][e] = gc + e < n ? d : 0.0f;
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < SYM16_T / 64; ++u) {
+        const int gr = min(I * SYM16_T + lane + 64 * u, n - 1);
+        xi[u] = x[gr];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) ci[b][u] = xc[b][gr];
+    }
+    // (a wave's LDS accesses complete in order: the group loop reads these writes)
+    auto store_di = [&]() {
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int u = 0; u < SYM16_T / 64; ++u)
+                wi[b][lane + 64 * u] = lane + 64 * u < rmax ? (float)(ci[b][u] - xi[u]) : 0.0f;
+    };
+    if constexpr (NB > 2) store_di();
+    u32x4 v[WIN];
+#pragma unroll
+    for (int i = 0; i < WIN; ++i) v[i] = load(i);
+    if constexpr (NB <= 2) {
+        convert_dj();
+        store_di();
+    }
+    (void)convert_dj;
+    float ca[NB][8];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) ca[b][e] = 0.0f;
+    Group16Loop<0, SYM16_T / (2 * SYM16_GRP)>::run(
+        [&](auto gconst) {
+            constexpr int G = decltype(gconst)::value;
+            constexpr int s0 = (G % NSLOT) * SYM16_GRP;   // the group's window slots
+            constexpr int k0 = G * SYM16_GRP;             // its first load instruction
+            __builtin_amdgcn_sched_barrier(0);
+            float rp[SYM16_GRP][NB];
+#pragma unroll
+            for (int i = 0; i < SYM16_GRP; ++i) {
+                float qv[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) qv[e] = T::get(v[s0 + i], e);
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    float a = qv[0] * dj[b][0];
+#pragma unroll
+                    for (int e = 1; e < 8; ++e) a = fmaf(qv[e], dj[b][e], a);
+                    rp[i][b] = a;
+                    const float dv = wi[b][2 * (k0 + i) + half];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) ca[b][e] = fmaf(qv[e], dv, ca[b][e]);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            // the group's rows are consumed: refill its slots with the instructions WIN ahead
+            if constexpr (2 * (k0 + WIN) < SYM16_T) {
+#pragma unroll
+                for (int i = 0; i < SYM16_GRP; ++i) v[s0 + i] = load(k0 + WIN + i);
+            }
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const float t = reduce2f(rp[0][b], rp[1][b]);
+                // 16-lane row g holds tile row 2 k0 + {0, 2, 1, 3}[g]
+                if ((lane & 15) == 0) rbuf[b][2 * k0 + ((lane >> 4) & 1) * 2 + (lane >> 5)] = t;
+            }
+        },
+        rmax);
+    __builtin_amdgcn_sched_barrier(0);
+    // row results (rows past rmax are never read), then the column results: the two halves of
+    // the wave add in a fixed order (lower half first)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int u = 0; u < SYM16_T / 64; ++u) res[b * SYM16_T + lane + 64 * u] = rbuf[b][lane + 64 * u];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float o = __shfl_xor(ca[b][e], 32, 64);
+            if (half == 0) res[(size_t)(Bw + b) * SYM16_T + c8 + e] = ca[b][e] + o;
+        }
+    }
+}
+
+template <int DT, int B>
+__global__ void __launch_bounds__(64, SYM_WAVES) k_spass16(Slot *__restrict__ slots, SymPass sp)
+{
+    __shared__ float wi[B][SYM16_T];
+    __shared__ float rbuf[B][SYM16_T];
+    Slot *S = slots;
+    if (S->status != ST_RUNNING || S->mode != MODE_TRIAL) return;
+    const int t = blockIdx.x;
+    const int s = t / sp.ntt;
+    int I, J;
+    sym_tile_ij(t - s * sp.ntt, sp.NT, I, J);
+    const uint16_t *q = sp.P16 + (size_t)t * SYM16_TILE;
+    float *res = sp.ws16 + (size_t)t * 2 * sp.B * SYM16_T;
+    const double *xc[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) xc[b] = S->xc[b];
+    sym16_tile<DT, B>(q, sp.n, I, J, xc, S->x, res, sp.B, wi, rbuf);
+}
+
+// W_b rows of tile row I of stored matrix s: the row results of tiles (I, J >= I), then the column
+// results of tiles (K <= I, I), each converted to FP64 and added in that order
+template <int B>
+__global__ void __launch_bounds__(SYM16_T) k_sred16(Slot *__restrict__ slots, SymPass sp)
+{
+    Slot *S = slots;
+    if (S->status != ST_RUNNING || S->mode != MODE_TRIAL) return;
+    const int s = blockIdx.x / sp.NT, I = blockIdx.x % sp.NT;
+    const int rr = threadIdx.x, gr = I * SYM16_T + rr;
+    if (gr >= sp.n) return;
+    const size_t stride = (size_t)2 * sp.B * SYM16_T;
+    const size_t ob = (size_t)sp.ubase[s] + gr;
+    const int nrow = sp.NT - I, nterm = sp.NT + 1;
+    for (int b = 0; b < B; ++b) {
+        double v = 0.0;
+        for (int k0 = 0; k0 < nterm; k0 += 8) {
+            float t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = k0 + u;
+                t[u] = 0.0f;
+                if (k < nterm) {
+                    t[u] = k < nrow
+                               ? sp.ws16[(size_t)sym_tile_index(s, I, I + k, sp.NT, sp.ntt) * stride + b * SYM16_T + rr]
+                               : sp.ws16[(size_t)sym_tile_index(s, k - nrow, I, sp.NT, sp.ntt) * stride +
+                                         (size_t)(sp.B + b) * SYM16_T + rr];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (k0 + u < nterm) v += (double)t[u];
+        }
+        S->W[b][ob] = v;
+    }
+}
+
+template <int DT, int B>
+static void launch_sym16_dt(hipStream_t s, Slot *slots, const SymPass &sp)
+{
+    const int ntiles = sp.nq * sp.ntt;
+    if (ntiles <= 0) return;
+    k_spass16<DT, B><<<ntiles, 64, 0, s>>>(slots, sp);
+    k_sred16<B><<<sp.nq * sp.NT, SYM16_T, 0, s>>>(slots, sp);
+}
+
+template <int B>
+static void launch_sym16_b(hipStream_t s, Slot *slots, const SymPass &sp)
+{
+    if (sp.dt == DT_BF16) launch_sym16_dt<DT_BF16, B>(s, slots, sp);
+    else launch_sym16_dt<DT_F16, B>(s, slots, sp);
+}
+
 hipError_t launch_pass_only(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles,
                             const int *starts, int B, int dtype, int max_nw, int pass_grid, int nt,
                             const SymPass *sym)
 {
+    if (sym && sym->dt != DT_F64) {
+        // 16-bit storage: anchors (exact FP64 accumulation at the iterate) stream the row-major
+        // stack; the trial passes stream the packed tiles
+        switch (B) {
+        case 1: launch_pass_b<1>(s, slots, tiles, ntiles, starts, dtype, max_nw, pass_grid, nt, 1); launch_sym16_b<1>(s, slots, *sym); break;
+        case 2: launch_pass_b<2>(s, slots, tiles, ntiles, starts, dtype, max_nw, pass_grid, nt, 1); launch_sym16_b<2>(s, slots, *sym); break;
+        case 3: launch_pass_b<3>(s, slots, tiles, ntiles, starts, dtype, max_nw, pass_grid, nt, 1); launch_sym16_b<3>(s, slots, *sym); break;
+        default: launch_pass_b<4>(s, slots, tiles, ntiles, starts, dtype, max_nw, pass_grid, nt, 1); launch_sym16_b<4>(s, slots, *sym); break;
+        }
+        return hipGetLastError();
+    }
     if (sym) {
         switch (B) {
         case 1: launch_sym_b<1>(s, slots, *sym); break;

@@ -370,8 +370,10 @@ static qcqp_status validate_options(const qcqp_options *o)
     if (o->pass_mode < QCQP_PASS_AUTO || o->pass_mode > QCQP_PASS_INCREMENTAL)
         return fail(QCQP_E_INVALID, "unknown pass mode");
     if (o->sym_pass != 0 && o->sym_pass != 1) return fail(QCQP_E_INVALID, "sym_pass must be 0 or 1");
-    if (o->sym_pass && (o->storage != QCQP_F64 || o->pass_mode == QCQP_PASS_INCREMENTAL))
-        return fail(QCQP_E_INVALID, "sym_pass needs F64 storage and direct passes");
+    if (o->sym_pass && o->storage == QCQP_F64 && o->pass_mode == QCQP_PASS_INCREMENTAL)
+        return fail(QCQP_E_INVALID, "sym_pass with F64 storage needs direct passes");
+    if (o->sym_pass && (o->storage == QCQP_F32 || (o->storage != QCQP_F64 && o->pass_mode == QCQP_PASS_DIRECT)))
+        return fail(QCQP_E_INVALID, "sym_pass needs F64 storage, or BF16/F16 storage with incremental passes");
     return QCQP_OK;
 }
 
@@ -651,7 +653,45 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
     }
 
     // ---- options.sym_pass: the packed upper-triangle copy of the stack ----
-    if (o.sym_pass && nq > 0) {
+    if (o.sym_pass && nq > 0 && h->dtype != DT_F64) {
+        // 16-bit storage: SYM16_T-wide tiles of the stored values, FP32 per-tile results
+        const int32_t NT = (int32_t)((n + SYM16_T - 1) / SYM16_T);
+        const int64_t ntt = (int64_t)NT * (NT + 1) / 2;
+        const size_t pbytes = (size_t)nq * ntt * SYM16_TILE * 2;
+        const size_t wbytes = (size_t)nq * ntt * 2 * h->B * SYM16_T * sizeof(float);
+        std::vector<int32_t> ub;
+        for (int64_t i = 0; i <= m; ++i)
+            if (qmap[i] >= 0) ub.push_back((int32_t)(i * n));
+        const size_t nub = ub.size();
+        ub.push_back(0);   // the packing's inexact-halving flag
+        if (hipMalloc(&h->dP, pbytes) != hipSuccess || hipMalloc(&h->dws, wbytes) != hipSuccess ||
+            hipMalloc(&h->dubase, ub.size() * sizeof(int32_t)) != hipSuccess) {
+            free_handle_memory(h);
+            delete h;
+            return fail(QCQP_E_NOMEM, "packed symmetric stack (%zu bytes)", pbytes + wbytes);
+        }
+        h->sym = SymPass{nullptr, nullptr, h->dubase, (int32_t)n, NT, (int32_t)ntt, (int32_t)nq, (int32_t)h->B,
+                         h->dtype, reinterpret_cast<const uint16_t *>(h->dP), reinterpret_cast<float *>(h->dws)};
+        unsigned *inexact = reinterpret_cast<unsigned *>(h->dubase + nub);
+        unsigned flag = 0;
+        hipError_t e = hipMemcpyAsync(h->dubase, ub.data(), ub.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                      h->stream);
+        if (e == hipSuccess) e = launch_sym_pack16(h->stream, h->dQ, h->ld, h->dtype, h->sym, h->dP, inexact);
+        if (e == hipSuccess) e = hipMemcpyAsync(&flag, inexact, sizeof(flag), hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);   // ub is read by the copy
+        if (e != hipSuccess) {
+            free_handle_memory(h);
+            delete h;
+            return fail(QCQP_E_DEVICE, "packing the symmetric stack: %s", hipGetErrorString(e));
+        }
+        if (flag) {
+            free_handle_memory(h);
+            delete h;
+            return fail(QCQP_E_INVALID, "sym_pass: a diagonal entry of Q is too small to halve exactly in the storage type");
+        }
+        h->use_sym = true;
+        h->sym_bytes = pbytes + wbytes + ub.size() * sizeof(int32_t);
+    } else if (o.sym_pass && nq > 0) {
         const int32_t NT = (int32_t)((n + SYM_T - 1) / SYM_T);
         const int64_t ntt = (int64_t)NT * (NT + 1) / 2;
         const size_t pbytes = (size_t)nq * ntt * SYM_TILE_STRIDE * sizeof(double);
@@ -665,7 +705,8 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
             delete h;
             return fail(QCQP_E_NOMEM, "packed symmetric stack (%zu bytes)", pbytes + wbytes);
         }
-        h->sym = SymPass{h->dP, h->dws, h->dubase, (int32_t)n, NT, (int32_t)ntt, (int32_t)nq, (int32_t)h->B};
+        h->sym = SymPass{h->dP, h->dws, h->dubase, (int32_t)n, NT, (int32_t)ntt, (int32_t)nq, (int32_t)h->B,
+                         DT_F64, nullptr, nullptr};
         hipError_t e = hipMemcpyAsync(h->dubase, ub.data(), ub.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                                       h->stream);
         if (e == hipSuccess) e = launch_sym_pack(h->stream, (const double *)h->dQ, h->ld, h->sym, h->dP);
@@ -940,7 +981,7 @@ static void fill_info(const qcqp_handle *h, const Slot &S, qcqp_info *info, doub
     info->timed_passes = timed;
     info->last_gap = S.last_gap;
     info->stop_value = S.crit;
-    info->pass_bytes = h->use_sym ? (int64_t)h->nq * (h->n * (h->n + 1) / 2) * 8
+    info->pass_bytes = h->use_sym ? (int64_t)h->nq * (h->n * (h->n + 1) / 2) * elem_size(h->dtype)
                                   : (int64_t)h->nq * h->n * h->n * elem_size(h->dtype);
     switch (S.status) {
     case ST_CONVERGED: info->status = QCQP_OK; break;
@@ -1221,7 +1262,7 @@ qcqp_status qcqp_eval_trial_pass(qcqp_handle *h, const double *x, const double *
     double *res[MAXB];
     for (int b = 0; b < h->B; ++b) {
         HIPCHK(hipMemcpyAsync(S.xc[b], xc + b * n, n * 8, kin, h->stream));
-        res[b] = (h->incremental && !h->use_sym) ? S.W[b] : S.Uc[b];
+        res[b] = h->incremental ? S.W[b] : S.Uc[b];
         HIPCHK(hipMemsetAsync(res[b], 0, un * 8, h->stream));   // rows of matrices not stored
     }
     HIPCHK(hipMemcpyAsync(h->dslot_eval, &S, sizeof(Slot), hipMemcpyHostToDevice, h->stream));

@@ -1,0 +1,121 @@
+"""The packed symmetric pass for 16-bit storage (sym_pass with BF16 / FP16, incremental mode).
+
+Only the upper-triangle tiles of each stored Q_i are streamed (256 x 256 stored elements per
+tile, the diagonal tiles with half the diagonal); each tile gives its row dots Q_IJ d_J and its
+column dots Q_IJ' d_I.  Products and tile partial sums are FP32, the per-row sum of the tiles'
+partials is FP64.
+
+* Trial pass, element by element against the oracle's FP64 (Q_i d)_r on the same stored values:
+  d_b is rounded to FP32 once; a column partial is a chain of at most 128 FP32 fused
+  multiply-adds plus one addition, a row partial 8 products and 5 additions, and the per-row
+  sum over at most n/256 + 1 tile partials runs in FP64, so with u = 2^-24, k = 136 and
+  gamma_k = k u / (1 - k u):  |W_ir - (Q_i d)_r| <= (u + gamma_k + 2^-46) S_ir,
+  S_ir = sum_j |Q_ij| |d_j|.  A zero step gives W = 0 exactly.
+* Whole solves: the result's relative KKT residual, evaluated by the oracle in FP64 on the stored
+  instance, is <= 1e-6, with the objective of the row-major BF16 solve to 1e-6 relative.
+* Refusals: FP32 storage, and 16-bit storage with direct passes.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from tests.gpu_common import abs_products, announce, oracle, qi, tau_bar_of, to_np
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def _bound():
+    k = 136
+    return U32 + k * U32 / (1.0 - k * U32) + 2.0 ** -46
+
+
+def _points(n, B, seed, lb=-10.0, ub=10.0):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0.5 * lb, 0.5 * ub, n)
+    xc = np.empty((B, n))
+    for b in range(B):
+        xc[b] = np.clip(x + 0.7 ** b * 0.05 * rng.standard_normal(n), lb, ub)
+    return x, xc
+
+
+@pytest.mark.parametrize("storage", ["bfloat16", "float16"])
+@pytest.mark.parametrize("n,B", [(333, 3), (1100, 4), (256, 1), (97, 2)])
+def test_sym16_trial_pass_parity(storage, n, B):
+    from paper_2605_29291_amd import Solver
+    m = 4
+    inst = qi.round_instance(qi.random_qcqp(n, m, seed=7100 + n, shift=0.01), storage)
+    announce(f"sym16 trial pass {storage} n={n} m={m} B={B}")
+    s = Solver(inst, storage=storage, tau_bar=1.0, spec_trials=B, sym_pass=1)
+    x, xc = _points(n, B, seed=n + B)
+    if B > 1:
+        xc[B - 1] = x                                   # a zero step
+    W = to_np(s.eval_trial_pass(x, xc))
+    s.close()
+    P = oracle.Problem(inst)
+    c = _bound()
+    worst = 0.0
+    for b in range(B):
+        d = xc[b] - x
+        ref = oracle.operator(P, d)["U"]
+        if not d.any():
+            np.testing.assert_array_equal(W[b], 0.0)
+            continue
+        S = abs_products(inst, d)
+        err = np.abs(W[b] - ref)
+        r = float(np.max(err / np.maximum(S, 1e-300)))
+        assert np.all(err <= c * S), (b, r, c)
+        worst = max(worst, r)
+    assert worst > 1e-10, worst     # the sums really run in FP32
+    announce(f"  max |dW| / S = {worst:.2e} (bound {c:.2e})")
+
+
+@pytest.mark.parametrize("storage", ["bfloat16", "float16"])
+def test_sym16_solve_reaches_the_oracle_kkt(storage):
+    from paper_2605_29291_amd import Solver
+    inst = qi.round_instance(qi.random_qcqp(700, 12, seed=7200, shift=0.01), storage)
+    kw = dict(storage=storage, tau_bar=tau_bar_of(inst), gamma0=0.1, spec_trials=2)
+    announce(f"sym16 solve {storage} n=700")
+    s = Solver(inst, sym_pass=1, **kw)
+    x, y, info = s.solve()
+    s.close()
+    assert info["status"] == "ok", info
+    assert info["pass_bytes"] == 13 * (700 * 701 // 2) * 2
+    kk = oracle.kkt(oracle.Problem(inst), to_np(x), to_np(y))
+    assert kk["rel_kkt"] <= 1e-6, kk
+    assert abs(kk["rel_kkt"] - info["rel_kkt"]) <= 1e-9
+    s = Solver(inst, sym_pass=0, **kw)
+    _, _, ref = s.solve()
+    s.close()
+    assert abs(info["f"] - ref["f"]) <= 1e-6 * (1 + abs(ref["f"])), (info["f"], ref["f"])
+    announce(f"  iters {info['iters']} (row-major {ref['iters']}), f {info['f']:.10f} ({ref['f']:.10f})")
+
+
+def test_sym16_config3_full_size_kkt():
+    """n = 4000, m = 200, BF16 (3.2 GB of packed tiles): oracle-evaluated relative KKT <= 1e-6."""
+    import torch
+    from paper_2605_29291_amd import Solver
+    announce("sym16 full size n=4000 m=200 bfloat16")
+    inst = qi.random_qcqp_torch(4000, 200, qi.config_seed(3), shift=0.01, device="cuda",
+                                store_dtype=torch.bfloat16)
+    s = Solver(inst, device=True, storage="bfloat16", tau_bar=0.0, gamma0=0.1, sym_pass=1)
+    x, y, info = s.solve()
+    s.close()
+    assert info["status"] == "ok", info
+    import dataclasses
+    host = dataclasses.replace(inst, Q=inst.Q.cpu())
+    del inst
+    torch.cuda.empty_cache()
+    kk = oracle.kkt(oracle.Problem(host), to_np(x), to_np(y))
+    assert kk["rel_kkt"] <= 1e-6, kk
+
+
+def test_sym16_refusals():
+    from paper_2605_29291_amd import QCQPError, Solver, abi
+    inst = qi.random_qcqp(60, 2, seed=7300, shift=0.01)
+    for kw in (dict(storage="float32"), dict(storage="bfloat16", pass_mode="direct")):
+        with pytest.raises(QCQPError) as e:
+            Solver(qi.round_instance(inst, kw["storage"]), tau_bar=1.0, sym_pass=1, **kw)
+        assert e.value.code == abi.E_INVALID and "sym_pass" in str(e.value)

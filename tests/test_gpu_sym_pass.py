@@ -13,7 +13,8 @@ The packed stack holds only the upper-triangle 128 x 128 tiles of every Q_i; the
 * final solutions: relative KKT <= 1e-6 evaluated by the oracle; two solves bitwise equal;
 * the random convex QCQP n = 2000, m = 100 (the config-2 workload): converged, relative KKT of
   the returned point by the oracle's evaluation <= 1e-6;
-* refusals: 16-bit storage with sym_pass, and a batch admitting a sym_pass handle.
+* refusals: FP32 storage with sym_pass, and a batch admitting a sym_pass handle (16-bit
+  storage: tests/test_gpu_sym16.py).
 """
 import dataclasses
 
@@ -171,7 +172,7 @@ def test_sym_refusals():
     inst = qi.random_qcqp(100, 2, seed=45, shift=0.01)
     announce("sym refusals")
     with pytest.raises(QCQPError) as e:
-        _solver(qi.round_instance(inst, "bfloat16"), storage="bfloat16", tau_bar=1.0, sym_pass=1)
+        _solver(qi.round_instance(inst, "float32"), storage="float32", tau_bar=1.0, sym_pass=1)
     assert e.value.code == 1
     s = _solver(inst, tau_bar=1.0, sym_pass=1)
     b = Batch(max_slots=2)
