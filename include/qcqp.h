@@ -182,7 +182,8 @@ typedef struct {
     double pass_seconds;       /* summed Q-pass kernel time (only with options.timing) */
     double last_gap;           /* last G_xi value (NaN if none) */
     int64_t pass_bytes;        /* algorithmic HBM bytes of one Q pass: (m+has_q0) n^2 sizeof(storage);
-                                  with sym_pass the upper triangles, (m+has_q0) n(n+1)/2 x 8 */
+                                  with sym_pass the upper triangles,
+                                  (m+has_q0) n(n+1)/2 sizeof(storage) */
     int64_t timed_passes;      /* Q passes covered by pass_seconds */
     double stop_value;         /* the stop rule's value at the returned iterate */
 } qcqp_info;
