@@ -2084,14 +2084,15 @@ template <int B>
 static hipError_t group_b(hipStream_t s, Slot *slots, const int *live, int nslots, const Tile *tiles, int ntiles,
                           const int *starts,
                           int dtype, int variants, int max_nblk_step, int max_ny, int max_nw, int max_epi,
-                          int pass_grid, int nt, hipEvent_t ev0, hipEvent_t ev1, const SymPass *sym)
+                          int pass_grid, int nt, hipEvent_t ev0, hipEvent_t ev1, const SymPass *sym,
+                          const Sym16Launch *s16)
 {
     const size_t step_lds = (size_t)(B + 1) * (size_t)(max_ny > 0 ? max_ny : 1) * sizeof(double);
     const dim3 vgrid(max_nblk_step, nslots);
     if (variants & HAS_YX) k_step<B><<<vgrid, STEP_BS, step_lds, s>>>(slots, live);
     if (variants & HAS_XY) k_step_xy<B><<<vgrid, STEP_BS, step_lds, s>>>(slots, live);
     if (ev0) (void)hipEventRecord(ev0, s);
-    (void)launch_pass_only(s, slots, tiles, ntiles, starts, B, dtype, max_nw, pass_grid, nt, sym);
+    (void)launch_pass_only(s, slots, tiles, ntiles, starts, B, dtype, max_nw, pass_grid, nt, sym, s16);
     if (ev1) (void)hipEventRecord(ev1, s);
     k_epi<B><<<dim3(max_epi, nslots), STEP_BS, 0, s>>>(slots, live);
     if (variants & HAS_XY) k_post_xy<B><<<vgrid, STEP_BS, step_lds, s>>>(slots, live);
@@ -2102,13 +2103,14 @@ static hipError_t group_b(hipStream_t s, Slot *slots, const int *live, int nslot
 hipError_t launch_group(hipStream_t s, Slot *slots, const int *live, int nslots, const Tile *tiles,
                         int ntiles, const int *starts, int B, int dtype, int variants,
                         int max_nblk_step, int max_ny, int max_nw, int max_epi, int pass_grid,
-                        int nt, hipEvent_t ev0, hipEvent_t ev1, const SymPass *sym)
+                        int nt, hipEvent_t ev0, hipEvent_t ev1, const SymPass *sym,
+                        const Sym16Launch *s16)
 {
     switch (B) {
-    case 1: return group_b<1>(s, slots, live, nslots, tiles, ntiles, starts, dtype, variants, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1, sym);
-    case 2: return group_b<2>(s, slots, live, nslots, tiles, ntiles, starts, dtype, variants, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1, sym);
-    case 3: return group_b<3>(s, slots, live, nslots, tiles, ntiles, starts, dtype, variants, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1, sym);
-    default: return group_b<4>(s, slots, live, nslots, tiles, ntiles, starts, dtype, variants, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1, sym);
+    case 1: return group_b<1>(s, slots, live, nslots, tiles, ntiles, starts, dtype, variants, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1, sym, s16);
+    case 2: return group_b<2>(s, slots, live, nslots, tiles, ntiles, starts, dtype, variants, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1, sym, s16);
+    case 3: return group_b<3>(s, slots, live, nslots, tiles, ntiles, starts, dtype, variants, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1, sym, s16);
+    default: return group_b<4>(s, slots, live, nslots, tiles, ntiles, starts, dtype, variants, max_nblk_step, max_ny, max_nw, max_epi, pass_grid, nt, ev0, ev1, sym, s16);
     }
 }
 

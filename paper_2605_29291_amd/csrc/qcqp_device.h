@@ -136,18 +136,35 @@ struct SymPass {
     float *ws16;             // 16-bit storage: per tile [2][B][SYM16_T] (rows, then columns)
 };
 hipError_t launch_sym_pack(hipStream_t s, const double *Q, int64_t ld, const SymPass &sp, double *P);
+// Launch description of the 16-bit packed trial passes of one or more slots
+struct Sym16Launch {
+    int32_t dt, B;           // storage type (DT_BF16 / DT_F16) and candidates
+    const SymPass *descs;    // device, indexed by slot: each packed slot's tiles and results
+    const int2 *work;        // device: (slot, tile) per block of the tile kernel; NULL: slot 0,
+                             // tile = block
+    int32_t nwork;
+    const int2 *work_r;      // device: (slot, s NT + I) per block of the row sums; NULL: slot 0
+    int32_t nwork_r;
+    // a batch's packed slots' row-major tiles (streamed for their anchors only); NULL: the
+    // launch's tiles all belong to the packed slot of a single solve
+    const Tile *tiles;
+    int32_t ntiles, grid;
+    const int *starts;
+};
 // *inexact |= 1 when a diagonal entry's half is not exact in the storage type
 hipError_t launch_sym_pack16(hipStream_t s, const void *Q, int64_t ld, int dt, const SymPass &sp, void *P,
                              unsigned *inexact);
 
-// one trial group; sym != NULL streams the packed symmetric stack instead of the tiles
+// one trial group; sym != NULL streams the packed FP64 symmetric stack instead of the tiles;
+// s16 != NULL adds the 16-bit packed trial passes it describes
 hipError_t launch_group(hipStream_t s, Slot *slots, const int *live, int nslots, const Tile *tiles,
                         int ntiles, const int *starts, int B, int dtype, int variants,
                         int max_nblk_step, int max_ny, int max_nw, int max_epi, int pass_grid,
-                        int nt, hipEvent_t ev0, hipEvent_t ev1, const SymPass *sym = nullptr);
+                        int nt, hipEvent_t ev0, hipEvent_t ev1, const SymPass *sym = nullptr,
+                        const Sym16Launch *s16 = nullptr);
 hipError_t launch_pass_only(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles,
                             const int *starts, int B, int dtype, int max_nw, int pass_grid, int nt,
-                            const SymPass *sym = nullptr);
+                            const SymPass *sym = nullptr, const Sym16Launch *s16 = nullptr);
 // pass grid: resident blocks per CU of k_pass for this configuration
 int pass_blocks_per_cu(int B, int dtype, int max_nw);
 size_t pass_lds_bytes(int B, int dtype, int max_nw);

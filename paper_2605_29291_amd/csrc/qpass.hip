@@ -946,13 +946,21 @@ __device__ __forceinline__ void sym16_tile(const uint16_t *__restrict__ q, int n
 }
 
 template <int DT, int B>
-__global__ void __launch_bounds__(64, SYM_WAVES) k_spass16(Slot *__restrict__ slots, SymPass sp)
+__global__ void __launch_bounds__(64, SYM_WAVES) k_spass16(Slot *__restrict__ slots,
+                                                         const SymPass *__restrict__ descs,
+                                                         const int2 *__restrict__ work)
 {
     __shared__ float wi[B][SYM16_T];
     __shared__ float rbuf[B][SYM16_T];
-    Slot *S = slots;
+    int si = 0, t = blockIdx.x;
+    if (work) {
+        const int2 w = work[blockIdx.x];
+        si = w.x;
+        t = w.y;
+    }
+    Slot *S = slots + si;
     if (S->status != ST_RUNNING || S->mode != MODE_TRIAL) return;
-    const int t = blockIdx.x;
+    const SymPass &sp = descs[si];
     const int s = t / sp.ntt;
     int I, J;
     sym_tile_ij(t - s * sp.ntt, sp.NT, I, J);
@@ -967,11 +975,19 @@ __global__ void __launch_bounds__(64, SYM_WAVES) k_spass16(Slot *__restrict__ sl
 // W_b rows of tile row I of stored matrix s: the row results of tiles (I, J >= I), then the column
 // results of tiles (K <= I, I), each converted to FP64 and added in that order
 template <int B>
-__global__ void __launch_bounds__(SYM16_T) k_sred16(Slot *__restrict__ slots, SymPass sp)
+__global__ void __launch_bounds__(SYM16_T) k_sred16(Slot *__restrict__ slots, const SymPass *__restrict__ descs,
+                                                    const int2 *__restrict__ work_r)
 {
-    Slot *S = slots;
+    int si = 0, k = blockIdx.x;
+    if (work_r) {
+        const int2 w = work_r[blockIdx.x];
+        si = w.x;
+        k = w.y;
+    }
+    Slot *S = slots + si;
     if (S->status != ST_RUNNING || S->mode != MODE_TRIAL) return;
-    const int s = blockIdx.x / sp.NT, I = blockIdx.x % sp.NT;
+    const SymPass &sp = descs[si];
+    const int s = k / sp.NT, I = k % sp.NT;
     const int rr = threadIdx.x, gr = I * SYM16_T + rr;
     if (gr >= sp.n) return;
     const size_t stride = (size_t)2 * sp.B * SYM16_T;
@@ -1001,33 +1017,46 @@ __global__ void __launch_bounds__(SYM16_T) k_sred16(Slot *__restrict__ slots, Sy
 }
 
 template <int DT, int B>
-static void launch_sym16_dt(hipStream_t s, Slot *slots, const SymPass &sp)
+static void launch_sym16_dt(hipStream_t s, Slot *slots, const Sym16Launch &l)
 {
-    const int ntiles = sp.nq * sp.ntt;
-    if (ntiles <= 0) return;
-    k_spass16<DT, B><<<ntiles, 64, 0, s>>>(slots, sp);
-    k_sred16<B><<<sp.nq * sp.NT, SYM16_T, 0, s>>>(slots, sp);
+    if (l.nwork > 0) k_spass16<DT, B><<<l.nwork, 64, 0, s>>>(slots, l.descs, l.work);
+    if (l.nwork_r > 0) k_sred16<B><<<l.nwork_r, SYM16_T, 0, s>>>(slots, l.descs, l.work_r);
 }
 
 template <int B>
-static void launch_sym16_b(hipStream_t s, Slot *slots, const SymPass &sp)
+static void launch_sym16_b(hipStream_t s, Slot *slots, const Sym16Launch &l)
 {
-    if (sp.dt == DT_BF16) launch_sym16_dt<DT_BF16, B>(s, slots, sp);
-    else launch_sym16_dt<DT_F16, B>(s, slots, sp);
+    if (l.dt == DT_BF16) launch_sym16_dt<DT_BF16, B>(s, slots, l);
+    else launch_sym16_dt<DT_F16, B>(s, slots, l);
+}
+
+template <int B>
+static void launch_pass16_b(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles, const int *starts,
+                            int dtype, int max_nw, int pass_grid, int nt, const Sym16Launch &l)
+{
+    if (!l.tiles) {
+        // a single solve: every tile belongs to the packed slot, streamed for its anchors only
+        launch_pass_b<B>(s, slots, tiles, ntiles, starts, dtype, max_nw, pass_grid, nt, 1);
+    } else {
+        // a batch: the row-major slots' tiles, then the packed slots' tiles for their anchors
+        if (ntiles > 0) launch_pass_b<B>(s, slots, tiles, ntiles, starts, dtype, max_nw, pass_grid, nt, 0);
+        if (l.ntiles > 0) launch_pass_b<B>(s, slots, l.tiles, l.ntiles, l.starts, dtype, max_nw, l.grid, nt, 1);
+    }
+    launch_sym16_b<B>(s, slots, l);
 }
 
 hipError_t launch_pass_only(hipStream_t s, Slot *slots, const Tile *tiles, int ntiles,
                             const int *starts, int B, int dtype, int max_nw, int pass_grid, int nt,
-                            const SymPass *sym)
+                            const SymPass *sym, const Sym16Launch *s16)
 {
-    if (sym && sym->dt != DT_F64) {
-        // 16-bit storage: anchors (exact FP64 accumulation at the iterate) stream the row-major
-        // stack; the trial passes stream the packed tiles
+    if (s16) {
+        // 16-bit packed slots: anchors (exact FP64 accumulation at the iterate) stream the
+        // row-major stack, the trial passes the packed tiles
         switch (B) {
-        case 1: launch_pass_b<1>(s, slots, tiles, ntiles, starts, dtype, max_nw, pass_grid, nt, 1); launch_sym16_b<1>(s, slots, *sym); break;
-        case 2: launch_pass_b<2>(s, slots, tiles, ntiles, starts, dtype, max_nw, pass_grid, nt, 1); launch_sym16_b<2>(s, slots, *sym); break;
-        case 3: launch_pass_b<3>(s, slots, tiles, ntiles, starts, dtype, max_nw, pass_grid, nt, 1); launch_sym16_b<3>(s, slots, *sym); break;
-        default: launch_pass_b<4>(s, slots, tiles, ntiles, starts, dtype, max_nw, pass_grid, nt, 1); launch_sym16_b<4>(s, slots, *sym); break;
+        case 1: launch_pass16_b<1>(s, slots, tiles, ntiles, starts, dtype, max_nw, pass_grid, nt, *s16); break;
+        case 2: launch_pass16_b<2>(s, slots, tiles, ntiles, starts, dtype, max_nw, pass_grid, nt, *s16); break;
+        case 3: launch_pass16_b<3>(s, slots, tiles, ntiles, starts, dtype, max_nw, pass_grid, nt, *s16); break;
+        default: launch_pass16_b<4>(s, slots, tiles, ntiles, starts, dtype, max_nw, pass_grid, nt, *s16); break;
         }
         return hipGetLastError();
     }

@@ -256,6 +256,12 @@ struct qcqp_handle {
     double *dP = nullptr, *dws = nullptr;
     int32_t *dubase = nullptr;
     size_t sym_bytes = 0;
+    // 16-bit storage: the device copy of `sym` and the launch description of a single solve
+    SymPass *dsym = nullptr;
+    Sym16Launch s16{};
+    // the packed pass to launch, by storage type
+    const SymPass *sym64() const { return use_sym && dtype == DT_F64 ? &sym : nullptr; }
+    const Sym16Launch *sym16() const { return use_sym && dtype != DT_F64 ? &s16 : nullptr; }
 };
 
 struct qcqp_batch {
@@ -291,6 +297,19 @@ struct qcqp_batch {
     hipStream_t gstream = nullptr;        // G_xi evaluations of pending slots (default priority)
     std::vector<int> gap_busy;            // per slot: a G_xi is in flight on gstream
     std::vector<hipEvent_t> gev;          // per slot: recorded after that G_xi
+    // slots whose handles run the 16-bit packed pass (sym_pass): their descriptors (by slot),
+    // their row-major tiles (anchors), the blocks of the tile and row-sum kernels
+    SymPass *ddesc = nullptr;
+    Tile *dtiles16 = nullptr;
+    size_t tiles16_cap = 0;
+    int *dstarts16 = nullptr;
+    size_t starts16_cap = 0;
+    std::vector<int> starts16_host;
+    int2 *dwork = nullptr;
+    size_t work_cap = 0;
+    std::vector<int2> work_host;
+    Sym16Launch s16{};
+    bool has16 = false;
 };
 
 // ---------------------------------------------------------------------------------------
@@ -399,8 +418,10 @@ static void free_handle_memory(qcqp_handle *h)
     if (h->dP) (void)hipFree(h->dP);
     if (h->dws) (void)hipFree(h->dws);
     if (h->dubase) (void)hipFree(h->dubase);
+    if (h->dsym) (void)hipFree(h->dsym);
     h->dP = h->dws = nullptr;
     h->dubase = nullptr;
+    h->dsym = nullptr;
     h->dQ = nullptr;
     h->arena = nullptr;
     h->h_poll = nullptr;
@@ -665,17 +686,21 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
         const size_t nub = ub.size();
         ub.push_back(0);   // the packing's inexact-halving flag
         if (hipMalloc(&h->dP, pbytes) != hipSuccess || hipMalloc(&h->dws, wbytes) != hipSuccess ||
-            hipMalloc(&h->dubase, ub.size() * sizeof(int32_t)) != hipSuccess) {
+            hipMalloc(&h->dubase, ub.size() * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc(&h->dsym, sizeof(SymPass)) != hipSuccess) {
             free_handle_memory(h);
             delete h;
             return fail(QCQP_E_NOMEM, "packed symmetric stack (%zu bytes)", pbytes + wbytes);
         }
         h->sym = SymPass{nullptr, nullptr, h->dubase, (int32_t)n, NT, (int32_t)ntt, (int32_t)nq, (int32_t)h->B,
                          h->dtype, reinterpret_cast<const uint16_t *>(h->dP), reinterpret_cast<float *>(h->dws)};
+        h->s16 = Sym16Launch{h->dtype, h->B, h->dsym, nullptr, (int32_t)(nq * ntt), nullptr, (int32_t)(nq * NT),
+                             nullptr, 0, 0, nullptr};
         unsigned *inexact = reinterpret_cast<unsigned *>(h->dubase + nub);
         unsigned flag = 0;
         hipError_t e = hipMemcpyAsync(h->dubase, ub.data(), ub.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                                       h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(h->dsym, &h->sym, sizeof(SymPass), hipMemcpyHostToDevice, h->stream);
         if (e == hipSuccess) e = launch_sym_pack16(h->stream, h->dQ, h->ld, h->dtype, h->sym, h->dP, inexact);
         if (e == hipSuccess) e = hipMemcpyAsync(&flag, inexact, sizeof(flag), hipMemcpyDeviceToHost, h->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);   // ub is read by the copy
@@ -690,7 +715,7 @@ qcqp_status qcqp_create(const qcqp_problem *P, const qcqp_options *opt, qcqp_han
             return fail(QCQP_E_INVALID, "sym_pass: a diagonal entry of Q is too small to halve exactly in the storage type");
         }
         h->use_sym = true;
-        h->sym_bytes = pbytes + wbytes + ub.size() * sizeof(int32_t);
+        h->sym_bytes = pbytes + wbytes + ub.size() * sizeof(int32_t) + sizeof(SymPass);
     } else if (o.sym_pass && nq > 0) {
         const int32_t NT = (int32_t)((n + SYM_T - 1) / SYM_T);
         const int64_t ntt = (int64_t)NT * (NT + 1) / 2;
@@ -1044,7 +1069,7 @@ qcqp_status qcqp_solve(qcqp_handle *h, const double *x0, const double *y0, doubl
                                         (int)(h->m + 1 + h->p), h->pass_grid, h->nt,
                                         with_events ? ev[2 * (set * poll + g)] : nullptr,
                                         with_events ? ev[2 * (set * poll + g) + 1] : nullptr,
-                                        h->use_sym ? &h->sym : nullptr);
+                                        h->sym64(), h->sym16());
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -1133,7 +1158,7 @@ static qcqp_status eval_loaded_point(qcqp_handle *h)
     HIPCHK(hipMemsetAsync(h->d_ueval, 0, (h->m + 1) * h->n * 8, h->stream));
     HIPCHK(hipMemcpyAsync(h->dslot_eval, &S, sizeof(Slot), hipMemcpyHostToDevice, h->stream));
     HIPCHK(launch_pass_only(h->stream, h->dslot_eval, h->dtiles, (int)h->tiles.size(), h->dstarts, h->B, h->dtype, (int)h->nw, h->pass_grid, h->nt,
-                            h->use_sym ? &h->sym : nullptr));
+                            h->sym64(), h->sym16()));
     HIPCHK(launch_epi_anchor(h->stream, h->dslot_eval, nullptr, 1, (int)(h->m + 1 + h->p)));
     return QCQP_OK;
 }
@@ -1267,7 +1292,7 @@ qcqp_status qcqp_eval_trial_pass(qcqp_handle *h, const double *x, const double *
     }
     HIPCHK(hipMemcpyAsync(h->dslot_eval, &S, sizeof(Slot), hipMemcpyHostToDevice, h->stream));
     HIPCHK(launch_pass_only(h->stream, h->dslot_eval, h->dtiles, (int)h->tiles.size(), h->dstarts, h->B,
-                            h->dtype, (int)h->nw, h->pass_grid, h->nt, h->use_sym ? &h->sym : nullptr));
+                            h->dtype, (int)h->nw, h->pass_grid, h->nt, h->sym64(), h->sym16()));
     for (int b = 0; b < h->B; ++b) HIPCHK(hipMemcpyAsync(out + b * un, res[b], un * 8, kout, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return QCQP_OK;
@@ -1348,11 +1373,11 @@ qcqp_status qcqp_time_pass(qcqp_handle *h, int64_t reps, double *avg_seconds)
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(launch_pass_only(h->stream, h->dslot, h->dtiles, (int)h->tiles.size(), h->dstarts, h->B, h->dtype, (int)h->nw, h->pass_grid, h->nt,
-                            h->use_sym ? &h->sym : nullptr));
+                            h->sym64(), h->sym16()));
     HIPCHK(hipEventRecord(e0, h->stream));
     for (int64_t r = 0; r < reps; ++r)
         HIPCHK(launch_pass_only(h->stream, h->dslot, h->dtiles, (int)h->tiles.size(), h->dstarts, h->B, h->dtype, (int)h->nw, h->pass_grid, h->nt,
-                            h->use_sym ? &h->sym : nullptr));
+                            h->sym64(), h->sym16()));
     HIPCHK(hipEventRecord(e1, h->stream));
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -1398,8 +1423,11 @@ qcqp_status qcqp_batch_create(const qcqp_options *opt, size_t budget, int64_t ma
     bt->last_passes.assign(max_slots, 0);
     if (hipMalloc(&bt->dlive, max_slots * sizeof(int)) != hipSuccess ||
         hipMalloc(&bt->dslots, max_slots * sizeof(Slot)) != hipSuccess ||
+        hipMalloc(&bt->ddesc, max_slots * sizeof(SymPass)) != hipSuccess ||
         hipHostMalloc((void **)&bt->h_poll, max_slots * sizeof(Slot)) != hipSuccess) {
         if (bt->dslots) (void)hipFree(bt->dslots);
+        if (bt->dlive) (void)hipFree(bt->dlive);
+        if (bt->ddesc) (void)hipFree(bt->ddesc);
         delete bt;
         return fail(QCQP_E_NOMEM, "slot table");
     }
@@ -1407,6 +1435,8 @@ qcqp_status qcqp_batch_create(const qcqp_options *opt, size_t budget, int64_t ma
     for (int64_t s = 0; s < max_slots; ++s) bt->h_poll[s].status = ST_IDLE;
     if (hipMemcpy(bt->dslots, bt->h_poll, max_slots * sizeof(Slot), hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(bt->dslots);
+        (void)hipFree(bt->dlive);
+        (void)hipFree(bt->ddesc);
         (void)hipHostFree(bt->h_poll);
         delete bt;
         return fail(QCQP_E_DEVICE, "slot table init");
@@ -1419,7 +1449,7 @@ static size_t batch_resident(const qcqp_batch *bt)
 {
     size_t s = 0;
     for (auto *h : bt->handles)
-        if (h) s += h->q_bytes + h->arena_bytes;
+        if (h) s += h->q_bytes + h->arena_bytes + h->sym_bytes;
     return s;
 }
 
@@ -1441,12 +1471,12 @@ qcqp_status qcqp_batch_admit(qcqp_batch *bt, qcqp_handle *h, const double *x0, c
     if (h->owner) return fail(QCQP_E_INVALID, "handle already admitted");
     if (h->dtype != (int)bt->opt.storage || h->B != bt->opt.spec_trials || h->dev != bt->dev)
         return fail(QCQP_E_INVALID, "handle storage/spec_trials/device differ from the batch's");
-    if (h->use_sym) return fail(QCQP_E_INVALID, "a handle created with sym_pass solves alone only");
+    if (h->sym64()) return fail(QCQP_E_INVALID, "a handle created with sym_pass and F64 storage solves alone only");
     int64_t free_slot = -1;
     for (int64_t s = 0; s < bt->max_slots; ++s)
         if (!bt->handles[s]) { free_slot = s; break; }
     if (free_slot < 0) return fail(QCQP_E_NO_ROOM, "no free slot");
-    if (bt->budget && batch_resident(bt) + h->q_bytes + h->arena_bytes > bt->budget)
+    if (bt->budget && batch_resident(bt) + h->q_bytes + h->arena_bytes + h->sym_bytes > bt->budget)
         return fail(QCQP_E_NO_ROOM, "HBM budget exhausted");
     // the handle's own stream work, and the caller's writes of x0 / y0, come first
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -1462,6 +1492,8 @@ qcqp_status qcqp_batch_admit(qcqp_batch *bt, qcqp_handle *h, const double *x0, c
     HIPCHK(hipMemcpyAsync(bt->dslots + free_slot, &bt->h_poll[free_slot], sizeof(Slot),
                           hipMemcpyHostToDevice, bt->stream));
     HIPCHK(launch_start(bt->stream, bt->dslots + free_slot));
+    if (h->sym16())
+        HIPCHK(hipMemcpyAsync(bt->ddesc + free_slot, &h->sym, sizeof(SymPass), hipMemcpyHostToDevice, bt->stream));
     HIPCHK(hipStreamSynchronize(bt->stream));
     bt->handles[free_slot] = h;
     bt->finished[free_slot] = 0;
@@ -1474,8 +1506,10 @@ qcqp_status qcqp_batch_admit(qcqp_batch *bt, qcqp_handle *h, const double *x0, c
 
 static qcqp_status rebuild_tiles(qcqp_batch *bt)
 {
-    std::vector<Tile> all;
+    std::vector<Tile> all, all16;
     std::vector<int> live;
+    std::vector<int2> work, work_r;
+    size_t resident16 = 0;
     bt->max_nblk = 1;
     bt->max_ny = 1;
     bt->max_nw = 2;
@@ -1485,9 +1519,17 @@ static qcqp_status rebuild_tiles(qcqp_batch *bt)
         qcqp_handle *h = bt->handles[s];
         if (!h || bt->finished[s]) continue;
         live.push_back((int)s);
+        // a packed slot's row-major tiles only serve its anchors: they go to their own launch,
+        // so that they do not unbalance the trial-pass grid of the other slots
+        std::vector<Tile> &dst = h->sym16() ? all16 : all;
         for (Tile t : h->tiles) {
             t.slot = (int32_t)s;
-            all.push_back(t);
+            dst.push_back(t);
+        }
+        if (h->sym16()) {
+            for (int32_t t = 0; t < h->s16.nwork; ++t) work.push_back(int2{(int)s, t});
+            for (int32_t k = 0; k < h->s16.nwork_r; ++k) work_r.push_back(int2{(int)s, k});
+            resident16 += h->q_bytes;
         }
 
         bt->max_nblk = std::max(bt->max_nblk, h->nblk_step);
@@ -1501,7 +1543,7 @@ static qcqp_status rebuild_tiles(qcqp_batch *bt)
     std::vector<Tile> &mixed = all;
     size_t resident = 0;
     for (int64_t s2 = 0; s2 < bt->max_slots; ++s2)
-        if (bt->handles[s2] && !bt->finished[s2]) resident += bt->handles[s2]->q_bytes;
+        if (bt->handles[s2] && !bt->finished[s2] && !bt->handles[s2]->sym16()) resident += bt->handles[s2]->q_bytes;
     bt->nt = (double)resident > CACHE_RESIDENT_BYTES ? 1 : 0;
     if (mixed.size() > bt->tiles_cap) {
         if (bt->dtiles) (void)hipFree(bt->dtiles);
@@ -1535,6 +1577,50 @@ static qcqp_status rebuild_tiles(qcqp_batch *bt)
     if (!live.empty())
         HIPCHK(hipMemcpyAsync(bt->dlive, live.data(), live.size() * sizeof(int), hipMemcpyHostToDevice,
                               bt->stream));
+    // the packed slots: anchor tiles with their own balanced grid, and the blocks of the tile and
+    // row-sum kernels
+    bt->has16 = !work.empty() || !all16.empty();
+    if (bt->has16) {
+        const int B = bt->opt.spec_trials, dt = (int)bt->opt.storage;
+        if (all16.size() > bt->tiles16_cap) {
+            if (bt->dtiles16) (void)hipFree(bt->dtiles16);
+            bt->dtiles16 = nullptr;
+            const size_t cap = std::max<size_t>(all16.size() * 2, 1024);
+            HIPCHK(hipMalloc(&bt->dtiles16, cap * sizeof(Tile)));
+            bt->tiles16_cap = cap;
+        }
+        if (!all16.empty())
+            HIPCHK(hipMemcpyAsync(bt->dtiles16, all16.data(), all16.size() * sizeof(Tile), hipMemcpyHostToDevice,
+                                  bt->stream));
+        const int grid16 = std::max(1, std::min<int>(pass_grid_for(B, dt, bt->max_nw, (double)resident16),
+                                                      (int)all16.size()));
+        std::vector<int64_t> tb;
+        for (const Tile &t : all16) tb.push_back((int64_t)t.nrows * bt->handles[t.slot]->n * elem_size(dt));
+        bt->starts16_host = balanced_starts(tb, grid16);
+        if (bt->starts16_host.size() > bt->starts16_cap) {
+            if (bt->dstarts16) (void)hipFree(bt->dstarts16);
+            bt->dstarts16 = nullptr;
+            const size_t cap = std::max<size_t>(bt->starts16_host.size() * 2, 1024);
+            HIPCHK(hipMalloc(&bt->dstarts16, cap * sizeof(int)));
+            bt->starts16_cap = cap;
+        }
+        HIPCHK(hipMemcpyAsync(bt->dstarts16, bt->starts16_host.data(), bt->starts16_host.size() * sizeof(int),
+                              hipMemcpyHostToDevice, bt->stream));
+        bt->work_host = work;
+        bt->work_host.insert(bt->work_host.end(), work_r.begin(), work_r.end());
+        if (bt->work_host.size() > bt->work_cap) {
+            if (bt->dwork) (void)hipFree(bt->dwork);
+            bt->dwork = nullptr;
+            const size_t cap = std::max<size_t>(bt->work_host.size() * 2, 4096);
+            HIPCHK(hipMalloc(&bt->dwork, cap * sizeof(int2)));
+            bt->work_cap = cap;
+        }
+        if (!bt->work_host.empty())
+            HIPCHK(hipMemcpyAsync(bt->dwork, bt->work_host.data(), bt->work_host.size() * sizeof(int2),
+                                  hipMemcpyHostToDevice, bt->stream));
+        bt->s16 = Sym16Launch{dt, B, bt->ddesc, bt->dwork, (int32_t)work.size(), bt->dwork + work.size(),
+                              (int32_t)work_r.size(), bt->dtiles16, (int32_t)all16.size(), grid16, bt->dstarts16};
+    }
     bt->nlive = (int)live.size();
     bt->ntiles = (int)mixed.size();
     if (bt->gexec) (void)hipGraphExecDestroy(bt->gexec);   // launch shapes changed
@@ -1565,7 +1651,8 @@ qcqp_status qcqp_batch_step(qcqp_batch *bt, int64_t groups)
                                             bt->max_nblk,
                                             bt->max_ny, bt->max_nw, bt->max_epi, bt->pass_grid, bt->nt,
                                             with_events ? bt->ev[2 * g] : nullptr,
-                                            with_events ? bt->ev[2 * g + 1] : nullptr);
+                                            with_events ? bt->ev[2 * g + 1] : nullptr, nullptr,
+                                            bt->has16 ? &bt->s16 : nullptr);
                 if (e != hipSuccess) return e;
             }
             return hipSuccess;
@@ -1597,7 +1684,8 @@ qcqp_status qcqp_batch_step(qcqp_batch *bt, int64_t groups)
         if (!h) continue;
         const int64_t d = bt->h_poll[s].passes - bt->last_passes[s];
         if (d > 0) {
-            bt->pass_bytes += (double)d * (double)h->nq * (double)h->n * (double)h->n * elem_size(h->dtype);
+            const double nn = h->sym16() ? (double)h->n * (double)(h->n + 1) / 2 : (double)h->n * (double)h->n;
+            bt->pass_bytes += (double)d * (double)h->nq * nn * elem_size(h->dtype);
             bt->passes += d;
         }
         bt->last_passes[s] = bt->h_poll[s].passes;
@@ -1710,6 +1798,10 @@ qcqp_status qcqp_batch_destroy(qcqp_batch *bt)
     if (bt->dtiles) (void)hipFree(bt->dtiles);
     if (bt->dstarts) (void)hipFree(bt->dstarts);
     if (bt->dlive) (void)hipFree(bt->dlive);
+    if (bt->ddesc) (void)hipFree(bt->ddesc);
+    if (bt->dtiles16) (void)hipFree(bt->dtiles16);
+    if (bt->dstarts16) (void)hipFree(bt->dstarts16);
+    if (bt->dwork) (void)hipFree(bt->dwork);
     for (auto &e : bt->ev) (void)hipEventDestroy(e);
     if (bt->gexec) (void)hipGraphExecDestroy(bt->gexec);
     if (bt->ev_join) (void)hipEventDestroy(bt->ev_join);

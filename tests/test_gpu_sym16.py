@@ -13,6 +13,8 @@ partials is FP64.
   S_ir = sum_j |Q_ij| |d_j|.  A zero step gives W = 0 exactly.
 * Whole solves: the result's relative KKT residual, evaluated by the oracle in FP64 on the stored
   instance, is <= 1e-6, with the objective of the row-major BF16 solve to 1e-6 relative.
+* In a batch, packed and row-major requests admitted at different times each return bitwise the
+  iterate, multipliers and counters of their solve alone.
 * Refusals: FP32 storage, and 16-bit storage with direct passes.
 """
 import math
@@ -119,3 +121,41 @@ def test_sym16_refusals():
         with pytest.raises(QCQPError) as e:
             Solver(qi.round_instance(inst, kw["storage"]), tau_bar=1.0, sym_pass=1, **kw)
         assert e.value.code == abi.E_INVALID and "sym_pass" in str(e.value)
+
+
+def test_sym16_batch_alone_equals_mix():
+    from paper_2605_29291_amd import Batch, Solver
+    storage = "bfloat16"
+    specs = [(600, 8, 1), (150, 5, 0), (1030, 3, 1), (300, 9, 1), (90, 4, 0), (520, 6, 1)]
+    insts = [qi.round_instance(qi.random_qcqp(n, m, seed=7400 + k, shift=0.01), storage)
+             for k, (n, m, _) in enumerate(specs)]
+    kw = [dict(storage=storage, tau_bar=tau_bar_of(i), gamma0=0.1, restart_every=40, sym_pass=sp)
+          for i, (_, _, sp) in zip(insts, specs)]
+    alone = []
+    for inst, o in zip(insts, kw):
+        announce(f"sym16 batch: alone n={inst.n} sym_pass={o['sym_pass']}")
+        s = Solver(inst, **o)
+        x, y, info = s.solve()
+        s.close()
+        assert info["status"] == "ok", info
+        alone.append((to_np(x), to_np(y), info))
+    announce("sym16 batch: mix")
+    b = Batch(max_slots=8, storage=storage)
+    slot_of = {}
+    for k in (0, 1, 2):
+        slot_of[b.admit(Solver(insts[k], **kw[k]))] = k
+    b.step(5)
+    for k in (3, 4, 5):
+        slot_of[b.admit(Solver(insts[k], **kw[k]))] = k
+    got = {}
+    while len(got) < len(insts):
+        b.step(6)
+        for slot in b.poll():
+            got[slot_of[slot]] = b.fetch(slot)
+    b.close()
+    for k in range(len(insts)):
+        _, x, y, info = got[k]
+        np.testing.assert_array_equal(to_np(x), alone[k][0])
+        np.testing.assert_array_equal(to_np(y), alone[k][1])
+        assert (info["iters"], info["trials"], info["q_passes"]) == \
+            (alone[k][2]["iters"], alone[k][2]["trials"], alone[k][2]["q_passes"])
