@@ -443,8 +443,7 @@ def serving_section(args, requests=512, check=16):
         fp64_single_instance_fifo=fifo,
         pass_roofline={"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": gbs / HBM_PEAK_GBS if gbs else None,
-                       "kernel": f"k_pass<DT_BF16,{args.spec}> over all resident requests (algorithmic "
-                                 "bytes (m+1) n^2 x 2 per request pass)"},
+                       "kernel": _batch_pass_kernel(args) + " over all resident requests"},
         oracle_checks=checks, max_oracle_rel_kkt=max(c["rel_kkt_oracle"] for c in checks),
         instance_synthesis_s=gen, cpu_baseline=cpu, budget_bytes=budget, spec_trials=args.spec,
         groups_per_step=args.groups)
@@ -475,10 +474,20 @@ def precision_section(args, solves=3):
         kk_unrounded = s64.eval_kkt(x, y)
         xr = x.cpu().numpy()
         s.close()
+        # the packed 16-bit pass (sym_pass): upper-triangle tiles of the stored values
+        sp = Solver(instr, device=True, storage=storage, tau_bar=tau_bar, gamma0=0.1, timing=1, sym_pass=1)
+        wall_p, lat_p, infos_p, xp, yp = run_solves(sp, solves, 1)
+        sp.close()
+        sp2 = Solver(instr, device=True, storage=storage, tau_bar=tau_bar, gamma0=0.1, sym_pass=1)
+        sp_pass = min(sp2.time_pass(10) for _ in range(2))
+        sp2.close()
+        pb_p = infos_p[0]["pass_bytes"]
+        xpn, ypn = xp.cpu().numpy(), yp.cpu().numpy()
         host = qi.Instance(n, m, 0, Qr.cpu(), inst64.q, inst64.c, inst64.lb, inst64.ub)
         del Qr, instr
         torch.cuda.empty_cache()
         kk = oracle.kkt(oracle.Problem(host), xr, y.cpu().numpy())
+        kk_p = oracle.kkt(oracle.Problem(host), xpn, ypn)
         del host
         out[storage] = dict(
             solves_per_s=solves / wall, p50_ms=float(np.percentile(np.array(lat) * 1e3, 50)),
@@ -491,7 +500,17 @@ def precision_section(args, solves=3):
             error_vs_fp64_unrounded=dict(
                 x_rel=float(np.linalg.norm(xr - x64n) / (1 + np.linalg.norm(x64n))),
                 f_rel=float(abs(kk_unrounded["f"] - i64["f"]) / (1 + abs(i64["f"]))),
-                rel_kkt_on_unrounded=kk_unrounded["rel_kkt"]))
+                rel_kkt_on_unrounded=kk_unrounded["rel_kkt"]),
+            packed_pass=dict(
+                solves_per_s=solves / wall_p, p50_ms=float(np.percentile(np.array(lat_p) * 1e3, 50)),
+                iters=infos_p[0]["iters"], q_passes=infos_p[0]["q_passes"],
+                rel_kkt_oracle_on_stored=kk_p["rel_kkt"], f=kk_p["f"],
+                all_converged=all(i["status"] == "ok" and i["rel_kkt"] <= 1e-6 for i in infos_p),
+                pass_roofline={"bound": "hbm", "achieved": pb_p / sp_pass / 1e9, "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": pb_p / sp_pass / 1e9 / HBM_PEAK_GBS,
+                               "us": sp_pass * 1e6, "bytes": pb_p,
+                               "kernel": "k_spass16<16-bit, 2> + k_sred16 (packed upper triangles, "
+                                         "(m+1) n(n+1)/2 x 2 bytes; trial passes)"}))
         log(f"precision {storage}: {out[storage]}")
     s64.close()
     del inst64
@@ -506,11 +525,20 @@ def precision_section(args, solves=3):
 # ----------------------------------------------------------------------------------------------
 # other workloads (not the default bench line): --workload serving | precision | kml
 
-def _est_bytes(n, m, storage, B=2):
+def _est_bytes(n, m, storage, B=2, sym=0):
     es = {"float64": 8, "float32": 4, "bfloat16": 2, "float16": 2}[storage]
     ld = -(-n // (128 // es)) * (128 // es)
     inc = 0 if storage == "float64" else B
-    return (m + 1) * n * ld * es + 8 * (m + 1) * n * (3 + B + inc) + (4 << 20)
+    packed = 0
+    if sym:
+        nt = -(-n // 256)
+        packed = (m + 1) * nt * (nt + 1) // 2 * (256 * 256 * 2 + 2 * B * 256 * 4)
+    return (m + 1) * n * ld * es + packed + 8 * (m + 1) * n * (3 + B + inc) + (4 << 20)
+
+
+def _sym16(args, n):
+    """Whether a serving request of size n streams the packed 16-bit pass."""
+    return 1 if args.sym16_min_n and n >= args.sym16_min_n else 0
 
 
 def _gen_request(req, storage):
@@ -540,7 +568,7 @@ def serve_batched(trace, storage, args, budget, timing=1):
         now = time.perf_counter() - t0 - gen
         while idx < len(reqs) and reqs[idx]["arrival"] <= now:
             r = reqs[idx]
-            est = _est_bytes(r["n"], r["m"], storage)
+            est = _est_bytes(r["n"], r["m"], storage, sym=_sym16(args, r["n"]))
             if slot_req and resident + est > budget:
                 break
             if held is None:
@@ -552,7 +580,7 @@ def serve_batched(trace, storage, args, budget, timing=1):
                 gen += time.perf_counter() - tg
                 ta = time.perf_counter()
                 held = Solver(inst, device=True, storage=storage, tau_bar=0.0, gamma0=0.1,
-                              spec_trials=args.spec)
+                              spec_trials=args.spec, sym_pass=_sym16(args, r["n"]))
                 r["admission_ms"] = (time.perf_counter() - ta) * 1e3
                 del inst
             nb = held.nbytes()
@@ -589,6 +617,14 @@ def serve_batched(trace, storage, args, budget, timing=1):
     ps = b.pass_stats()
     b.close()
     return reqs, total, gen, ps
+
+
+def _batch_pass_kernel(args):
+    if not args.sym16_min_n:
+        return f"k_pass<DT_BF16,{args.spec}> (algorithmic bytes (m+1) n^2 x 2 per request pass)"
+    return (f"k_spass16<DT_BF16,{args.spec}> + k_sred16 for requests with n >= {args.sym16_min_n} (packed "
+            f"upper triangles, (m+1) n(n+1)/2 x 2 bytes), k_pass<DT_BF16,{args.spec}> for the others "
+            f"((m+1) n^2 x 2 bytes)")
 
 
 def serve_fifo(trace, storage, args):
@@ -953,7 +989,7 @@ def workload_batch_pass(args):
         for r in trace[:k]:
             inst = _gen_request(r, storage)
             s = Solver(inst, device=True, storage=storage, tau_bar=0.0, gamma0=0.1,
-                       spec_trials=args.spec)
+                       spec_trials=args.spec, sym_pass=_sym16(args, r["n"]))
             del inst
             if b.admit(s) is None:
                 s.close()
@@ -981,9 +1017,10 @@ def workload_batch_pass(args):
             "warmup": 2, "ms_per_step": last["us_per_group_pass"] / 1e3, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "bf16-storage", "data": "synthetic",
             "config": {"workload": "continuous batch of serving-trace requests, BF16, steady-state pass",
-                       "spec_trials": args.spec},
+                       "spec_trials": args.spec, "packed_from_n": args.sym16_min_n},
             "roofline": {"bound": "hbm", "achieved": last["pass_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": last["frac"], "traffic": None, "kernel": f"k_pass<DT_BF16,{args.spec}>"},
+                         "frac": last["frac"], "traffic": None,
+                         "kernel": _batch_pass_kernel(args)},
             "cpu_baseline": None, "per_batch": out}
 
 
@@ -1090,6 +1127,9 @@ def main():
     ap.add_argument("--groups", type=int, default=4, help="serving: trial groups per batch step")
     ap.add_argument("--check", type=int, default=8, help="serving: requests checked by the oracle")
     ap.add_argument("--no-fifo", action="store_true", help="serving: skip the FP64 FIFO comparison")
+    ap.add_argument("--sym16-min-n", type=int, default=0,
+                    help="serving/batch_pass: requests with n at least this stream the packed BF16 pass "
+                         "(0, the default: every request streams the row-major pass)")
     ap.add_argument("--spec", type=int, default=2,
                     help="serving, batch_pass: speculative candidates per pass")
     ap.add_argument("--kml-iters", type=int, default=20000, help="kml: iteration cap")
