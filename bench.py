@@ -739,10 +739,10 @@ def workload_precision(args):
     x64, y64, i64 = s64.solve()
     log(f"fp64 reference: iters={i64['iters']} rel_kkt={i64['rel_kkt']:.2e} f={i64['f']:.10f}")
     out = {}
-    for storage in ("bfloat16", "float16"):
+    for storage, sym in (("bfloat16", 0), ("float16", 0), ("bfloat16", 1), ("float16", 1)):
         Qr = inst64.Q.to({"bfloat16": torch.bfloat16, "float16": torch.float16}[storage])
         instr = qi.Instance(n, m, 0, Qr, inst64.q, inst64.c, inst64.lb, inst64.ub)
-        s = Solver(instr, device=True, storage=storage, tau_bar=tau_bar, gamma0=0.1, timing=1)
+        s = Solver(instr, device=True, storage=storage, tau_bar=tau_bar, gamma0=0.1, timing=1, sym_pass=sym)
         wall, lat, infos, x, y = run_solves(s, args.steps, args.warmup)
         avg_pass, tp = pass_stats(infos)
         pb = infos[0]["pass_bytes"]
@@ -755,7 +755,8 @@ def workload_precision(args):
         # KKT on the stored instance, evaluated in FP64 on the GPU (parity of this evaluation
         # with the oracle is a GPU test)
         kk_stored = s.eval_kkt(x, y)
-        out[storage] = dict(solves_per_s=args.steps / wall, p50_ms=float(np.percentile(np.array(lat) * 1e3, 50)),
+        key = storage + ("_packed" if sym else "")
+        out[key] = dict(solves_per_s=args.steps / wall, p50_ms=float(np.percentile(np.array(lat) * 1e3, 50)),
                             p99_ms=float(np.percentile(np.array(lat) * 1e3, 99)),
                             iters=infos[0]["iters"], q_passes=infos[0]["q_passes"],
                             rel_kkt=infos[0]["rel_kkt"], rel_kkt_stored_fp64_eval=kk_stored["rel_kkt"],
@@ -763,7 +764,7 @@ def workload_precision(args):
                             q_pass_frac=pb / avg_pass / 1e9 / HBM_PEAK_GBS, bytes_per_pass=pb,
                             error_vs_fp64_unrounded=err,
                             all_converged=all(i["status"] == "ok" for i in infos))
-        log(f"{storage}: {out[storage]}")
+        log(f"{key}: {out[key]}")
         s.close()
         del Qr, instr
         torch.cuda.empty_cache()
@@ -1029,7 +1030,7 @@ def workload_traffic(args):
     WRITE_SIZE): a plain device copy of known size (the calibration), then the config-2 FP64
     row-major pass and the packed symmetric pass (k_spass + k_sred) exactly as the config-2
     solves launch them (trial mode, CONFIG2_SPEC candidates), and a BF16 pass as the serving
-    batches launch it (2 candidates)."""
+    batches launch it (2 candidates), row-major and packed (k_spass16 + k_sred16)."""
     import torch
     import qcqp_inputs as qi
     from paper_2605_29291_amd import Solver
@@ -1057,6 +1058,10 @@ def workload_traffic(args):
     s = Solver(ib, device=True, storage="bfloat16", tau_bar=1.0, spec_trials=2)
     s.time_pass(reps=3)
     out["bf16_pass_bytes"] = 101 * 2000 * 2000 * 2
+    s.close()
+    s = Solver(ib, device=True, storage="bfloat16", tau_bar=1.0, spec_trials=2, sym_pass=1)
+    s.time_pass(reps=3)
+    out["bf16_sym_pass_bytes"] = 101 * (2000 * 2001 // 2) * 2
     s.close()
     return out
 
