@@ -844,8 +844,11 @@ def workload_kml_minmax(args):
             avg, tp = pass_stats(tinfos)
             info = infos[-1]
             pb = info["pass_bytes"]
+            # solves count only when every timed solve stopped at relative KKT <= 1e-6
+            ok = all(i["status"] == "ok" and i["rel_kkt"] <= 1e-6 for i in infos)
             out[f"n{npts}_{label}"] = dict(
-                solves_per_s=args.steps / wall, ms_per_solve=wall / args.steps * 1e3,
+                solves_per_s=args.steps / wall if ok else None, ms_per_solve=wall / args.steps * 1e3,
+                all_converged=ok,
                 iters=info["iters"], trials=info["trials"], q_passes=info["q_passes"],
                 rel_kkt=info["rel_kkt"], status=info["status"],
                 q_pass_us=avg * 1e6, q_pass_GBs=pb / avg / 1e9, bytes_per_pass=pb,
