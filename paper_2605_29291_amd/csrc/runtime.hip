@@ -1478,8 +1478,9 @@ qcqp_status qcqp_batch_admit(qcqp_batch *bt, qcqp_handle *h, const double *x0, c
     if (free_slot < 0) return fail(QCQP_E_NO_ROOM, "no free slot");
     if (bt->budget && batch_resident(bt) + h->q_bytes + h->arena_bytes + h->sym_bytes > bt->budget)
         return fail(QCQP_E_NO_ROOM, "HBM budget exhausted");
-    // the handle's own stream work, and the caller's writes of x0 / y0, come first
-    HIPCHK(hipStreamSynchronize(h->stream));
+    // the handle's own stream work, and the caller's writes of x0 / y0, come first (stream
+    // order only: the host does not wait)
+    HIPCHK(join_streams(bt->stream, h->stream, h->ev_join));
     HIPCHK(join_streams(bt->stream, bt->ustream, bt->ev_join));
     hipStream_t saved = h->stream;
     h->stream = bt->stream;
@@ -1494,7 +1495,10 @@ qcqp_status qcqp_batch_admit(qcqp_batch *bt, qcqp_handle *h, const double *x0, c
     HIPCHK(launch_start(bt->stream, bt->dslots + free_slot));
     if (h->sym16())
         HIPCHK(hipMemcpyAsync(bt->ddesc + free_slot, &h->sym, sizeof(SymPass), hipMemcpyHostToDevice, bt->stream));
-    HIPCHK(hipStreamSynchronize(bt->stream));
+    // The slot table entry is copied from pinned memory that only this slot's later polls
+    // overwrite (queued behind the copy).  Caller-owned device start points are read by the
+    // queued copies: wait for them before returning, so that the caller may reuse their memory.
+    if (h->on_device && (x0 || y0)) HIPCHK(hipStreamSynchronize(bt->stream));
     bt->handles[free_slot] = h;
     bt->finished[free_slot] = 0;
     bt->last_passes[free_slot] = 0;
