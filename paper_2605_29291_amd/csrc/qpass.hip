@@ -661,29 +661,35 @@ __global__ void __launch_bounds__(SYM_T) k_sred(Slot *__restrict__ slots, SymPas
     const size_t stride = (size_t)2 * sp.B * SYM_T;
     const size_t ob = (size_t)sp.ubase[s] + gr;
     // terms k = 0 .. NT - I - 1: row result of (I, I + k); k = NT - I .. NT: column result of
-    // (k - (NT - I), I); loaded eight at a time so that the loads are in flight together
+    // (k - (NT - I), I); eight terms of every candidate are loaded at a time, so that the loads
+    // are in flight together; each candidate's sum runs over k in order
     const int nrow = sp.NT - I, nterm = sp.NT + 1;
-    for (int b = 0; b < nb; ++b) {
-        double v = 0.0;
-        for (int k0 = 0; k0 < nterm; k0 += 8) {
-            double t[8];
+    double v[B];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int k = k0 + u;
-                t[u] = 0.0;
-                if (k < nterm) {
-                    t[u] = k < nrow
-                               ? sp.ws[(size_t)sym_tile_index(s, I, I + k, sp.NT, sp.ntt) * stride + b * SYM_T + rr]
-                               : sp.ws[(size_t)sym_tile_index(s, k - nrow, I, sp.NT, sp.ntt) * stride +
-                                       (size_t)(sp.B + b) * SYM_T + rr];
-                }
-            }
+    for (int b = 0; b < B; ++b) v[b] = 0.0;
+    for (int k0 = 0; k0 < nterm; k0 += 8) {
+        double t[B][8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = k0 + u;
+            const size_t base = k < nrow ? (size_t)sym_tile_index(s, I, I + k, sp.NT, sp.ntt) * stride + rr
+                                         : (size_t)sym_tile_index(s, k - nrow, I, sp.NT, sp.ntt) * stride +
+                                               (size_t)sp.B * SYM_T + rr;
+#pragma unroll
+            for (int b = 0; b < B; ++b) t[b][u] = (k < nterm && b < nb) ? sp.ws[base + (size_t)b * SYM_T] : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b)
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                if (k0 + u < nterm) v += t[u];
+                if (k0 + u < nterm) v[b] += t[b][u];
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        if (b < nb) {
+            double *out = anchor ? S->Uc[0] : S->Uc[b];
+            out[ob] = v[b];
         }
-        double *out = anchor ? S->Uc[0] : S->Uc[b];
-        out[ob] = v;
     }
 }
 
@@ -823,11 +829,15 @@ __device__ __forceinline__ void sym16_tile(const uint16_t *__restrict__ q, int n
     const int voff = gc < n ? c8 * 2 : OFF_NONE;
     const int dmask = I == J ? OFF_NONE : 0;
     // row r of the tile in this lane's half; on the diagonal tile a lane whose eight columns
-    // all lie below the diagonal (c8 + 7 < r) reads nothing (the packed tile holds zeros there)
+    // all lie below the diagonal (c8 + 7 < r) reads nothing (the packed tile holds zeros there).
+    // The scalar offset is the wave's first row 2k (uniform); the half's row goes into the lane
+    // offset, so that the load is one instruction for the whole wave (a lane-dependent scalar
+    // offset would be issued once per distinct value).
+    const int hoff = half * SYM16_T * 2;
     auto load = [&](int k) -> u32x4 {
         const int r = 2 * k + half;
-        const int vo = voff | (dmask & ((c8 + 7 - r) >> 31));
-        return __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, vo, r * SYM16_T * 2, BUF_NT));
+        const int vo = (voff | (dmask & ((c8 + 7 - r) >> 31))) + hoff;
+        return __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, vo, 2 * k * SYM16_T * 2, BUF_NT));
     };
     // d_J of the lane's eight columns and d_I of the tile's rows (FP32 of the FP64 differences,
     // zero past n): the loads go out before the window and are converted behind it, so the first
@@ -993,27 +1003,30 @@ __global__ void __launch_bounds__(SYM16_T) k_sred16(Slot *__restrict__ slots, co
     const size_t stride = (size_t)2 * sp.B * SYM16_T;
     const size_t ob = (size_t)sp.ubase[s] + gr;
     const int nrow = sp.NT - I, nterm = sp.NT + 1;
-    for (int b = 0; b < B; ++b) {
-        double v = 0.0;
-        for (int k0 = 0; k0 < nterm; k0 += 8) {
-            float t[8];
+    // eight terms of every candidate at a time (loads in flight together), each candidate's sum
+    // over k in order
+    double v[B];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int k = k0 + u;
-                t[u] = 0.0f;
-                if (k < nterm) {
-                    t[u] = k < nrow
-                               ? sp.ws16[(size_t)sym_tile_index(s, I, I + k, sp.NT, sp.ntt) * stride + b * SYM16_T + rr]
-                               : sp.ws16[(size_t)sym_tile_index(s, k - nrow, I, sp.NT, sp.ntt) * stride +
-                                         (size_t)(sp.B + b) * SYM16_T + rr];
-                }
-            }
+    for (int b = 0; b < B; ++b) v[b] = 0.0;
+    for (int k0 = 0; k0 < nterm; k0 += 8) {
+        float t[B][8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = k0 + u;
+            const size_t base = k < nrow ? (size_t)sym_tile_index(s, I, I + k, sp.NT, sp.ntt) * stride + rr
+                                         : (size_t)sym_tile_index(s, k - nrow, I, sp.NT, sp.ntt) * stride +
+                                               (size_t)sp.B * SYM16_T + rr;
+#pragma unroll
+            for (int b = 0; b < B; ++b) t[b][u] = k < nterm ? sp.ws16[base + (size_t)b * SYM16_T] : 0.0f;
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b)
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                if (k0 + u < nterm) v += (double)t[u];
-        }
-        S->W[b][ob] = v;
+                if (k0 + u < nterm) v[b] += (double)t[b][u];
     }
+#pragma unroll
+    for (int b = 0; b < B; ++b) S->W[b][ob] = v[b];
 }
 
 template <int DT, int B>
