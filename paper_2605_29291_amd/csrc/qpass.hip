@@ -550,7 +550,8 @@ __device__ __forceinline__ void sym_tile(const double *__restrict__ q, int n, in
     const int gi = I * SYM_T + c;
     const bool cval = gc < n;
     const int rmax = min(SYM_T, n - I * SYM_T);
-    // rows past rmax lie outside the resource; columns past n take an offset outside it
+    // the resource spans the tile's valid rows; columns past n take a lane offset outside it
+    // (rows past rmax, reached only by the window's read-ahead, hold zeros in the packed tile)
     const __amdgpu_buffer_rsrc_t rs = tile_rsrc(q, rmax * SYM_T * 8);
     const int voff = cval ? c * 8 : OFF_NONE;
     const int dmask = I == J ? OFF_NONE : 0;
