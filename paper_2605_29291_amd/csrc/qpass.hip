@@ -440,38 +440,25 @@ hipError_t launch_sym_pack(hipStream_t s, const double *Q, int64_t ld, const Sym
     return hipGetLastError();
 }
 
-// One tile by one 64-lane wave: lane l holds columns 2l, 2l+1 of every row (one 16-byte
-// non-temporal buffer load per row).  The loads run WIN rows ahead of the arithmetic in a
-// rolling window: a group's registers are refilled with the rows WIN further down as soon as
-// the group is consumed, so about WIN KB of the tile stay in flight per wave.  The row loop is
-// unrolled at compile time so every window slot stays in one register (a rolled loop would
-// copy the slots at its back edge and wait there for all loads in flight).
-// Row dots are summed over the 64 lanes four rows at a time by a transposing reduction (two
-// half-swapping steps with the gfx950 permlane swaps, then four rotations inside 16-lane rows
-// with DPP: VALU only) and parked in LDS; the column dots stay in the lane's registers over all
-// rows.  Lane l holds w_I at rows 2l, 2l+1, and each row's value is broadcast with readlane.
+// One tile by one 64-lane wave.  One 16-byte non-temporal buffer load per lane covers two
+// doubles, so a load instruction covers half a tile row in each half of the wave: instruction k
+// reads row pair p = k / 2 (lanes 0..31 row 2p, lanes 32..63 row 2p + 1) at column half k % 2,
+// and lane l holds columns 2 (l mod 32) + {0, 1, 64, 65} of its rows.  The loads run WIN
+// instructions ahead of the arithmetic in a rolling window: a group's registers are refilled
+// with the instructions WIN further on as soon as the group is consumed, so about WIN KB of the
+// tile stay in flight per wave.  The loop over the tile is unrolled at compile time so every
+// window slot stays in one register (a rolled loop would copy the slots at its back edge and
+// wait there for all loads in flight).
+// Row dots: four products per lane, then over the row's 32 lanes by a transposing step that
+// pairs two row pairs (one permlane16 swap) and four DPP rotations inside 16-lane rows (VALU
+// only); the sums are parked in LDS.  Column dots stay in the lane's registers over the rows of
+// its half, multiplied by w_I read from LDS (one broadcast read per half and row, no VALU), and
+// the two halves are added once at the end.
 // A diagonal tile is stored as its upper triangle with half the diagonal (k_sym_pack), so it
 // runs the same code; lanes whose 16 bytes lie wholly below the diagonal fetch nothing.
 
-// the value v of lane `src` (uniform) in every lane
-__device__ __forceinline__ double lane_bcast(double v, int src)
-{
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
-    return __hiloint2double(hi, lo);
-}
-
-// Cross-lane steps on doubles, VALU only (no LDS): exchange halves of the wave with the
-// gfx950 permlane swaps, and rotate within 16-lane rows with DPP.
-__device__ __forceinline__ void swap32(double &a, double &b)
-{
-    // lanes 32..63 of a <-> lanes 0..31 of b
-    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(a), (unsigned)__double2loint(b), false, false);
-    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(a), (unsigned)__double2hiint(b), false, false);
-    a = __hiloint2double((int)hi[0], (int)lo[0]);
-    b = __hiloint2double((int)hi[1], (int)lo[1]);
-}
-
+// Cross-lane steps on doubles, VALU only (no LDS): exchange quarter-waves with the gfx950
+// permlane16 swap, and rotate within 16-lane rows with DPP.
 __device__ __forceinline__ void swap16(double &a, double &b)
 {
     // lanes 16..31 (48..63) of a <-> lanes 0..15 (32..47) of b
@@ -485,29 +472,15 @@ __device__ __forceinline__ void swap16(double &a, double &b)
 template <int K>
 __device__ __forceinline__ double row_ror(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x120 + K, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x120 + K, 0xf, 0xf, false);
+    // every row and bank is enabled and a rotation reads no lane outside the row, so every lane
+    // is written: no old value is needed (an update form would zero the destination first)
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x120 + K, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x120 + K, 0xf, 0xf, false);
     return __hiloint2double(hi, lo);
 }
 
-// p[k] holds each lane's share of row k (k = 0..3); returns in every lane of 16-lane row q the
-// sum over all 64 lanes of row q, in a fixed order
-__device__ __forceinline__ double reduce4(double p0, double p1, double p2, double p3)
-{
-    swap32(p0, p2);                 // lanes 0..31: row 0 (1), lanes 32..63: row 2 (3)
-    swap32(p1, p3);
-    double s0 = p0 + p2, s1 = p1 + p3;
-    swap16(s0, s1);                 // 16-lane row q now holds shares of tile row q
-    double t = s0 + s1;
-    t += row_ror<8>(t);
-    t += row_ror<4>(t);
-    t += row_ror<2>(t);
-    t += row_ror<1>(t);
-    return t;
-}
-
-constexpr int SYM_WIN = 16;   // rows in flight per wave
-constexpr int SYM_GRP = 4;    // rows per transposing reduction
+constexpr int SYM_WIN = 16;   // load instructions in flight per wave (half a row pair each)
+constexpr int SYM_GRP = 4;    // instructions (rows) per transposing reduction
 constexpr int SYM_WAVES = 3;  // register budget: waves per SIMD
 
 // A buffer resource over the first `bytes` bytes of a tile: loads beyond it return zero without
@@ -537,94 +510,134 @@ struct GroupLoop {
     }
 };
 
+// p0: each lane's share of tile rows 4g (lanes 0..31) and 4g + 1 (lanes 32..63); p1 the same for
+// rows 4g + 2 and 4g + 3.  Returns in every lane of 16-lane row q the full sum of tile row
+// 4g + {0, 2, 1, 3}[q], in a fixed order (one half-swap, then four rotations inside 16-lane rows)
+__device__ __forceinline__ double reduce2d(double p0, double p1)
+{
+    swap16(p0, p1);
+    double t = p0 + p1;
+    t += row_ror<8>(t);
+    t += row_ror<4>(t);
+    t += row_ror<2>(t);
+    t += row_ror<1>(t);
+    return t;
+}
+
 template <int NB>
 __device__ __forceinline__ void sym_tile(const double *__restrict__ q, int n, int I, int J,
                                          const double *const (&w)[NB], double *__restrict__ rp,
-                                         double *__restrict__ cp, double (*__restrict__ rbuf)[SYM_T])
+                                         double *__restrict__ cp, double (*__restrict__ wi)[SYM_T],
+                                         double (*__restrict__ rbuf)[SYM_T])
 {
     using T = Store<DT_F64>;
     constexpr int NSLOT = SYM_WIN / SYM_GRP;     // groups in flight
     const int lane = threadIdx.x & 63;
-    const int c = 2 * lane;
+    const int half = lane >> 5;
+    const int c = 2 * (lane & 31);                // columns c, c + 1 and c + 64, c + 65
     const int gc = J * SYM_T + c;
-    const int gi = I * SYM_T + c;
-    const bool cval = gc < n;
     const int rmax = min(SYM_T, n - I * SYM_T);
     // the resource spans the tile's valid rows; columns past n take a lane offset outside it
     // (rows past rmax, reached only by the window's read-ahead, hold zeros in the packed tile)
     const __amdgpu_buffer_rsrc_t rs = tile_rsrc(q, rmax * SYM_T * 8);
-    const int voff = cval ? c * 8 : OFF_NONE;
-    const int dmask = I == J ? OFF_NONE : 0;
-    // row r; on the diagonal tile a lane whose two columns both lie below the diagonal
-    // (c + 1 < r) reads nothing (the packed tile holds zeros there)
-    auto load = [&](int r) -> u32x4 {
-        const int vo = voff | (dmask & ((c + 1 - r) >> 31));
-        return __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, vo, r * SYM_T * 8, BUF_NT));
+    // instruction k: row pair p = k / 2 (lanes 0..31 row 2p, lanes 32..63 row 2p + 1), column
+    // half h = k % 2.  The scalar offset is the pair's first row (uniform); the half's row and the
+    // columns go into the lane offset.  On the diagonal tile a lane whose two columns both lie
+    // below the diagonal (c_h + 1 < 2p + half, i.e. p >= pd_h) reads nothing.
+    int vbase[2], pd[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int ch = c + 64 * h;
+        vbase[h] = (J * SYM_T + ch < n ? ch * 8 : OFF_NONE) + half * SYM_T * 8;
+        pd[h] = I == J ? (ch + 3 - half) >> 1 : SYM_T;
+    }
+    auto load = [&](int k) -> u32x4 {
+        const int p = k >> 1, h = k & 1;
+        const int vo = p >= pd[h] ? OFF_NONE : vbase[h];
+        return __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, vo, 2 * p * SYM_T * 8, BUF_NT));
     };
+    // w_J at the lane's four columns and w_I at the tile's rows (zero past n); indices past n are
+    // clamped, so that the loads are issued unconditionally and go out together
+    double xj[NB][4], xi[NB][2];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) xj[b][e] = w[b][min(gc + (e & 1) + 64 * (e >> 1), n - 1)];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) xi[b][u] = w[b][min(I * SYM_T + lane + 64 * u, n - 1)];
+    }
     u32x4 v[SYM_WIN];
 #pragma unroll
     for (int i = 0; i < SYM_WIN; ++i) v[i] = load(i);
-    // indices past n are clamped, so that the loads are issued unconditionally and go out
-    // together; their values are then replaced by zero
-    double xj0[NB], xj1[NB], xi0[NB], xi1[NB], ca0[NB], ca1[NB];
-    const int jc0 = min(gc, n - 1), jc1 = min(gc + 1, n - 1);
-    const int ic0 = min(gi, n - 1), ic1 = min(gi + 1, n - 1);
+    // (a wave's LDS accesses complete in order: the group loop reads these writes)
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        const double a0 = w[b][jc0], a1 = w[b][jc1], b0 = w[b][ic0], b1 = w[b][ic1];
-        xj0[b] = cval ? a0 : 0.0;
-        xj1[b] = gc + 1 < n ? a1 : 0.0;
-        xi0[b] = gi < n ? b0 : 0.0;
-        xi1[b] = gi + 1 < n ? b1 : 0.0;
-        ca0[b] = 0.0;
-        ca1[b] = 0.0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (gc + (e & 1) + 64 * (e >> 1) >= n) xj[b][e] = 0.0;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) wi[b][lane + 64 * u] = lane + 64 * u < rmax ? xi[b][u] : 0.0;
     }
+    double ca[NB][4];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ca[b][e] = 0.0;
     GroupLoop<0, SYM_T / SYM_GRP>::run(
         [&](auto gconst) {
             constexpr int G = decltype(gconst)::value;
             constexpr int s0 = (G % NSLOT) * SYM_GRP;   // the group's window slots
-            constexpr int r0 = G * SYM_GRP;
-            // keep each group's broadcasts and partial sums together (bounded register use)
+            constexpr int k0 = G * SYM_GRP;             // its first load instruction (rows 4G..)
             __builtin_amdgcn_sched_barrier(0);
-            double rp4[SYM_GRP][NB];
+            double rp2[2][NB];
 #pragma unroll
-            for (int i = 0; i < SYM_GRP; ++i) {
-                const double q0 = T::get(v[s0 + i], 0), q1 = T::get(v[s0 + i], 1);
+            for (int j = 0; j < 2; ++j) {
+                const u32x4 lo = v[s0 + 2 * j], hi = v[s0 + 2 * j + 1];   // column halves 0 and 1
+                const double q0 = T::get(lo, 0), q1 = T::get(lo, 1), q2 = T::get(hi, 0), q3 = T::get(hi, 1);
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
-                    rp4[i][b] = fma(q1, xj1[b], q0 * xj0[b]);
-                    // rows r = 2 k + e live in lane k, element e (zero past n)
-                    const double xv = lane_bcast((i & 1) ? xi1[b] : xi0[b], (r0 + i) >> 1);
-                    ca0[b] = fma(q0, xv, ca0[b]);
-                    ca1[b] = fma(q1, xv, ca1[b]);
+                    rp2[j][b] = fma(q3, xj[b][3], fma(q2, xj[b][2], fma(q1, xj[b][1], q0 * xj[b][0])));
+                    const double xv = wi[b][k0 + 2 * j + half];   // row 2 (k0 / 2 + j) + half
+                    ca[b][0] = fma(q0, xv, ca[b][0]);
+                    ca[b][1] = fma(q1, xv, ca[b][1]);
+                    ca[b][2] = fma(q2, xv, ca[b][2]);
+                    ca[b][3] = fma(q3, xv, ca[b][3]);
                 }
             }
             __builtin_amdgcn_sched_barrier(0);
-            // the group's rows are consumed: refill its slots with the rows WIN further down
-            if constexpr (r0 + SYM_WIN < SYM_T) {
+            // the group's instructions are consumed: refill its slots with those WIN further on
+            // (a tile is SYM_T instructions: 64 row pairs, two column halves each)
+            if constexpr (k0 + SYM_WIN < SYM_T) {
 #pragma unroll
-                for (int i = 0; i < SYM_GRP; ++i) v[s0 + i] = load(r0 + SYM_WIN + i);
+                for (int i = 0; i < SYM_GRP; ++i) v[s0 + i] = load(k0 + SYM_WIN + i);
             }
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                const double t = reduce4(rp4[0][b], rp4[1][b], rp4[2][b], rp4[3][b]);
-                if ((lane & 15) == 0) rbuf[b][r0 + (lane >> 4)] = t;
+                const double t = reduce2d(rp2[0][b], rp2[1][b]);
+                // 16-lane row g holds tile row k0 + {0, 2, 1, 3}[g]
+                if ((lane & 15) == 0) rbuf[b][k0 + ((lane >> 4) & 1) * 2 + (lane >> 5)] = t;
             }
         },
         rmax);
     __builtin_amdgcn_sched_barrier(0);
-    // coalesced stores (a wave's LDS accesses complete in order, so the reads see the writes)
+    // row results (coalesced; rows past rmax are never read), then the column results: the two
+    // halves of the wave (even and odd rows) add in a fixed order (lower half first)
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         for (int r = lane; r < rmax; r += 64) rp[b * SYM_T + r] = rbuf[b][r];
-        if (cval) cp[b * SYM_T + c] = ca0[b];
-        if (gc + 1 < n) cp[b * SYM_T + c + 1] = ca1[b];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const double o = __shfl_xor(ca[b][e], 32, 64);
+            const int col = c + (e & 1) + 64 * (e >> 1);
+            if (half == 0 && J * SYM_T + col < n) cp[b * SYM_T + col] = ca[b][e] + o;
+        }
     }
 }
 
 template <int B>
 __global__ void __launch_bounds__(64, SYM_WAVES) k_spass(Slot *__restrict__ slots, SymPass sp)
 {
+    __shared__ double wi[B][SYM_T];
     __shared__ double rbuf[B][SYM_T];
     Slot *S = slots;
     if (S->status != ST_RUNNING) return;
@@ -637,12 +650,12 @@ __global__ void __launch_bounds__(64, SYM_WAVES) k_spass(Slot *__restrict__ slot
     double *cp = rp + (size_t)sp.B * SYM_T;
     if (S->mode == MODE_ANCHOR) {
         const double *const w1[1] = {S->x};
-        sym_tile<1>(q, sp.n, I, J, w1, rp, cp, rbuf);
+        sym_tile<1>(q, sp.n, I, J, w1, rp, cp, wi, rbuf);
     } else {
         const double *wb[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) wb[b] = S->xc[b];
-        sym_tile<B>(q, sp.n, I, J, wb, rp, cp, rbuf);
+        sym_tile<B>(q, sp.n, I, J, wb, rp, cp, wi, rbuf);
     }
 }
 
@@ -778,6 +791,7 @@ __device__ __forceinline__ void swap16f(float &a, float &b)
 template <int K>
 __device__ __forceinline__ float row_rorf(float v)
 {
+    // (the update form lets the compiler fold the rotation into the following add)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x120 + K, 0xf, 0xf, false));
 }
 
