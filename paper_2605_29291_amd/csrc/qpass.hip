@@ -538,7 +538,8 @@ __device__ __forceinline__ void sym_tile(const double *__restrict__ q, int n, in
     const int gc = J * SYM_T + c;
     const int rmax = min(SYM_T, n - I * SYM_T);
     // the resource spans the tile's valid rows; columns past n take a lane offset outside it
-    // (rows past rmax, reached only by the window's read-ahead, hold zeros in the packed tile)
+    // (rows past rmax, reached by the window's read-ahead and by the last group of four rows,
+    // hold zeros in the packed tile)
     const __amdgpu_buffer_rsrc_t rs = tile_rsrc(q, rmax * SYM_T * 8);
     // instruction k: row pair p = k / 2 (lanes 0..31 row 2p, lanes 32..63 row 2p + 1), column
     // half h = k % 2.  The scalar offset is the pair's first row (uniform); the half's row and the
