@@ -1155,7 +1155,7 @@ static qcqp_status eval_loaded_point(qcqp_handle *h)
     S.y = h->d_ye;
     S.Uc[0] = h->d_ueval;
     S.Gc[0] = h->d_geval;
-    HIPCHK(hipMemsetAsync(h->d_ueval, 0, (h->m + 1) * h->n * 8, h->stream));
+    HIPCHK(launch_fill(h->stream, h->d_ueval, (h->m + 1) * h->n, 0.0));   // rows of matrices not stored
     HIPCHK(hipMemcpyAsync(h->dslot_eval, &S, sizeof(Slot), hipMemcpyHostToDevice, h->stream));
     HIPCHK(launch_pass_only(h->stream, h->dslot_eval, h->dtiles, (int)h->tiles.size(), h->dstarts, h->B, h->dtype, (int)h->nw, h->pass_grid, h->nt,
                             h->sym64(), h->sym16()));
@@ -1168,7 +1168,7 @@ static qcqp_status load_point(qcqp_handle *h, const double *x, const double *y, 
     const hipMemcpyKind k = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     if (x != h->d_xe) HIPCHK(hipMemcpyAsync(h->d_xe, x, h->n * 8, k, h->stream));
     if (h->ny) {
-        if (!y) HIPCHK(hipMemsetAsync(h->d_ye, 0, h->ny * 8, h->stream));
+        if (!y) HIPCHK(launch_fill(h->stream, h->d_ye, h->ny, 0.0));
         else if (y != h->d_ye) HIPCHK(hipMemcpyAsync(h->d_ye, y, h->ny * 8, k, h->stream));
     }
     return QCQP_OK;
@@ -1215,8 +1215,11 @@ static qcqp_status gap_enqueue(qcqp_handle *h, const double *x_dev, const double
     double *rowabs = v0, *Z = v0 + vs, *D = v0 + 2 * vs, *Dn = v0 + 3 * vs, *Hz = v0 + 4 * vs;
     double *part = v0 + 6 * vs, *ctl = part + 2 * GAP_MAX_BLOCKS;
     GridBar *bar = reinterpret_cast<GridBar *>(ctl + 32);
-    HIPCHK(hipMemsetAsync(Z, 0, 2 * vs * 8, h->stream));   // Z and D
-    HIPCHK(hipMemsetAsync(bar, 0, sizeof(GridBar), h->stream));
+    // Z and D, then the barrier words (all-zero bits), cleared by a fill kernel rather than
+    // memset nodes, so that a caller may capture this work into a graph
+    static_assert(sizeof(GridBar) % sizeof(double) == 0, "GridBar is cleared as doubles");
+    HIPCHK(launch_fill(h->stream, Z, 2 * vs, 0.0));
+    HIPCHK(launch_fill(h->stream, reinterpret_cast<double *>(bar), sizeof(GridBar) / sizeof(double), 0.0));
     HIPCHK(launch_gap_setup(h->stream, h->dslot_eval, (int)n, (int)h->ny, h->d_ye, h->d_geval, h->d_grad, xi, H,
                             (int)ldh, rowabs, h->opt.inner_tol, ctl));
     // the LDS form uses Hz (written only after the loop) as the second step buffer
