@@ -56,7 +56,8 @@ class _Info(C.Structure):
 def lib():
     global _LIB
     if _LIB is None:
-        # ORACLE_LIB names another build of the same source (the sanitizer run of the pins)
+        # ORACLE_LIB names another build: the sanitizer build of the same source, or a copy with
+        # a planted mistake that the pins must catch
         path = os.environ.get("ORACLE_LIB") or _build.LIB
         if path == _build.LIB and (not os.path.exists(path) or
                                    os.path.getmtime(path) < os.path.getmtime(_build.SRC)):

@@ -21,6 +21,15 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_from(src_path: str, out_path: str) -> str:
+    """Build another copy of the oracle's source (the tests' planted-mistake copies) with the
+    flags of build()."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter",
+           "-o", out_path, src_path, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out_path
+
+
 def build_sanitized(out_path: str) -> str:
     """AddressSanitizer + UndefinedBehaviorSanitizer build of the oracle (host code only), for
     running the CPU pins under the sanitizers; any report aborts the process."""
