@@ -160,6 +160,26 @@ def test_kkt_residual_at_closed_form_and_off_it(orc):
     assert k3["rel_comp"] > 1e-2 and k3["rel_pri"] == 0.0
 
 
+def test_kkt_residual_worked_example(orc):
+    """A one-variable instance worked by hand, with every term of the normalisations nonzero
+    and distinct: Q_0 = 2, q_0 = 0, c_0 = 0; Q_1 = 4, q_1 = 1, c_1 = -2; A = 2, b = 0.5;
+    X = [-10, 10]; at x = 0.5, v = 0.5, lambda = 3:
+      Q_0 x + q_0 = 1,  lambda (Q_1 x + q_1) = 3 * 3 = 9,  A'v = 1,  grad_x Phi = 11,
+      r_x = 0.5 - clip(0.5 - 11) = 0.5 + 10 = 10.5,  rel_dual = 10.5 / (1 + 1 + 9 + 1) = 0.875;
+      g_1 = 0.5 + 0.5 - 2 = -1,  r_l = |min(3, 1)| = 1,  rel_comp = 1 / (1 + 2) = 1/3;
+      Ax - b = 0.5,  rel_pri = 0.5 / (1 + 2 + 0.5) = 1/7;
+      f = 0.25;  largest violation 0.5."""
+    P = orc.Problem(Q=np.array([[[2.0]], [[4.0]]]), q=np.array([[0.0], [1.0]]), c=np.array([0.0, -2.0]),
+                    lb=np.array([-10.0]), ub=np.array([10.0]), A=np.array([[2.0]]), b=np.array([0.5]))
+    k = orc.kkt(P, np.array([0.5]), np.array([0.5, 3.0]))
+    assert k["rel_dual"] == pytest.approx(0.875, rel=1e-15)
+    assert k["rel_comp"] == pytest.approx(1.0 / 3.0, rel=1e-15)
+    assert k["rel_pri"] == pytest.approx(1.0 / 7.0, rel=1e-15)
+    assert k["rel_kkt"] == pytest.approx(0.875, rel=1e-15)
+    assert k["f"] == pytest.approx(0.25, rel=1e-15)
+    assert k["max_violation"] == pytest.approx(0.5, rel=1e-15)
+
+
 def _np_ops(inst, x):
     """U, grad_y Phi = (Ax-b, g(x)) computed with numpy, independently of the oracle."""
     U = np.einsum("irj,j->ir", inst.Q, x)
@@ -177,13 +197,17 @@ def _np_gradx(inst, x, lam):
     return U[0] + inst.q[0] + lam @ (U[1:] + inst.q[1:])
 
 
+@pytest.mark.parametrize("start", ["origin", "positive_multipliers"])
 @pytest.mark.parametrize("variant", ["yx", "xy"])
-def test_test_function_matches_printed_definition(orc, variant):
+def test_test_function_matches_printed_definition(orc, variant, start):
     """Re-evaluate E_k from its printed definition (Phi differences for yx, gradient
     differences for xy) for the first iterations and check the oracle's accept/reject
-    sequence, its recorded E_k and its next iterate."""
+    sequence, its recorded E_k and its next iterate.  From lambda^0 = 0 the first dual step of
+    yx stays at 0 on this instance (g(x^0) < 0), so the term of E_0 that carries alpha_0 is
+    zero; the start with lambda^0 > 0 makes it count."""
     inst = qi.random_qcqp(12, 3, seed=31, shift=0.05)
     P = orc.Problem(inst)
+    y0 = None if start == "origin" else np.full(inst.m, 0.5)
     eta, tb, g0 = 0.7, 2.0, 0.3
     if variant == "yx":
         ca, cb, dl = 0.4, 0.0, 0.5
@@ -194,7 +218,7 @@ def test_test_function_matches_printed_definition(orc, variant):
     for k in range(K + 1):
         o = orc.Options(variant=variant, tau_bar=tb, gamma0=g0, restart="none", max_iter=k,
                         tol=0.0, c_alpha=ca, c_beta=cb, delta=dl, eta=eta)
-        runs.append(orc.solve(P, o, trace_cap=K))
+        runs.append(orc.solve(P, o, y0=y0, trace_cap=K))
     tr = runs[K]["trace"]
     for k in range(K):
         x, lam = runs[k]["x"], runs[k]["y"]

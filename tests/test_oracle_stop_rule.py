@@ -2,6 +2,8 @@
 max{ |f(x) - f*| / (1 + |f*|), mean constraint violation } <= tol for a known optimal value f*.
 The criterion is re-evaluated from the problem data with numpy at the iterate where the solve
 stops and at the iterate before it (obtained by capping the iteration count)."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -43,3 +45,23 @@ def test_paper_stop_rule_fires_at_the_first_crossing(orc, variant):
     assert _paper_criterion_numpy(inst.Q, inst.q, inst.c, before["x"], fs) > 1e-6
     np.testing.assert_allclose(r["x"], orc.solve(P, mk(tol=0.0, **dict(kw, max_iter=k)))["x"],
                                rtol=0, atol=0)
+
+
+def test_paper_criterion_counts_equality_constraints(orc):
+    """With p equality constraints the mean violation of §5.1 runs over the p + m scalar
+    constraints: |Ax - b| for each equality, [g_i]_+ for each inequality.  Compared with numpy
+    at early iterates of a capped solve, where both parts of the criterion are large."""
+    inst = qi.paper_random_qcqp(40, 4, seed=5)
+    rng = np.random.default_rng(11)
+    A = rng.standard_normal((2, inst.n))
+    b = A @ np.full(inst.n, 0.1)
+    inst = dataclasses.replace(inst, p=2, A=A, b=b)
+    P = orc.Problem(inst)
+    L = np.linalg.norm(inst.Q[0], 2)
+    fs = -1.0
+    for k in (1, 3, 8):
+        r = orc.solve(P, orc.Options(tau_bar=1 / L, gamma0=1.0, stop_rule="paper", f_star=fs, tol=0.0,
+                                     max_iter=k))
+        assert r["info"]["iters"] == k
+        ref = _paper_criterion_numpy(inst.Q, inst.q, inst.c, r["x"], fs, A=A, b=b)
+        assert abs(r["info"]["stop_value"] - ref) <= 1e-12 * max(1.0, ref), (k, r["info"]["stop_value"], ref)
