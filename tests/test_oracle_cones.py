@@ -188,3 +188,26 @@ def test_cone_validation(orc):
     bad = np.array([0, 1, 1], dtype=np.int32)       # disagrees with has_q0
     P = orc.Problem(Q=Q[1:], q=q, c=c, lb=lb, ub=ub, q_stored=bad)
     assert orc.solve(P, o)["info"]["status"] == "invalid"
+
+
+def test_cone_kkt_residual_worked_example(orc):
+    """One variable, one scalar constraint in R_+ and one second-order cone of dimension 2,
+    all affine (only Q_0 = 2 stored), worked by hand at x = 1, lambda = 0:
+      g = (q_i x + c_i) = (0.5, (1, 3));  Pi_{R_+}(0.5) = 0.5;  the cone block (t, u) = (1, 3)
+      has |u| > |t|, so Pi_Q = ((1 + 3) / 2) (1, 3 / 3) = (2, 2), of norm 2 sqrt(2);
+      dist(g, -K) = ||Pi_K*(g)|| = sqrt(0.25 + 8) and the largest violation is 2 sqrt(2);
+      r_l = ||lambda - Pi_K*(lambda + g)|| = sqrt(8.25);  ||c_{1..3}|| = sqrt(10.25);
+      grad_x Phi = Q_0 x = 2, r_x = 1 - clip(1 - 2) = 2, rel_dual = 2 / (1 + 2)."""
+    q = np.zeros((4, 1))
+    c = np.array([0.0, 0.5, 1.0, 3.0])
+    stored = np.array([1, 0, 0, 0], dtype=np.int32)
+    P = orc.Problem(Q=np.array([[[2.0]]]), q=q, c=c, lb=np.array([-10.0]), ub=np.array([10.0]),
+                    lambda_set="cones", soc_dims=[2], q_stored=stored)
+    k = orc.kkt(P, np.array([1.0]), np.zeros(3))
+    den = 1.0 + np.sqrt(10.25)
+    assert k["max_violation"] == pytest.approx(2.0 * np.sqrt(2.0), rel=1e-15)
+    assert k["rel_pri"] == pytest.approx(np.sqrt(8.25) / den, rel=1e-15)
+    assert k["rel_comp"] == pytest.approx(np.sqrt(8.25) / den, rel=1e-15)
+    assert k["rel_dual"] == pytest.approx(2.0 / 3.0, rel=1e-15)
+    assert k["rel_kkt"] == pytest.approx(np.sqrt(8.25) / den, rel=1e-15)
+    assert k["f"] == pytest.approx(1.0, rel=1e-15)

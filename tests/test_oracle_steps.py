@@ -12,6 +12,8 @@ and bounds that any correct implementation satisfies:
 Smoothed gap (Definition in §4, Remark in §4.2): G >= 0 on the domain, G ~ 0 at a saddle point,
 and the x-/y-parts agree with brute force (face enumeration of the box QP, scipy on y).
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -181,33 +183,47 @@ def test_kkt_residual_worked_example(orc):
 
 
 def _np_ops(inst, x):
-    """U, grad_y Phi = (Ax-b, g(x)) computed with numpy, independently of the oracle."""
+    """U and grad_y Phi = (Ax - b, g(x)) with f(x), computed with numpy, independently of the
+    oracle (y = (v, lambda))."""
     U = np.einsum("irj,j->ir", inst.Q, x)
     g = np.array([0.5 * x @ U[i] + inst.q[i] @ x + inst.c[i] for i in range(inst.m + 1)])
-    return U, g[1:], g[0]
+    r = inst.A @ x - inst.b if inst.p else np.zeros(0)
+    return U, np.concatenate([r, g[1:]]), g[0]
 
 
-def _np_phi(inst, x, lam):
-    U, g, f = _np_ops(inst, x)
-    return f + lam @ g
+def _np_phi(inst, x, y):
+    U, G, f = _np_ops(inst, x)
+    return f + y @ G
 
 
-def _np_gradx(inst, x, lam):
+def _np_gradx(inst, x, y):
     U, _, _ = _np_ops(inst, x)
-    return U[0] + inst.q[0] + lam @ (U[1:] + inst.q[1:])
+    gx = U[0] + inst.q[0] + y[inst.p:] @ (U[1:] + inst.q[1:])
+    return gx + inst.A.T @ y[:inst.p] if inst.p else gx
 
 
+def _np_proj(inst, y):
+    """onto R^p x R^m_+"""
+    return np.concatenate([y[:inst.p], np.maximum(0.0, y[inst.p:])])
+
+
+@pytest.mark.parametrize("constraints", ["inequalities", "with_equalities"])
 @pytest.mark.parametrize("start", ["origin", "positive_multipliers"])
 @pytest.mark.parametrize("variant", ["yx", "xy"])
-def test_test_function_matches_printed_definition(orc, variant, start):
+def test_test_function_matches_printed_definition(orc, variant, start, constraints):
     """Re-evaluate E_k from its printed definition (Phi differences for yx, gradient
     differences for xy) for the first iterations and check the oracle's accept/reject
     sequence, its recorded E_k and its next iterate.  From lambda^0 = 0 the first dual step of
     yx stays at 0 on this instance (g(x^0) < 0), so the term of E_0 that carries alpha_0 is
-    zero; the start with lambda^0 > 0 makes it count."""
+    zero; the start with lambda^0 > 0 makes it count.  The second instance adds two equality
+    constraints Ax = b (v free), whose multipliers enter grad_x Phi through A'v."""
     inst = qi.random_qcqp(12, 3, seed=31, shift=0.05)
+    if constraints == "with_equalities":
+        A = np.random.default_rng(3).standard_normal((2, inst.n))
+        inst = dataclasses.replace(inst, p=2, A=A, b=A @ np.full(inst.n, 0.05))
     P = orc.Problem(inst)
-    y0 = None if start == "origin" else np.full(inst.m, 0.5)
+    ny = inst.p + inst.m
+    y0 = None if start == "origin" else np.concatenate([np.full(inst.p, -0.3), np.full(inst.m, 0.5)])
     eta, tb, g0 = 0.7, 2.0, 0.3
     if variant == "yx":
         ca, cb, dl = 0.4, 0.0, 0.5
@@ -221,8 +237,8 @@ def test_test_function_matches_printed_definition(orc, variant, start):
         runs.append(orc.solve(P, o, y0=y0, trace_cap=K))
     tr = runs[K]["trace"]
     for k in range(K):
-        x, lam = runs[k]["x"], runs[k]["y"]
-        xp, lamp = (runs[k - 1]["x"], runs[k - 1]["y"]) if k else (x, lam)
+        x, yk = runs[k]["x"], runs[k]["y"][:ny]
+        xp, yp = (runs[k - 1]["x"], runs[k - 1]["y"][:ny]) if k else (x, yk)
         sig_prev = tr[k - 1, 1] if k else g0 * tb
         tau_prev = tr[k - 1, 0] if k else tb
         tau_pp = (tr[k - 2, 0] if k >= 2 else tb)
@@ -236,28 +252,28 @@ def test_test_function_matches_printed_definition(orc, variant, start):
             sig = g0 * tau
             th = sig_prev / sig
             if variant == "yx":
-                ly = np.maximum(0, lam + sig * ((1 + th) * G - th * Gp))
+                ly = _np_proj(inst, yk + sig * ((1 + th) * G - th * Gp))
                 xn = np.clip(x - tau * _np_gradx(inst, x, ly), inst.lb, inst.ub)
                 d = xn - x
                 _, Gn, _ = _np_ops(inst, xn)
                 E = (_np_phi(inst, xn, ly) - _np_phi(inst, x, ly) - _np_gradx(inst, x, ly) @ d
                      - 0.5 * d @ d / tau + np.sum((Gn - G) ** 2) / (2 * ca / sig)
-                     - (1 / sig - th * alpha_k) * 0.5 * np.sum((ly - lam) ** 2))
+                     - (1 / sig - th * alpha_k) * 0.5 * np.sum((ly - yk) ** 2))
             else:
-                s = (1 + th) * _np_gradx(inst, x, lam) - th * _np_gradx(inst, xp, lamp)
+                s = (1 + th) * _np_gradx(inst, x, yk) - th * _np_gradx(inst, xp, yp)
                 xn = np.clip(x - tau * s, inst.lb, inst.ub)
                 d = xn - x
                 _, Gn, _ = _np_ops(inst, xn)
-                ly = np.maximum(0, lam + sig * Gn)
+                ly = _np_proj(inst, yk + sig * Gn)
                 a1, b1 = ca / tau, g0 * cb / sig
-                E = (np.sum((_np_gradx(inst, xn, ly) - _np_gradx(inst, xn, lam)) ** 2) / (2 * a1)
-                     - 0.5 * np.sum((ly - lam) ** 2) / sig
-                     + np.sum((_np_gradx(inst, xn, lam) - _np_gradx(inst, x, lam)) ** 2) / (2 * b1)
+                E = (np.sum((_np_gradx(inst, xn, ly) - _np_gradx(inst, xn, yk)) ** 2) / (2 * a1)
+                     - 0.5 * np.sum((ly - yk) ** 2) / sig
+                     + np.sum((_np_gradx(inst, xn, yk) - _np_gradx(inst, x, yk)) ** 2) / (2 * b1)
                      - (1 / tau - th * (alpha_k + beta_k)) * 0.5 * d @ d)
-            rhs = -dl / tau * 0.5 * d @ d - dl / sig * 0.5 * np.sum((ly - lam) ** 2)
+            rhs = -dl / tau * 0.5 * d @ d - dl / sig * 0.5 * np.sum((ly - yk) ** 2)
             if E <= rhs:
                 break
         assert j + 1 == int(tr[k, 2]), (k, j, tr[k])
         assert abs(E - tr[k, 3]) <= 1e-7 * (abs(E) + abs(rhs))
         np.testing.assert_allclose(runs[k + 1]["x"], xn, rtol=1e-11, atol=1e-12)
-        np.testing.assert_allclose(runs[k + 1]["y"], ly, rtol=1e-11, atol=1e-12)
+        np.testing.assert_allclose(runs[k + 1]["y"][:ny], ly, rtol=1e-11, atol=1e-12)
