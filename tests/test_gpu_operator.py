@@ -26,7 +26,7 @@ def _check_operator(inst, storage="float64", device=False, seed=0, tol=1e-12):
     assert_operator_parity(inst, x, y, out, ref, tol=tol)
     kk = s.eval_kkt(x, y)
     kr = oracle.kkt(P, x, y)
-    for k in ("rel_kkt", "rel_dual", "rel_pri", "rel_comp", "f"):
+    for k in ("rel_kkt", "rel_dual", "rel_pri", "rel_comp", "f", "max_violation"):
         assert abs(kk[k] - kr[k]) <= 1e-11 * (abs(kr[k]) + 1e-12), (k, kk[k], kr[k])
     s.close()
 
