@@ -72,3 +72,36 @@ def test_table2_row_stops_where_the_oracle_stops(name):
     crit = max(abs(f - f_star) / (1 + abs(f_star)), float(np.mean(np.maximum(g, 0.0))))
     assert info["stop_value"] <= 1e-7
     assert abs(crit - info["stop_value"]) <= 1e-12, (crit, info["stop_value"])
+
+
+@pytest.mark.parametrize("variant", ["yx", "xy"])
+def test_paper_stop_rule_with_equality_constraints(variant):
+    """The criterion of §5.1 with two equality constraints: the mean violation runs over the
+    p + m scalar constraints (|Ax - b| for each equality).  The GPU stops at the oracle's
+    iteration, and its stop value is the criterion at the returned point evaluated from the
+    data."""
+    import dataclasses
+    from paper_2605_29291_amd import Solver
+    inst = qi.paper_random_qcqp(100, 10, seed=qi.config_seed(6))
+    A = np.random.default_rng(11).standard_normal((2, inst.n))
+    b = A @ np.full(inst.n, 0.1)
+    inst = dataclasses.replace(inst, p=2, A=A, b=b)
+    P = oracle.Problem(inst)
+    tb = 1 / np.linalg.norm(inst.Q[0], 2)
+    ref0 = oracle.solve(P, oracle.Options(tau_bar=tb, gamma0=1.0, tol=1e-11, max_iter=200000))
+    assert ref0["info"]["status"] == "converged"
+    f_star = ref0["info"]["f"]
+    common = dict(tau_bar=tb, gamma0=1.0, tol=1e-7, stop_rule="paper", f_star=f_star, max_iter=50000,
+                  restart="fixed", restart_every=400)
+    mk = oracle.Options.xy if variant == "xy" else oracle.Options
+    ref = oracle.solve(P, mk(**common))
+    announce(f"stop rule of §5.1 with p=2 ({variant}): oracle stopped at {ref['info']['iters']}")
+    x, y, info = Solver(inst, variant=variant, **dict(common, **(XY if variant == "xy" else {}))).solve()
+    assert ref["info"]["status"] == "converged" and info["status"] == "ok", (info, ref["info"])
+    assert info["iters"] == ref["info"]["iters"], (info["iters"], ref["info"]["iters"])
+    xs = to_np(x)
+    f = 0.5 * xs @ inst.Q[0] @ xs + inst.q[0] @ xs
+    g = np.array([0.5 * xs @ inst.Q[i] @ xs + inst.q[i] @ xs + inst.c[i] for i in range(1, inst.m + 1)])
+    viol = np.concatenate([np.abs(A @ xs - b), np.maximum(g, 0.0)])
+    crit = max(abs(f - f_star) / (1 + abs(f_star)), float(np.mean(viol)))
+    assert abs(crit - info["stop_value"]) <= 1e-12, (crit, info["stop_value"])
