@@ -36,6 +36,33 @@ def test_trajectory_matches_oracle(K):
     np.testing.assert_allclose(to_np(y), ref["y"], rtol=1e-10, atol=1e-11)
 
 
+@pytest.mark.parametrize("variant", ["yx", "xy"])
+@pytest.mark.parametrize("K", [1, 5, 25])
+def test_trajectory_from_a_start_with_positive_multipliers(K, variant):
+    """From a given (x^0, y^0) with lambda^0 > 0 and v^0 != 0 on an instance with two equality
+    constraints: the first test functions then carry the epoch's starting alpha_0 (and beta_0)
+    and A'v, which a start at y^0 = 0 leaves out.  Same iterates and trial counts as the oracle
+    from the same start."""
+    import dataclasses
+    inst = qi.random_qcqp(100, 10, qi.config_seed(1))
+    A = np.random.default_rng(13).standard_normal((2, inst.n))
+    inst = dataclasses.replace(inst, p=2, A=A, b=A @ np.full(inst.n, 0.05))
+    tb = tau_bar_of(inst)
+    rng = np.random.default_rng(17)
+    x0 = rng.uniform(-0.5, 0.5, inst.n)
+    y0 = np.concatenate([rng.standard_normal(2), rng.uniform(0.1, 1.0, inst.m)])
+    xy = dict(c_alpha=0.25, c_beta=0.3, delta=0.4) if variant == "xy" else {}
+    announce(f"trajectory from (x0, y0) K={K} {variant}")
+    s = _solver(inst, **gpu_opts(tb, max_iter=K, tol=0.0, spec_trials=2, variant=variant, **xy))
+    x, y, info = s.solve(x0, y0)
+    mk = oracle.Options.xy if variant == "xy" else oracle.Options
+    ref = oracle.solve(oracle.Problem(inst), mk(tau_bar=tb, gamma0=0.1, max_iter=K, tol=0.0), x0=x0, y0=y0)
+    assert info["iters"] == K == ref["info"]["iters"]
+    assert info["trials"] == ref["info"]["trials"]
+    np.testing.assert_allclose(to_np(x), ref["x"], rtol=1e-10, atol=1e-11)
+    np.testing.assert_allclose(to_np(y), ref["y"][:inst.p + inst.m], rtol=1e-10, atol=1e-11)
+
+
 def test_speculative_candidates_are_bitwise_sequential():
     inst = qi.random_qcqp(150, 12, seed=5, shift=0.01)
     tb = tau_bar_of(inst)
