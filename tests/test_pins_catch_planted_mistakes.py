@@ -6,9 +6,10 @@ operand, a step taken at the wrong point) in a copy of qcqp_oracle.c, builds the
 oracle's own flags and runs every oracle pin (tests/test_oracle_*.py without the sanitizer run)
 against it in a child process (ORACLE_LIB names the copy); the run must report a failure.  The
 cases cover the operator and its storage decoders, the stored-matrix map, the constraint values
-and gradient, the dual-domain projections (orthant, simplex, second-order cones, balls), both
-test functions and their steps, the averages, the step-size rule, the relative KKT residual
-(orthant, simplex and cone forms), the §5.1 criterion, G_xi and the epoch start.  The restart
+and gradient, the dual-domain projections (orthant, simplex, second-order cones, balls, and
+their order), both test functions and their steps, the averages, the step-size rule and its
+state shift, the relative KKT residual (orthant, simplex and cone forms), the §5.1 criterion,
+G_xi, the epoch start (momentum reset) and the restart point's evaluation.  The restart
 driver's cases run by default in tests/test_restart_pins_catch_mistakes.py.
 
 One measured mistake is left out because it changes no result: dropping the gradient restart of
@@ -35,6 +36,9 @@ MISTAKES = {
     'avg_weight_uniform': (
         'double tk = sig / ep->sig0;',
         'double tk = 1.0;'),
+    'ball_before_cone': (
+        '    project_kstar(P, lam);\n    if (P->ball > 0.0) scale_to_ball(y, p + m, P->ball);',
+        '    if (P->ball > 0.0) scale_to_ball(y, p + m, P->ball);\n    project_kstar(P, lam);'),
     'ball_not_applied': (
         '    if (P->ball > 0.0) scale_to_ball(y, p + m, P->ball);',
         '    if (P->ball > 1e300) scale_to_ball(y, p + m, P->ball);'),
@@ -47,6 +51,12 @@ MISTAKES = {
     'epoch_alpha_tau': (
         'ep->alpha_k = (o->variant == 0) ? o->c_alpha / ep->sig_prev : o->c_alpha / ep->tau_prev;',
         'ep->alpha_k = (o->variant == 0) ? o->c_alpha / ep->tau_prev : o->c_alpha / ep->tau_prev;'),
+    'epoch_keeps_momentum_x': (
+        '    memcpy(S->Gyp, S->Gy, sizeof(double) * S->ny);\n    memcpy(S->gxp, S->gxk, sizeof(double) * S->n);\n    memset(S->cx',
+        '    memcpy(S->Gyp, S->Gy, sizeof(double) * S->ny);\n    memset(S->cx'),
+    'epoch_keeps_momentum_y': (
+        '    memcpy(S->Gyp, S->Gy, sizeof(double) * S->ny);\n    memcpy(S->gxp, S->gxk, sizeof(double) * S->n);\n    memset(S->cx',
+        '    memcpy(S->gxp, S->gxk, sizeof(double) * S->n);\n    memset(S->cx'),
     'eta_not_applied_once': (
         '        ep->tau *= o->eta;                   /* tau_k <- eta tau_k */',
         '        ep->tau *= o->eta * o->eta;'),
@@ -101,6 +111,9 @@ MISTAKES = {
     'kkt_dual_denominator_s1': (
         'double rel_dual = sqrt(rx) / (1.0 + sqrt(s0) + sqrt(s1) + sqrt(s2));',
         'double rel_dual = sqrt(rx) / (1.0 + sqrt(s0) + sqrt(s2));'),
+    'kkt_pri_includes_negative_g': (
+        '            if (g > 0) { pri += g * g; if (g > maxv) maxv = g; }',
+        '            { pri += g * g; if (g > maxv) maxv = g; }'),
     'kkt_pri_no_b': (
         '    double rel_pri = sqrt(pri) / (1.0 + sqrt(cn) + sqrt(bn));',
         '    double rel_pri = sqrt(pri) / (1.0 + sqrt(cn));'),
@@ -128,6 +141,9 @@ MISTAKES = {
     'paper_mean_over_m': (
         'double mv = cnt > 0 ? viol / (double)cnt : 0.0;',
         'double mv = m > 0 ? viol / (double)m : 0.0;'),
+    'restart_point_not_installed': (
+        '        for (int64_t l = 0; l < S->ny; ++l) S->y[l] = S->cy[l] / S->T;\n        install_point(S);',
+        '        for (int64_t l = 0; l < S->ny; ++l) S->y[l] = S->cy[l] / S->T;'),
     'rhs_delta_dual_dropped': (
         'rhs = -(o->delta / tau) * Dp - (o->delta / sig) * Dd;\n            if (E <= rhs) {\n                ep->alpha_k = alpha_next;\n                break;',
         'rhs = -(o->delta / tau) * Dp;\n            if (E <= rhs) {\n                ep->alpha_k = alpha_next;\n                break;'),
@@ -137,9 +153,15 @@ MISTAKES = {
     'separable_ball_v_on_all': (
         '    if (P->ball_v > 0.0) scale_to_ball(y, p, P->ball_v);',
         '    if (P->ball_v > 0.0) scale_to_ball(y, p + m, P->ball_v);'),
+    'sigma_prev_not_shifted': (
+        '    ep->sig_prev = sig;\n    ep->tau_prev = tau;',
+        '    ep->tau_prev = tau;'),
     'simplex_kkt_sign': (
         '        for (int64_t i = 0; i < m; ++i) w[i] = y[p + i] + Gy[p + i];\n        project_simplex(w, m);',
         '        for (int64_t i = 0; i < m; ++i) w[i] = y[p + i] - Gy[p + i];\n        project_simplex(w, m);'),
+    'simplex_no_clip': (
+        '    for (int64_t i = 0; i < k; ++i) z[i] = z[i] > theta ? z[i] - theta : 0.0;',
+        '    for (int64_t i = 0; i < k; ++i) z[i] = z[i] - theta;'),
     'simplex_theta_last': (
         '        if (u[j] > t) theta = t;',
         '        theta = t;'),
@@ -155,6 +177,12 @@ MISTAKES = {
     'stored_index_skip': (
         '        for (int64_t k = 0; k < i; ++k) s += P->q_stored[k] ? 1 : 0;',
         '        for (int64_t k = 0; k < i; ++k) s += 1;'),
+    'theta_inverted': (
+        '        th = ep->sig_prev / sig;             /* theta_k = sigma_{k-1} / sigma_k */',
+        '        th = sig / ep->sig_prev;'),
+    'trace_tau_next': (
+        '        trace_row[0] = tau; trace_row[1] = sig;',
+        '        trace_row[0] = tau_next; trace_row[1] = sig;'),
     'xy_E_Dd_sign': (
         '            E = nrm2sq(S->gtmp, n) / (2.0 * alpha_next) - Dd / sig +',
         '            E = nrm2sq(S->gtmp, n) / (2.0 * alpha_next) + Dd / sig +'),
@@ -185,6 +213,9 @@ MISTAKES = {
     'yx_E_theta_alpha_dropped': (
         'E = quad - Dp / tau + dG / (2.0 * alpha_next) - (1.0 / sig - th * ep->alpha_k) * Dd;',
         'E = quad - Dp / tau + dG / (2.0 * alpha_next) - (1.0 / sig) * Dd;'),
+    'yx_alpha_next_tau': (
+        'double alpha_next = o->c_alpha / sig;                    /* alpha_{k+1} = c_a / sigma_k */',
+        'double alpha_next = o->c_alpha / tau;'),
     'yx_grad_at_old_y': (
         '            grad_x(P, S->U, S->yt, S->gtmp);',
         '            grad_x(P, S->U, S->y, S->gtmp);'),
