@@ -211,3 +211,36 @@ def test_dual_domain_validation():
     bad = qi.random_qcqp(20, 0, seed=41, shift=0.01)
     with pytest.raises(QCQPError):
         _solver(bad, tau_bar=1.0, lambda_set="simplex")
+
+
+@pytest.mark.parametrize("case", ["equality", "ball", "separable_balls", "simplex", "cones"])
+def test_gap_matches_oracle_over_dual_domains(case):
+    """G_xi (Definition in §4, Remark in §4.2) at given points for each dual domain: the y-part
+    projects onto R^p x K* (orthant, simplex, cones) intersected with the requested ball, and
+    the x-part's Hessian carries the identity part of the objective (simplex case, rho = 1).
+    Py and Px equal the oracle's at the bars of the lambda >= 0 case."""
+    from paper_2605_29291_amd import Solver
+    kw_gpu, kw_orc = {}, {}
+    if case == "simplex":
+        inst = _simplex_inst(80, 5, seed=31)
+    elif case == "cones":
+        inst = qi.random_conic_qcqp(80, 2, [3, 4], seed=37, p=1)
+    else:
+        inst = qi.random_qcqp(80, 5, seed=29, shift=0.01, p=2)
+        if case == "ball":
+            kw_gpu = kw_orc = dict(ball=1.5)
+        elif case == "separable_balls":
+            kw_gpu, kw_orc = dict(ball_v=0.7, ball_lambda=0.9), dict(ball_v=0.7, ball_l=0.9)
+    P = oracle.Problem(inst, **kw_orc)
+    s = _solver(inst, tau_bar=1.0, **kw_gpu)
+    rng = np.random.default_rng(23)
+    for trial in range(2):
+        x = rng.uniform(-1, 1, inst.n)
+        y = np.concatenate([rng.standard_normal(inst.p), rng.uniform(0, 0.5, inst.m)])
+        announce(f"G_xi over the {case} domain, point {trial}")
+        g = s.eval_gap(x, y, xi=0.04)
+        r = oracle.gap(P, x, y, xi=0.04)
+        assert abs(g["Py"] - r["Py"]) <= 1e-11 * (1 + abs(r["Py"])), (g, r)
+        assert abs(g["Px"] - r["Px"]) <= 1e-9 * (1 + abs(r["Px"])), (g, r)
+        assert g["G"] == pytest.approx(g["Py"] + g["Px"], rel=1e-15, abs=1e-300)
+    s.close()
