@@ -182,3 +182,31 @@ def test_sym_refusals():
     b.close()
     x, y, info = s.solve()
     assert info["status"] == "ok"
+
+
+def test_sym_adaptive_restart_and_gap():
+    """The packed FP64 pass with the adaptive restart of eq. (ada_restart): G_xi at a given point
+    on the packed handle equals the oracle's (its anchor pass streams the packed tiles, its box
+    QP reads the row-major stack), and the solve takes the oracle's restart decisions on the
+    schedule (iterations within 1 %, the same restart count)."""
+    inst = qi.random_qcqp(300, 8, seed=43, shift=0.01)
+    tb = tau_bar_of(inst)
+    P = oracle.Problem(inst)
+    s = _solver(inst, sym_pass=1, spec_trials=3, tau_bar=tb)
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-1, 1, inst.n)
+    y = rng.uniform(0, 0.5, inst.m)
+    announce("sym G_xi at a point")
+    g = s.eval_gap(x, y, xi=0.04)
+    r = oracle.gap(P, x, y, xi=0.04)
+    assert abs(g["Py"] - r["Py"]) <= 1e-11 * (1 + abs(r["Py"])), (g, r)
+    assert abs(g["Px"] - r["Px"]) <= 1e-9 * (1 + abs(r["Px"])), (g, r)
+    s.close()
+    kw = dict(tau_bar=tb, gamma0=0.1, tol=1e-9, restart="adaptive", ada_first=10, ada_every=20, max_iter=20000)
+    ref = oracle.solve(P, oracle.Options(**kw))
+    announce(f"sym adaptive solve: oracle {ref['info']['iters']} iterations, {ref['info']['restarts']} restarts")
+    xs, ys, info = _solver(inst, sym_pass=1, spec_trials=3, **kw).solve()
+    assert ref["info"]["status"] == "converged" and info["status"] == "ok", (info, ref["info"])
+    k, k_ref = info["iters"], ref["info"]["iters"]
+    assert abs(k - k_ref) <= max(2, 0.01 * k_ref), (k, k_ref)
+    assert info["restarts"] == ref["info"]["restarts"] >= 2, (info["restarts"], ref["info"]["restarts"])
