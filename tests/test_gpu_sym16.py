@@ -159,3 +159,29 @@ def test_sym16_batch_alone_equals_mix():
         np.testing.assert_array_equal(to_np(y), alone[k][1])
         assert (info["iters"], info["trials"], info["q_passes"]) == \
             (alone[k][2]["iters"], alone[k][2]["trials"], alone[k][2]["q_passes"])
+
+
+@pytest.mark.parametrize("storage", ["bfloat16", "float16"])
+def test_sym16_gap_and_adaptive_solve(storage):
+    """A packed 16-bit handle evaluates G_xi with an exact FP64 anchor pass over the stored
+    values, so G_xi at a given point equals the oracle's on the same rounded instance.  An
+    adaptive-restart solve then reaches the oracle-evaluated KKT of 1e-6 with restarts taken."""
+    from paper_2605_29291_amd import Solver
+    inst = qi.round_instance(qi.random_qcqp(300, 8, seed=7500, shift=0.01), storage)
+    P = oracle.Problem(inst)
+    kw = dict(storage=storage, tau_bar=tau_bar_of(inst), gamma0=0.1, spec_trials=2, sym_pass=1)
+    s = Solver(inst, **kw)
+    rng = np.random.default_rng(9)
+    x = rng.uniform(-1, 1, inst.n)
+    y = rng.uniform(0, 0.5, inst.m)
+    announce(f"sym16 G_xi at a point ({storage})")
+    g = s.eval_gap(x, y, xi=0.04)
+    r = oracle.gap(P, x, y, xi=0.04)
+    s.close()
+    assert abs(g["Py"] - r["Py"]) <= 1e-11 * (1 + abs(r["Py"])), (g, r)
+    assert abs(g["Px"] - r["Px"]) <= 1e-9 * (1 + abs(r["Px"])), (g, r)
+    announce(f"sym16 adaptive solve ({storage})")
+    xs, ys, info = Solver(inst, restart="adaptive", ada_first=10, ada_every=20, **kw).solve()
+    assert info["status"] == "ok" and info["restarts"] >= 1 and info["gap_evals"] >= 2, info
+    kk = oracle.kkt(P, to_np(xs), to_np(ys))
+    assert kk["rel_kkt"] <= 1e-6, kk
