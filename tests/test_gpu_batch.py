@@ -178,3 +178,48 @@ def test_mixed_adaptive_and_fixed_restarts_alone_equals_mix():
         np.testing.assert_array_equal(got[k][1], alone[k][1])
         for key in ("iters", "trials", "restarts", "gap_evals"):
             assert got[k][2][key] == alone[k][2][key], (k, key)
+
+
+@pytest.mark.parametrize("storage", ["float64", "bfloat16"])
+def test_requests_with_equality_constraints_alone_equals_mix(storage):
+    """Requests with different numbers of equality constraints (p = 0..3, so y = (v, lambda)
+    has a different split in every slot) return bitwise the same result alone and in one
+    batch, admitted at different times, and reach the oracle-evaluated KKT of 1e-6."""
+    from paper_2605_29291_amd import Batch, Solver
+    specs = [(150, 6, 2), (80, 0, 3), (220, 10, 0), (97, 4, 1)]
+    insts = []
+    for k, (n, m, p) in enumerate(specs):
+        inst = qi.random_qcqp(n, m, seed=5300 + k, shift=0.01, p=p)
+        insts.append(qi.round_instance(inst, storage) if storage != "float64" else inst)
+    alone = []
+    for inst in insts:
+        announce(f"alone {inst.name} p={inst.p}")
+        s = Solver(inst, **_opts(inst, storage))
+        x, y, info = s.solve()
+        alone.append((to_np(x), to_np(y), info))
+        s.close()
+    announce("mix with equality constraints")
+    b = Batch(max_slots=4, storage=storage)
+    solvers = [Solver(inst, **_opts(inst, storage)) for inst in insts]
+    slot_of = {b.admit(solvers[0]): 0, b.admit(solvers[2]): 2}
+    b.step(2)
+    for k in (1, 3):
+        slot_of[b.admit(solvers[k])] = k
+    results = {}
+    guard = 0
+    while len(results) < len(insts):
+        b.step(5)
+        for slot in b.poll():
+            _, x, y, info = b.fetch(slot)
+            results[slot_of[slot]] = (to_np(x), to_np(y), info)
+        guard += 1
+        assert guard < 10000
+    b.close()
+    for k, inst in enumerate(insts):
+        x, y, info = results[k]
+        np.testing.assert_array_equal(x, alone[k][0], err_msg=inst.name)
+        np.testing.assert_array_equal(y, alone[k][1], err_msg=inst.name)
+        assert info["iters"] == alone[k][2]["iters"] and info["trials"] == alone[k][2]["trials"]
+        assert info["status"] == "ok", info
+        kk = oracle.kkt(oracle.Problem(inst), x, y)
+        assert kk["rel_kkt"] <= 1e-6, (inst.name, kk)
