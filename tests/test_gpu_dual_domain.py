@@ -244,3 +244,50 @@ def test_gap_matches_oracle_over_dual_domains(case):
         assert abs(g["Px"] - r["Px"]) <= 1e-9 * (1 + abs(r["Px"])), (g, r)
         assert g["G"] == pytest.approx(g["Py"] + g["Px"], rel=1e-15, abs=1e-300)
     s.close()
+
+
+def test_simplex_and_ball_requests_share_a_batch_bitwise():
+    """A simplex min-max request (identity part, mu = 1), a request whose joint ball binds, one
+    with separable balls and an equality constraint, and a plain QCQP run in one batch and
+    return bitwise the same iterates, multipliers and counters as when each runs alone.  The
+    requests without a binding ball also reach the oracle-evaluated KKT of 1e-6 (a binding ball
+    restricts the dual, so its request runs to its iteration cap)."""
+    from paper_2605_29291_amd import Batch
+    simplex = _simplex_inst(120, 6, seed=62)
+    plain = qi.random_qcqp(110, 5, seed=64, shift=0.01)
+    items = [(simplex, dict(tau_bar=0.5, gamma0=0.1, mu=1.0), True),
+             (qi.random_qcqp(90, 6, seed=61, shift=0.01), dict(ball=0.05, max_iter=300), False),
+             (qi.random_qcqp(70, 4, seed=63, shift=0.01, p=1), dict(ball_v=0.5, ball_lambda=1.0, max_iter=300),
+              False),
+             (plain, {}, True)]
+    kws = [dict(dict(tau_bar=tau_bar_of(inst), gamma0=0.1), **kw) for inst, kw, _ in items]
+    alone = []
+    for (inst, _, _), kw in zip(items, kws):
+        announce(f"alone {inst.name} {kw}")
+        x, y, info = _solver(inst, **kw).solve()
+        alone.append((to_np(x), to_np(y), info))
+    announce("mix of simplex, ball and plain requests")
+    b = Batch(max_slots=4)
+    slot_of = {b.admit(_solver(items[k][0], **kws[k])): k for k in (0, 3)}
+    b.step(2)
+    for k in (1, 2):
+        slot_of[b.admit(_solver(items[k][0], **kws[k]))] = k
+    got = {}
+    guard = 0
+    while len(got) < len(items):
+        b.step(4)
+        for slot in b.poll():
+            _, x, y, info = b.fetch(slot)
+            got[slot_of[slot]] = (to_np(x), to_np(y), info)
+        guard += 1
+        assert guard < 10000
+    b.close()
+    for k, (inst, _, converges) in enumerate(items):
+        np.testing.assert_array_equal(got[k][0], alone[k][0], err_msg=inst.name)
+        np.testing.assert_array_equal(got[k][1], alone[k][1], err_msg=inst.name)
+        for key in ("iters", "trials", "status"):
+            assert got[k][2][key] == alone[k][2][key], (inst.name, key)
+        if converges:
+            assert got[k][2]["status"] == "ok"
+            kk = oracle.kkt(oracle.Problem(inst), got[k][0], got[k][1])
+            assert kk["rel_kkt"] <= 1e-6, (inst.name, kk)
