@@ -30,7 +30,7 @@ def _opts(inst, storage):
     return dict(tau_bar=tau_bar_of(inst), gamma0=0.1, storage=storage, restart_every=30)
 
 
-@pytest.mark.parametrize("storage", ["float64", "bfloat16"])
+@pytest.mark.parametrize("storage", ["float64", "float32", "bfloat16", "float16"])
 def test_alone_equals_mix(storage):
     from paper_2605_29291_amd import Batch, Solver
     insts = _instances(storage)
