@@ -74,12 +74,15 @@ def test_sym16_trial_pass_parity(storage, n, B):
     announce(f"  max |dW| / S = {worst:.2e} (bound {c:.2e})")
 
 
+@pytest.mark.parametrize("variant", ["yx", "xy"])
 @pytest.mark.parametrize("storage", ["bfloat16", "float16"])
-def test_sym16_solve_reaches_the_oracle_kkt(storage):
+def test_sym16_solve_reaches_the_oracle_kkt(storage, variant):
     from paper_2605_29291_amd import Solver
     inst = qi.round_instance(qi.random_qcqp(700, 12, seed=7200, shift=0.01), storage)
-    kw = dict(storage=storage, tau_bar=tau_bar_of(inst), gamma0=0.1, spec_trials=2)
-    announce(f"sym16 solve {storage} n=700")
+    kw = dict(storage=storage, tau_bar=tau_bar_of(inst), gamma0=0.1, spec_trials=2, variant=variant)
+    if variant == "xy":
+        kw.update(c_alpha=0.25, c_beta=0.3, delta=0.4)
+    announce(f"sym16 solve {storage} {variant} n=700")
     s = Solver(inst, sym_pass=1, **kw)
     x, y, info = s.solve()
     s.close()
