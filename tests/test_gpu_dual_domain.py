@@ -172,15 +172,16 @@ def test_kml_minmax_workload_small():
 
 @pytest.mark.parametrize("has_q0", [True, False])
 @pytest.mark.parametrize("storage", ["float64", "bfloat16"])
-def test_q0_shift_operator_parity(has_q0, storage):
+@pytest.mark.parametrize("sym", [0, 1])
+def test_q0_shift_operator_parity(has_q0, storage, sym):
     base = qi.random_qcqp(150, 6, seed=9, shift=0.01)
     Q = base.Q if has_q0 else base.Q[1:]
     inst = qi.Instance(150, 6, 0, Q, base.q, base.c, base.lb, base.ub, None, None, has_q0,
                        "shift", q0_shift=1.7)
     if storage != "float64":
         inst = qi.round_instance(inst, storage)
-    announce(f"q0 shift operator has_q0={has_q0} {storage}")
-    s = _solver(inst, tau_bar=1.0, storage=storage)
+    announce(f"q0 shift operator has_q0={has_q0} {storage} sym_pass={sym}")
+    s = _solver(inst, tau_bar=1.0, storage=storage, sym_pass=sym)
     rng = np.random.default_rng(3)
     x = rng.uniform(-1, 1, 150)
     y = rng.uniform(0, 1, 6)
