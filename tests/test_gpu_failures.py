@@ -10,7 +10,7 @@ bits as alone.  (The kernels only compute with inf/NaN; nothing faults.)
 import numpy as np
 import pytest
 
-from tests.gpu_common import announce, qi, tau_bar_of, to_np
+from tests.gpu_common import announce, oracle, qi, tau_bar_of, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -92,3 +92,29 @@ def test_create_refuses_asymmetric_or_non_finite_matrices():
     near.Q = np.einsum("kij,klj->kil", A, A) / 70
     s = Solver(near, tau_bar=1.0)
     s.close()
+
+
+def test_infeasible_problem_runs_to_its_cap_like_the_oracle():
+    """g_1(x) = 1/2 ||x||^2 + 1 <= 0 has no solution.  The solve stops at max_iter with status
+    not_converged and finite iterates, its multiplier of the impossible constraint grows, the
+    primal residual stays away from zero, and the trajectory equals the oracle's (same trial
+    count, iterates to 1e-10)."""
+    import dataclasses
+    base = qi.random_qcqp(60, 3, seed=81, shift=0.01)
+    Q, q, c = base.Q.copy(), base.q.copy(), base.c.copy()
+    Q[1], q[1], c[1] = np.eye(60), 0.0, 1.0
+    inst = dataclasses.replace(base, Q=Q, q=q, c=c, name="infeasible")
+    tb = 1.0 / np.linalg.norm(Q[0], 2)
+    from paper_2605_29291_amd import Solver
+    announce("infeasible QCQP to its iteration cap")
+    x, y, info = Solver(inst, tau_bar=tb, gamma0=0.1, max_iter=300, tol=1e-6).solve()
+    ref = oracle.solve(oracle.Problem(inst), oracle.Options(tau_bar=tb, gamma0=0.1, max_iter=300, tol=1e-6))
+    assert info["status"] == "not_converged" and ref["info"]["status"] == "not_converged", (info, ref["info"])
+    assert info["iters"] == 300 and info["trials"] == ref["info"]["trials"]
+    xs, ys = to_np(x), to_np(y)
+    assert np.all(np.isfinite(xs)) and np.all(np.isfinite(ys))
+    np.testing.assert_allclose(xs, ref["x"], rtol=1e-10, atol=1e-11)
+    np.testing.assert_allclose(ys, ref["y"][:3], rtol=1e-10, atol=1e-11)
+    assert ys[0] > 10.0
+    kk = oracle.kkt(oracle.Problem(inst), xs, ys)
+    assert kk["rel_pri"] > 0.1 and abs(info["rel_kkt"] - kk["rel_kkt"]) <= 1e-12 * (1 + kk["rel_kkt"])
